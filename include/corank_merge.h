@@ -1,0 +1,202 @@
+/*
+ * corank_merge.h -- C ABI of the MI355X (gfx950) stable-merge library.
+ *
+ * The operations follow C. Siebert and J. L. Traeff, "Perfectly
+ * load-balanced, optimal, stable, parallel merge" (arXiv:1303.4312):
+ *
+ *   stable merge (Sections 1 and 2): C = stable_merge(A, B) for sorted A (m
+ *     elements) and B (n elements); C has m + n elements in nondecreasing
+ *     key order, and among equal keys every element of A comes before every
+ *     element of B, each side keeping its input order.
+ *   co-rank (Section 2, Lemma 1, Algorithm 1): for an output rank i with
+ *     0 <= i <= m + n, the unique (j, k) with j + k = i such that the first
+ *     i outputs of the stable merge are exactly A[0..j) and B[0..k).
+ *   parallel merge (Section 3, Algorithm 2, Proposition 2): the output is
+ *     cut into equal blocks, both ends of every block are co-ranked, and each
+ *     block is merged on its own; every block merges exactly the same number
+ *     of elements (the last may be shorter).
+ *
+ * Conventions shared by every call:
+ *   - Indices are 0-based; sizes are element counts (uint64_t).
+ *   - Keys are uint32, uint64 or float32 (cm_key_type).  float32 keys are
+ *     compared as IEEE floats, so -0.0 and +0.0 are equal keys (the tie rule
+ *     orders them and their bits are copied unchanged); NaN keys are not
+ *     allowed.  Payloads, where taken, are uint32 and move with their key.
+ *   - Inputs must already be sorted (nondecreasing).  This is a precondition
+ *     the merge calls do not check; cm_check_sorted checks it on request.
+ *   - "device" pointers are HIP device memory of the current device; "host"
+ *     pointers are ordinary host memory.  The caller owns every buffer,
+ *     including the workspace; the library keeps no pointer after a call
+ *     returns and allocates nothing on the merge path.
+ *   - Calls that take a stream enqueue work on it and return at once.
+ *     Argument errors are found before anything is enqueued and leave the
+ *     stream untouched.  A failed kernel launch returns CM_EHIP.
+ *   - Output arrays must not overlap input arrays (CM_EALIAS).  A and B may
+ *     overlap each other (both are only read).  A null pointer with a
+ *     nonzero length is CM_EINVAL.  Zero lengths are valid.
+ */
+#ifndef CORANK_MERGE_H
+#define CORANK_MERGE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes returned by every int-valued call. */
+enum cm_status {
+    CM_OK = 0,
+    CM_EINVAL = -1,    /* bad argument: null pointer, bad size, bad handle */
+    CM_ERANGE = -2,    /* rank outside [0, m + n] */
+    CM_EDTYPE = -3,    /* unknown key type */
+    CM_EALIAS = -4,    /* an output overlaps an input */
+    CM_ENOSPC = -5,    /* workspace smaller than the *_workspace_size result */
+    CM_EHIP = -6,      /* a HIP runtime call or kernel launch failed */
+    CM_EUNSORTED = -7, /* cm_check_sorted: the array is not sorted */
+    CM_ECONFIG = -8    /* unknown tile configuration */
+};
+
+/* Key types. */
+enum cm_key_type { CM_KEY_U32 = 0, CM_KEY_U64 = 1, CM_KEY_F32 = 2 };
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *cm_status_string(int status);
+
+/* Library ABI version (increases when a signature changes). */
+int cm_version(void);
+
+/*
+ * Co-rank on host arrays: Lemma 1 / Algorithm 1 (Section 2), run on the CPU.
+ * A (m keys) and B (n keys) are host arrays of key type `key_type`.
+ * On CM_OK, *j and *k hold the co-ranks of rank i (j + k = i).
+ * Errors: CM_ERANGE if i > m + n; CM_EINVAL for a null pointer with a
+ * nonzero length or null j/k; CM_EDTYPE for an unknown key type.
+ */
+int cm_co_rank_host(int key_type, uint64_t i,
+                    const void *A, uint64_t m, const void *B, uint64_t n,
+                    uint64_t *j, uint64_t *k);
+
+/*
+ * Co-rank of q ranks on device arrays: Algorithm 1 (Section 2), one GPU
+ * thread per rank.  ranks[r] (device, q entries) are output ranks; the call
+ * writes j_out[r] (device, q entries) with the A co-rank of ranks[r]; the B
+ * co-rank is ranks[r] - j_out[r].  A rank above m + n cannot be reported
+ * synchronously (the ranks live on the device): its j_out entry is set to
+ * UINT64_MAX.
+ * Errors (synchronous): CM_EINVAL, CM_EDTYPE, CM_EALIAS (j_out overlapping
+ * ranks, A or B), CM_EHIP.
+ */
+int cm_co_rank(int key_type, const uint64_t *ranks, uint64_t q,
+               const void *A, uint64_t m, const void *B, uint64_t n,
+               uint64_t *j_out, hipStream_t stream);
+
+/*
+ * Workspace bytes a single merge of m and n elements needs under the tile
+ * configuration currently selected for (key_type, with_payload): one
+ * uint64 co-rank per block boundary (Algorithm 2), rounded up to 256 bytes.
+ * Returns 0 for m + n = 0 or an unknown key type.
+ */
+size_t cm_merge_workspace_size(int key_type, int with_payload, uint64_t m, uint64_t n);
+
+/*
+ * Stable merge of keys (Sections 1-3).  A: m keys, B: n keys, C: m + n keys,
+ * all device arrays of key type `key_type`.  workspace: device memory of at
+ * least cm_merge_workspace_size(key_type, 0, m, n) bytes (may be NULL when
+ * that size is 0); its contents are scratch.
+ * Errors: CM_EINVAL, CM_EDTYPE, CM_EALIAS, CM_ENOSPC, CM_EHIP.
+ */
+int cm_stable_merge(int key_type,
+                    const void *A, uint64_t m, const void *B, uint64_t n,
+                    void *C, void *workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/*
+ * Stable merge of key + payload pairs (Sections 1-3).  Like cm_stable_merge;
+ * A_val (m), B_val (n) and C_val (m + n) are uint32 device arrays and every
+ * payload ends up beside its key.  Keys and payloads are separate arrays
+ * (structure of arrays).  workspace: cm_merge_workspace_size(key_type, 1,
+ * m, n) bytes.
+ * Errors: CM_EINVAL, CM_EDTYPE, CM_EALIAS, CM_ENOSPC, CM_EHIP.
+ */
+int cm_stable_merge_pairs(int key_type,
+                          const void *A, const uint32_t *A_val, uint64_t m,
+                          const void *B, const uint32_t *B_val, uint64_t n,
+                          void *C, uint32_t *C_val,
+                          void *workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/*
+ * Workspace bytes for a segmented merge of num_seg segments with total_a
+ * and total_b elements: per block boundary one uint64 co-rank and one
+ * uint32 segment index, rounded up to 256 bytes.
+ */
+size_t cm_segmented_workspace_size(int key_type, int with_payload,
+                                   uint64_t total_a, uint64_t total_b,
+                                   uint64_t num_seg);
+
+/*
+ * Batch of num_seg independent stable merges in one pass (each segment is
+ * one instance of the problem of Section 2; the batch is partitioned as one
+ * merge under the order (segment, key), so blocks of Algorithm 2 run across
+ * segment ends and every block still merges the same number of elements).
+ *
+ * Segment s merges A[a_off[s] .. a_off[s+1]) with B[b_off[s] .. b_off[s+1])
+ * into C[a_off[s] + b_off[s] .. a_off[s+1] + b_off[s+1]).
+ *   A, B, C: device key arrays (total_a, total_b, total_a + total_b keys).
+ *   A_val, B_val, C_val: uint32 device payload arrays, or all three NULL.
+ *   a_off, b_off: device uint64 arrays of num_seg + 1 nondecreasing entries
+ *     with a_off[0] = b_off[0] = 0, a_off[num_seg] = total_a and
+ *     b_off[num_seg] = total_b (the host passes total_a and total_b because
+ *     the offsets are on the device; a mismatch gives undefined output but
+ *     never an access outside the arrays).  Empty sides are allowed.
+ *   workspace: cm_segmented_workspace_size(...) bytes of device memory.
+ * Errors: CM_EINVAL (also num_seg = 0 with nonzero totals, or num_seg at or
+ * above 2**32), CM_EDTYPE, CM_EALIAS, CM_ENOSPC, CM_EHIP.
+ */
+int cm_stable_merge_segmented(int key_type,
+                              const void *A, const uint32_t *A_val, const uint64_t *a_off,
+                              uint64_t total_a,
+                              const void *B, const uint32_t *B_val, const uint64_t *b_off,
+                              uint64_t total_b,
+                              uint64_t num_seg,
+                              void *C, uint32_t *C_val,
+                              void *workspace, size_t workspace_bytes,
+                              hipStream_t stream);
+
+/*
+ * Check on the device that a key array is sorted (the precondition of
+ * Section 2).  flag: device uint32 that the call first sets to 0 and that
+ * ends up nonzero if some X[x-1] > X[x].  Read it after the stream is done.
+ * Errors: CM_EINVAL, CM_EDTYPE, CM_EHIP.
+ */
+int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
+                    hipStream_t stream);
+
+/*
+ * Tile configurations.  A configuration fixes the threads per workgroup (NT)
+ * and the outputs per thread (E); one block of Algorithm 2 is NT * E
+ * outputs.  Every configuration gives bit-identical results; they differ
+ * only in speed.  cm_config_count() configurations are numbered from 0.
+ *   cm_config_info: NT and E of configuration id (CM_ECONFIG if unknown).
+ *   cm_set_config / cm_get_config: the configuration used by the merge calls
+ *     for (key_type, with_payload) in this process (not thread-safe against
+ *     concurrent merges; set it before launching).
+ *   cm_set_search: co-rank search used by the kernels: 0 = Algorithm 1
+ *     (default), 1 = plain bisection over the diagonal.  Both return the
+ *     unique pair of Lemma 1.
+ */
+int cm_config_count(void);
+int cm_config_info(int config_id, int *threads, int *items_per_thread);
+int cm_set_config(int key_type, int with_payload, int config_id);
+int cm_get_config(int key_type, int with_payload);
+int cm_set_search(int search_mode);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CORANK_MERGE_H */

@@ -1,0 +1,144 @@
+// Device-side building blocks of the co-rank merge (gfx950, wave64).
+//
+// co_rank_alg1 is Algorithm 1 of Section 2 (Siebert and Traeff,
+// arXiv:1303.4312); co_rank_bisect finds the same pair by plain bisection on
+// the first Lemma 1 condition.  Both return the unique A co-rank j of rank i
+// (Lemma 1); the B co-rank is i - j.  The block merge follows Algorithm 2 of
+// Section 3 at two levels: workgroups take equal output blocks whose ends are
+// co-ranked in global memory, and threads take equal runs of E outputs whose
+// starts are co-ranked inside the block's windows held in LDS.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cm {
+
+enum SearchMode : int { kSearchAlg1 = 0, kSearchBisect = 1 };
+
+// Algorithm 1 (Section 2).  State j + k = i with lower bounds j_low, k_low.
+// The four keys a round may look at are fetched together, each only when its
+// index guard holds (the paper's conditional and), so positions -1, m and n
+// are never read.  Reading all four at once costs one memory round trip per
+// round: A[j-1], A[j] and B[k-1], B[k] are neighbours.
+// k_low is left unset by the paper; it is assigned in the first round before
+// any read (only the first condition can fail there), and starts at 0 here.
+// On sorted input a violated condition always has a nonzero step (the
+// co-rank lies strictly inside the interval being halved).  The zero-step
+// exits only matter for unsorted input, outside the paper's precondition:
+// there they keep the loop finite (the result is then meaningless but lies
+// in [max(0, i - n), min(i, m)]).
+template <typename K, typename I, typename RA, typename RB>
+__device__ __forceinline__ I co_rank_alg1(I i, RA A, I m, RB B, I n) {
+  I j = i < m ? i : m;
+  I k = i - j;
+  I j_low = i > n ? i - n : I(0);
+  I k_low = 0;
+  while (true) {
+    const bool g1 = j > 0 && k < n;  // guards of the first condition
+    const bool g2 = k > 0 && j < m;  // guards of the second condition
+    K a_prev{}, b_here{}, b_prev{}, a_here{};
+    if (g1) {
+      a_prev = A(j - 1);
+      b_here = B(k);
+    }
+    if (g2) {
+      b_prev = B(k - 1);
+      a_here = A(j);
+    }
+    if (g1 && a_prev > b_here) {  // first condition violated: j too large
+      const I d = (j - j_low + 1) >> 1;
+      if (d == 0) return j;
+      k_low = k;
+      j -= d;
+      k += d;
+    } else if (g2 && b_prev >= a_here) {  // second violated: k too large
+      const I d = (k - k_low + 1) >> 1;
+      if (d == 0) return j;
+      j_low = j;
+      j += d;
+      k -= d;
+    } else {
+      return j;
+    }
+  }
+}
+
+// The same pair by bisection: j is the largest value in
+// [max(0, i - n), min(i, m)] that is the lower end or satisfies
+// A[j-1] <= B[i-j]; that predicate is true then false along the diagonal.
+template <typename K, typename I, typename RA, typename RB>
+__device__ __forceinline__ I co_rank_bisect(I i, RA A, I m, RB B, I n) {
+  I lo = i > n ? i - n : I(0);
+  I hi = i < m ? i : m;
+  while (lo < hi) {
+    const I mid = lo + ((hi - lo + 1) >> 1);  // lo < mid <= hi
+    if (A(mid - 1) <= B(i - mid))
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename K, typename I, typename RA, typename RB>
+__device__ __forceinline__ I co_rank(int mode, I i, RA A, I m, RB B, I n) {
+  return mode == kSearchBisect ? co_rank_bisect<K>(i, A, m, B, n)
+                               : co_rank_alg1<K>(i, A, m, B, n);
+}
+
+// Length of a block's A window from the co-ranks of its two ends.  With
+// sorted input j0 <= j1 <= j0 + len always holds; the clamp only keeps every
+// access in bounds when the precondition is broken.
+__device__ __forceinline__ int window_a_len(uint64_t j0, uint64_t j1, int len) {
+  return j1 < j0 ? 0 : (int)(j1 - j0 < (uint64_t)len ? j1 - j0 : (uint64_t)len);
+}
+
+// Streams the two windows of a block into LDS: s_key[0, a_len) holds
+// A[ja, ja + a_len) and s_key[a_len, len) holds B[kb, kb + len - a_len);
+// payloads likewise.  Every thread issues all of its E loads before its
+// first LDS write so that E (or 2E with payloads) loads are in flight.
+// Consecutive lanes read consecutive addresses (one break at a_len).
+template <typename K, bool VAL, int NT, int E>
+__device__ __forceinline__ void load_windows(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+                                             uint64_t ja, const K* __restrict__ B,
+                                             const uint32_t* __restrict__ Bv, uint64_t kb, int a_len,
+                                             int len, K* s_key, uint32_t* s_val) {
+  K kr[E];
+  uint32_t vr[E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int x = (int)threadIdx.x + r * NT;
+    if (x < len) {
+      const bool from_a = x < a_len;
+      const uint64_t g = from_a ? ja + (uint64_t)x : kb + (uint64_t)(x - a_len);
+      kr[r] = from_a ? A[g] : B[g];
+      if constexpr (VAL) vr[r] = from_a ? Av[g] : Bv[g];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int x = (int)threadIdx.x + r * NT;
+    if (x < len) {
+      s_key[x] = kr[r];
+      if constexpr (VAL) s_val[x] = vr[r];
+    }
+  }
+}
+
+// Writes the block's LDS contents (already in output order) to C[i0, i0 + len)
+// with lane-contiguous stores.
+template <typename K, bool VAL, int NT, int E>
+__device__ __forceinline__ void store_block(K* __restrict__ C, uint32_t* __restrict__ Cv, uint64_t i0,
+                                            int len, const K* s_key, const uint32_t* s_val) {
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int x = (int)threadIdx.x + r * NT;
+    if (x < len) {
+      __builtin_nontemporal_store(s_key[x], C + i0 + x);
+      if constexpr (VAL) __builtin_nontemporal_store(s_val[x], Cv + i0 + x);
+    }
+  }
+}
+
+}  // namespace cm

@@ -1,0 +1,165 @@
+"""C ABI checks that need no GPU.
+
+- the shared library loads and exports every function include/*.h declares;
+- cm_co_rank_host (the library's own CPU Algorithm 1) equals the oracle;
+- argument errors are reported synchronously, before anything would be
+  launched (these calls pass made-up addresses that are never touched).
+"""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1303_4312_amd as cm
+from paper_1303_4312_amd import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+OK, EINVAL, ERANGE, EDTYPE, EALIAS, ENOSPC, ECONFIG = 0, -1, -2, -3, -4, -5, -8
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names.update(re.findall(r"\b(cm_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("cm_co_rank", "cm_co_rank_host", "cm_stable_merge", "cm_stable_merge_pairs",
+                     "cm_stable_merge_segmented"):
+        assert required in names
+
+
+def test_library_exports_every_declared_function():
+    lib = cm.load()
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(declared_functions()) == set(cm.EXPORTS)
+
+
+def test_status_strings_and_version():
+    assert cm.load().cm_version() >= 1
+    assert cm.status_string(OK) == "ok"
+    assert cm.status_string(ENOSPC) == "workspace too small"
+
+
+def test_host_co_rank_figure(figure):
+    A = np.array(figure["A"]["keys"], dtype=np.uint32)
+    B = np.array(figure["B"]["keys"], dtype=np.uint32)
+    assert cm.co_rank_host(22, A, B) == (12, 10)
+    for i in range(A.size + B.size + 1):
+        assert cm.co_rank_host(i, A, B) == oracle.co_rank_brute(i, A, B)
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64, np.float32])
+def test_host_co_rank_random(dtype):
+    rng = np.random.default_rng(5)
+    for m, n, hi in ((0, 0, 3), (0, 7, 3), (9, 0, 3), (500, 1500, 20), (4096, 4000, 2)):
+        A = np.sort(rng.integers(0, hi, m)).astype(dtype)
+        B = np.sort(rng.integers(0, hi, n)).astype(dtype)
+        for i in sorted(set(rng.integers(0, m + n + 1, 40).tolist()) | {0, m + n}):
+            assert cm.co_rank_host(i, A, B) == oracle.co_rank_brute(i, A, B)
+
+
+def test_host_co_rank_errors():
+    A = np.zeros(3, dtype=np.uint32)
+    with pytest.raises(cm.CMError) as e:
+        cm.co_rank_host(7, A, A)
+    assert e.value.status == ERANGE
+    lib = cm.load()
+    j, k = ctypes.c_uint64(), ctypes.c_uint64()
+    assert lib.cm_co_rank_host(9, 0, None, 0, None, 0, ctypes.byref(j), ctypes.byref(k)) == EDTYPE
+    assert lib.cm_co_rank_host(0, 0, None, 4, None, 0, ctypes.byref(j), ctypes.byref(k)) == EINVAL
+
+
+def test_merge_argument_errors_are_synchronous():
+    lib = cm.load()
+    P = ctypes.c_void_p
+    A, B, C = P(0x10000000), P(0x20000000), P(0x30000000)
+    ws = P(0x40000000)
+    big = 1 << 20
+    # unknown key type
+    assert lib.cm_stable_merge(9, A, 4, B, 4, C, ws, big, None) == EDTYPE
+    # null with nonzero length
+    assert lib.cm_stable_merge(0, None, 4, B, 4, C, ws, big, None) == EINVAL
+    assert lib.cm_stable_merge_pairs(0, A, None, 4, B, P(0x50000000), 4, C, P(0x60000000),
+                                     ws, big, None) == EINVAL
+    # output overlapping an input
+    assert lib.cm_stable_merge(0, A, 4, B, 4, P(0x10000000 + 8), ws, big, None) == EALIAS
+    assert lib.cm_stable_merge_pairs(0, A, P(0x50000000), 4, B, P(0x60000000), 4, C,
+                                     P(0x50000000), ws, big, None) == EALIAS
+    # workspace too small
+    need = lib.cm_merge_workspace_size(0, 0, 1 << 20, 1 << 20)
+    assert need > 0
+    assert lib.cm_stable_merge(0, A, 1 << 20, B, 1 << 20, C, ws, need - 1, None) == ENOSPC
+    assert lib.cm_stable_merge(0, A, 1 << 20, B, 1 << 20, C, None, 0, None) == ENOSPC
+    # empty merge is a no-op
+    assert lib.cm_stable_merge(0, None, 0, None, 0, None, None, 0, None) == OK
+    # segmented
+    assert lib.cm_stable_merge_segmented(0, None, None, None, 0, None, None, None, 0, 0, None,
+                                         None, None, 0, None) == OK
+    assert lib.cm_stable_merge_segmented(0, A, None, None, 4, B, None, None, 4, 0, C, None, ws,
+                                         big, None) == EINVAL
+    assert lib.cm_stable_merge_segmented(0, A, None, P(0x70000000), 4, B, None, P(0x71000000), 4,
+                                         1 << 32, C, None, ws, big, None) == EINVAL
+    # co_rank on device arrays
+    assert lib.cm_co_rank(0, None, 3, A, 4, B, 4, P(0x80000000), None) == EINVAL
+    assert lib.cm_co_rank(0, P(0x80000000), 4, A, 4, B, 4, P(0x80000000 + 8), None) == EALIAS
+
+
+def test_config_table():
+    n = cm.config_count()
+    assert n >= 4
+    tiles = set()
+    for c in range(n):
+        nt, e = cm.config_info(c)
+        assert nt % 64 == 0 and e % 2 == 1
+        tiles.add(nt * e)
+    assert len(tiles) == n
+    with pytest.raises(cm.CMError):
+        cm.config_info(n)
+    old = cm.get_config("uint32", True)
+    cm.set_config("uint32", True, n - 1)
+    assert cm.get_config("uint32", True) == n - 1
+    cm.set_config("uint32", True, old)
+    assert cm.load().cm_set_config(0, 1, n) == ECONFIG
+    assert cm.load().cm_set_search(2) == EINVAL
+
+
+def test_workspace_sizes():
+    lib = cm.load()
+    for c in range(cm.config_count()):
+        cm.set_config("uint32", False, c)
+        nt, e = cm.config_info(c)
+        T = nt * e
+        for N in (1, T - 1, T, T + 1, 10 * T + 3):
+            tiles = -(-N // T)
+            assert lib.cm_merge_workspace_size(0, 0, N, 0) >= 8 * (tiles + 1)
+            assert lib.cm_merge_workspace_size(0, 0, N, 0) % 256 == 0
+    cm.set_config("uint32", False, 2)
+    assert lib.cm_merge_workspace_size(0, 0, 0, 0) == 0
+
+
+def test_binding_refuses_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(cm, "_lib", None)
+    monkeypatch.setattr(cm, "library_path", str(tmp_path / "missing.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        cm.load()
+
+
+def test_workloads_shapes():
+    d = workloads.zipf(m=1 << 16, n=1 << 14)
+    assert d["A"].dtype == np.uint32 and d["A"].size == 1 << 16
+    assert np.all(np.diff(d["A"].astype(np.int64)) >= 0)
+    assert len(np.unique(np.concatenate([d["A"], d["B"]]))) <= 1024
+    s = workloads.segmented(num_seg=64, max_side=1 << 10)
+    assert s["a_off"][-1] == s["A"].size and s["b_off"][-1] == s["B"].size
+    assert np.all(np.diff(s["a_off"].astype(np.int64)) >= 1)
