@@ -1,0 +1,302 @@
+#!/usr/bin/env python3
+"""Throughput of the co-rank stable merge on one MI355X.
+
+A step is one pass of the whole path over one batch of synthetic input: the
+block-boundary co-rank pass and the block-merge kernel of one stable merge
+(cm_stable_merge_pairs).  The default workload is the single uneven merge:
+m = 2**28, n = 2**26, uint32 keys drawn from 1024 distinct values with
+Zipf(1.1) frequencies, each array sorted, uint32 origin payloads.  Inputs are
+resident in HBM before the timed region starts.
+
+Output: one JSON line with merged keys/s (whole job), the roofline of the
+block-merge kernel (algorithmic bytes = read m + n and write m + n elements,
+over its mean duration from HIP events recorded by the library on the
+stream it launches on), the CPU oracle timed on the host beside it
+(bit-exactness of the GPU output is checked in that leg), and the batched
+segmented merge against one launch pair per merge on the batch workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "merged keys/s & % of HBM peak; batched vs per-merge launches, bit-exact"
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_4312_amd", "csrc", f)
+                  for f in ("kernels.hpp", "merge_device.hpp", "launch.hip")]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_merge_blocks_zipf_u32_pairs_counters.md")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def workload_inputs(name):
+    from paper_1303_4312_amd import workloads as w
+    if name == "zipf":
+        d = w.zipf()
+        desc = ("single uneven merge m=2^28 n=2^26, uint32 keys Zipf(1.1) over 1024 values, "
+                "uint32 payloads")
+    elif name == "dup16":
+        d = w.dup16()
+        desc = "single merge m=n=2^20, uint32 keys uniform in [0,2^16), uint32 payloads"
+    elif name == "u64":
+        d = w.u64()
+        desc = "single merge m=n=2^27, uint64 keys uniform, uint32 payloads"
+    elif name == "f32":
+        d = w.f32()
+        desc = "single merge m=n=2^27, float32 keys N(0,1), uint32 payloads"
+    elif name in ("a_below_b", "interleaved", "all_equal"):
+        d = w.structured(name)
+        desc = f"single merge m=n=2^27, uint32 keys, structured case {name}, uint32 payloads"
+    else:
+        raise SystemExit(f"unknown workload {name}")
+    return d, desc
+
+
+def read_traffic(alg_bytes):
+    """Measured HBM bytes per launch of the block-merge kernel from the
+    committed rocprofv3 counter summary, if it was taken on this kernel
+    source; else None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    text = open(COUNTERS_FILE).read()
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("traffic_bytes_per_launch")
+
+
+def cpu_baseline_leg(d, C_gpu, Cv_gpu, seconds):
+    """The oracle (plain single-threaded C merge) on the same host arrays,
+    repeated until `seconds` of CPU time have passed (at least once); then
+    the GPU output is compared with the oracle's byte for byte."""
+    import numpy as np
+    import oracle
+    reps, t_total, out = 0, 0.0, None
+    while reps == 0 or t_total < seconds:
+        t0 = time.perf_counter()
+        out = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        t_total += time.perf_counter() - t0
+        reps += 1
+    n = d["A"].size + d["B"].size
+    exact = bool(np.array_equal(out[0].view(np.uint8), C_gpu.view(np.uint8)) and
+                 np.array_equal(out[1], Cv_gpu))
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {
+        "value": n * reps / t_total,
+        "unit": "keys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"the full workload arrays ({n} outputs), merged {reps}x by the "
+                   f"single-threaded oracle in {t_total:.1f} s on {cpu}"),
+    }, exact
+
+
+def batched_leg(steps, warmup):
+    """65536 independent merges, sides log-uniform in [1, 2^16]: one batched
+    call (co-rank pass + one block-merge launch) against one single-merge call
+    per segment; outputs compared byte for byte."""
+    import numpy as np
+    import torch
+    import paper_1303_4312_amd as cm
+    from paper_1303_4312_amd import workloads as w
+
+    log("batched: generating 65536 segments")
+    d = w.segmented()
+    dev = torch.device("cuda:0")
+    A, Av, B, Bv = (torch.from_numpy(d[k]).to(dev) for k in ("A", "Av", "B", "Bv"))
+    a_off = torch.from_numpy(d["a_off"]).to(dev)
+    b_off = torch.from_numpy(d["b_off"]).to(dev)
+    n = A.numel() + B.numel()
+    C = torch.empty(n, dtype=A.dtype, device=dev)
+    Cv = torch.empty(n, dtype=torch.uint32, device=dev)
+    ws = torch.empty(cm.segmented_workspace_size("uint32", True, A.numel(), B.numel(),
+                                                 a_off.numel() - 1), dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        cm.stable_merge_segmented(A, a_off, B, b_off, Av, Bv, C, Cv, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        cm.stable_merge_segmented(A, a_off, B, b_off, Av, Bv, C, Cv, workspace=ws)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / steps
+    log(f"batched: {t_batch * 1e3:.3f} ms per batch; running per-merge launches")
+    C2 = torch.empty_like(C)
+    Cv2 = torch.empty_like(Cv)
+    cm.stable_merge_segmented_each(A, d["a_off"], B, d["b_off"], Av, Bv, C2, Cv2)
+    torch.cuda.synchronize()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cm.stable_merge_segmented_each(A, d["a_off"], B, d["b_off"], Av, Bv, C2, Cv2)
+    torch.cuda.synchronize()
+    t_each = (time.perf_counter() - t0) / reps
+    same = bool(np.array_equal(C.cpu().numpy(), C2.cpu().numpy()) and
+                np.array_equal(Cv.cpu().numpy(), Cv2.cpu().numpy()))
+    return {
+        "workload": ("65536 merges, sides log-uniform in [1,2^16], uint32 keys uniform in "
+                     "[0,2^20) sorted per segment, uint32 payloads"),
+        "outputs": n,
+        "batched_keys_per_s": n / t_batch,
+        "batched_ms": t_batch * 1e3,
+        "per_merge_keys_per_s": n / t_each,
+        "per_merge_ms": t_each * 1e3,
+        "per_merge_launches": 2 * (a_off.numel() - 1),
+        "speedup": t_each / t_batch,
+        "identical_output": same,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="zipf")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one cm_copy of 1 GiB (for counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU runs are not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1303_4312_amd as cm
+
+    log(f"generating workload {args.workload}")
+    d, desc = workload_inputs(args.workload)
+    dev = torch.device("cuda:0")
+    A, Av, B, Bv = (torch.from_numpy(d[k]).to(dev) for k in ("A", "Av", "B", "Bv"))
+    m, n = A.numel(), B.numel()
+    N = m + n
+    key_dtype = str(A.dtype).replace("torch.", "")
+    key_bytes = A.element_size()
+    C = torch.empty(N, dtype=A.dtype, device=dev)
+    Cv = torch.empty(N, dtype=torch.uint32, device=dev)
+    ws = torch.empty(max(cm.merge_workspace_size(key_dtype, True, m, n), 1), dtype=torch.uint8,
+                     device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.uint32, device=dev)
+        dst = torch.empty_like(src)
+        cm.copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
+
+    log(f"warmup {args.warmup}")
+    for _ in range(args.warmup):
+        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+
+    log(f"timing {args.steps} steps")
+    cm.timing_start(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    calls, co_rank_ms, merge_ms = cm.timing_stop()
+    assert calls == args.steps
+    value = N * args.steps / elapsed
+    log(f"{elapsed / args.steps * 1e3:.3f} ms/step; merge kernel {merge_ms:.3f} ms, "
+        f"co-rank pass {co_rank_ms:.3f} ms")
+
+    per_elem = 2 * (key_bytes + 4)           # read + write one key and one payload
+    alg_bytes = N * per_elem
+    achieved = alg_bytes / (merge_ms * 1e-3) / 1e9
+    traffic = read_traffic(alg_bytes)
+    cfg, search, partition = cm.tuning_get(cm.OP_MERGE, key_dtype, True, N)
+    nt, e = cm.config_info(cfg)
+    result = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"uint32": "u32", "uint64": "u64", "float32": "f32"}[key_dtype],
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "m": m, "n": n, "key": key_dtype, "payload": "uint32",
+            "block": {"threads": nt, "items_per_thread": e},
+            "search": ["algorithm1", "bisection"][search],
+            "boundary_pass": ["one_level", "two_level"][partition],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_merge_blocks",
+            "kernel_ms": merge_ms,
+            "co_rank_pass_ms": co_rank_ms,
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+        "step_hbm_frac": (alg_bytes / (elapsed / args.steps)) / 1e9 / HBM_PEAK_GBS,
+    }
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on the host")
+        C_h = C.cpu().numpy()
+        Cv_h = Cv.cpu().numpy()
+        cpu, exact = cpu_baseline_leg(d, C_h, Cv_h, args.cpu_seconds)
+        result["cpu_baseline"] = cpu
+        result["bit_exact"] = exact
+    else:
+        result["cpu_baseline"] = None
+        result["bit_exact"] = None
+
+    if not args.no_batched:
+        del A, Av, B, Bv, C, Cv, ws
+        torch.cuda.empty_cache()
+        result["batched"] = batched_leg(steps=max(3, min(args.steps, 20)), warmup=2)
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

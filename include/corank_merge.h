@@ -95,9 +95,11 @@ int cm_co_rank(int key_type, const uint64_t *ranks, uint64_t q,
                uint64_t *j_out, hipStream_t stream);
 
 /*
- * Workspace bytes a single merge of m and n elements needs under the tile
- * configuration currently selected for (key_type, with_payload): one
- * uint64 co-rank per block boundary (Algorithm 2), rounded up to 256 bytes.
+ * Workspace bytes a single merge of m and n elements needs: one uint64
+ * co-rank per block boundary (Algorithm 2) and one per coarse boundary of
+ * the two-level boundary pass, sized for the smallest block of any tile
+ * configuration (so one workspace serves every configuration), each array
+ * rounded up to 256 bytes.
  * Returns 0 for m + n = 0 or an unknown key type.
  */
 size_t cm_merge_workspace_size(int key_type, int with_payload, uint64_t m, uint64_t n);
@@ -131,8 +133,9 @@ int cm_stable_merge_pairs(int key_type,
 
 /*
  * Workspace bytes for a segmented merge of num_seg segments with total_a
- * and total_b elements: per block boundary one uint64 co-rank and one
- * uint32 segment index, rounded up to 256 bytes.
+ * and total_b elements: a status word, and per block boundary one uint64
+ * co-rank and one uint32 segment index (sized for the smallest block of any
+ * configuration), each part rounded up to 256 bytes.
  */
 size_t cm_segmented_workspace_size(int key_type, int with_payload,
                                    uint64_t total_a, uint64_t total_b,
@@ -151,8 +154,10 @@ size_t cm_segmented_workspace_size(int key_type, int with_payload,
  *   a_off, b_off: device uint64 arrays of num_seg + 1 nondecreasing entries
  *     with a_off[0] = b_off[0] = 0, a_off[num_seg] = total_a and
  *     b_off[num_seg] = total_b (the host passes total_a and total_b because
- *     the offsets are on the device; a mismatch gives undefined output but
- *     never an access outside the arrays).  Empty sides are allowed.
+ *     the offsets are on the device).  Empty sides are allowed.  The offsets
+ *     are checked on the device before any merging: if they break these
+ *     rules, C is left unwritten and the first uint32 of the workspace is
+ *     nonzero after the stream completes (it is zero after a good call).
  *   workspace: cm_segmented_workspace_size(...) bytes of device memory.
  * Errors: CM_EINVAL (also num_seg = 0 with nonzero totals, or num_seg at or
  * above 2**32), CM_EDTYPE, CM_EALIAS, CM_ENOSPC, CM_EHIP.
@@ -185,15 +190,152 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *   cm_set_config / cm_get_config: the configuration used by the merge calls
  *     for (key_type, with_payload) in this process (not thread-safe against
  *     concurrent merges; set it before launching).
- *   cm_set_search: co-rank search used by the kernels: 0 = Algorithm 1
- *     (default), 1 = plain bisection over the diagonal.  Both return the
- *     unique pair of Lemma 1.
+ *   cm_set_search: co-rank search of the per-thread searches inside a
+ *     block and of the one-level boundary pass: 0 = Algorithm 1, 1 = plain
+ *     bisection over the diagonal (default).  Both return the unique pair
+ *     of Lemma 1.
+ *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
+ *     0 = one GPU thread per boundary over the whole diagonal; 1 = two
+ *     levels (default): every 64th boundary by a whole wave with a 64-ary
+ *     search, then the others by bisection between their two coarse
+ *     neighbours.  Both give the same co-ranks.
+ *   The cm_get_* calls return the current setting.
+ *   (Settings are process-wide and not thread-safe against concurrent
+ *   merges; set them before launching.)
  */
 int cm_config_count(void);
 int cm_config_info(int config_id, int *threads, int *items_per_thread);
 int cm_set_config(int key_type, int with_payload, int config_id);
 int cm_get_config(int key_type, int with_payload);
 int cm_set_search(int search_mode);
+int cm_get_search(void);
+int cm_set_partition(int partition_mode);
+int cm_get_partition(void);
+
+/*
+ * Autotuner (self-written; not part of the method).  Times every tile
+ * configuration x co-rank search x boundary pass on the caller's buffers
+ * (each candidate: one warm call, then `reps` calls between two HIP events
+ * on `stream`; the call synchronises), stores the fastest in the tuning
+ * table under (operation, key type, payload, size class of m + n) and, if
+ * best is not NULL, writes best[0..2] = {config, search, partition}.  Every
+ * candidate produces the same output, so C (and C_val) hold the merge
+ * afterwards.  Arguments are those of cm_stable_merge_pairs (payload
+ * pointers all NULL for keys only) / cm_stable_merge_segmented.  The
+ * segmented tuner tries only the one-level boundary pass (the batch's
+ * boundary pass has no two-level form).
+ * Errors: those of the merge calls; CM_EINVAL for reps outside [1, 10000]
+ * or an empty merge.
+ */
+int cm_autotune_merge(int key_type,
+                      const void *A, const uint32_t *A_val, uint64_t m,
+                      const void *B, const uint32_t *B_val, uint64_t n,
+                      void *C, uint32_t *C_val,
+                      void *workspace, size_t workspace_bytes,
+                      int reps, hipStream_t stream, int *best);
+int cm_autotune_segmented(int key_type,
+                          const void *A, const uint32_t *A_val, const uint64_t *a_off,
+                          uint64_t total_a,
+                          const void *B, const uint32_t *B_val, const uint64_t *b_off,
+                          uint64_t total_b, uint64_t num_seg,
+                          void *C, uint32_t *C_val,
+                          void *workspace, size_t workspace_bytes,
+                          int reps, hipStream_t stream, int *best);
+
+/*
+ * Tuning table.  Entries map (op, key_type, with_payload, size class) to
+ * {config, search, partition}; op 0 = single merge, 1 = segmented batch;
+ * the size class of a merge of N outputs is the bit length of N (0..64).
+ * A merge call uses the entry of its size class when there is one, else
+ * the settings of cm_set_config / cm_set_search / cm_set_partition.
+ *   cm_tuning_set: add or replace one entry.
+ *   cm_tuning_get: choice[0..2] that a call of N outputs would use now.
+ *   cm_tuning_save / cm_tuning_load: text file, one entry per line
+ *     "op key_type with_payload size_class config search partition ms";
+ *     load merges the file into the table (CM_EINVAL on a malformed line,
+ *     leaving the table unchanged).
+ *   cm_tuning_clear / cm_tuning_count: empty / size of the table.
+ */
+int cm_tuning_set(int op, int key_type, int with_payload, int size_class,
+                  int config_id, int search_mode, int partition_mode);
+int cm_tuning_get(int op, int key_type, int with_payload, uint64_t num_outputs, int *choice);
+int cm_tuning_save(const char *path);
+int cm_tuning_load(const char *path);
+int cm_tuning_clear(void);
+int cm_tuning_count(void);
+
+/*
+ * Graph plans: the whole kernel sequence of one merge call, captured once
+ * into a HIP graph (on a private stream; the capture records no memory
+ * sets) and replayed with one launch.  The plan keeps the caller's
+ * pointers and sizes: the buffers must outlive the plan, and a replay reads
+ * their contents at replay time.  The tuning choice is fixed at creation.
+ * Arguments are those of cm_stable_merge_pairs / cm_stable_merge_segmented
+ * (payload pointers all NULL for keys only).
+ *   cm_plan_create_*: CM_OK and *plan set, or an error of the merge call,
+ *     or CM_EHIP if capture or instantiation failed (*plan = NULL).
+ *   cm_plan_launch: one graph launch on `stream`.
+ *   cm_plan_destroy: frees the plan (not while a launch may still run).
+ */
+typedef struct cm_plan cm_plan;
+int cm_plan_create_merge(int key_type,
+                         const void *A, const uint32_t *A_val, uint64_t m,
+                         const void *B, const uint32_t *B_val, uint64_t n,
+                         void *C, uint32_t *C_val,
+                         void *workspace, size_t workspace_bytes, cm_plan **plan);
+int cm_plan_create_segmented(int key_type,
+                             const void *A, const uint32_t *A_val, const uint64_t *a_off,
+                             uint64_t total_a,
+                             const void *B, const uint32_t *B_val, const uint64_t *b_off,
+                             uint64_t total_b, uint64_t num_seg,
+                             void *C, uint32_t *C_val,
+                             void *workspace, size_t workspace_bytes, cm_plan **plan);
+int cm_plan_launch(cm_plan *plan, hipStream_t stream);
+int cm_plan_destroy(cm_plan *plan);
+
+/*
+ * Per-merge-launch form of cm_stable_merge_segmented: the same batch run as
+ * one single-merge call per segment (two kernel launches each), the
+ * baseline the one-pass batch is measured against.  a_off_host / b_off_host
+ * are host copies of the offsets (num_seg + 1 entries); the key and payload
+ * arrays are device arrays as in cm_stable_merge_segmented; workspace must
+ * hold cm_merge_workspace_size(key_type, with_payload, m_s, n_s) bytes for
+ * the largest segment.  Output is identical to cm_stable_merge_segmented.
+ * Errors: as cm_stable_merge_pairs, plus CM_EINVAL for inconsistent host
+ * offsets (checked before anything is launched).
+ */
+int cm_stable_merge_segmented_each(int key_type,
+                                   const void *A, const uint32_t *A_val, const uint64_t *a_off_host,
+                                   uint64_t total_a,
+                                   const void *B, const uint32_t *B_val, const uint64_t *b_off_host,
+                                   uint64_t total_b,
+                                   uint64_t num_seg,
+                                   void *C, uint32_t *C_val,
+                                   void *workspace, size_t workspace_bytes,
+                                   hipStream_t stream);
+
+/*
+ * Measurement helpers (not part of the method).
+ *
+ * cm_copy: copies `bytes` bytes from device src to device dst on `stream`
+ *   with 16-byte vector loads and stores (a plain streaming copy; used to
+ *   calibrate hardware byte counters and to measure the copy ceiling).
+ *   src and dst must not overlap (CM_EALIAS); both must be 16-byte aligned
+ *   and bytes a multiple of 16 (CM_EINVAL).
+ * cm_timing_start(capacity): from now on, each of the next `capacity` merge
+ *   calls (single or segmented; not the per-merge-launch form) records HIP
+ *   events on its stream before its first kernel, between its co-rank pass
+ *   and its block-merge kernel, and after the block-merge kernel.  Creates
+ *   the events (no device memory is allocated).  CM_EINVAL if capacity is 0
+ *   or timing is already on.
+ * cm_timing_stop: waits for the recorded events, writes the number of timed
+ *   calls and the mean duration in milliseconds of the co-rank pass and of
+ *   the block-merge kernel over them (either output may be NULL), and
+ *   releases the events.  CM_EINVAL if timing is off.
+ */
+int cm_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
+int cm_timing_start(uint32_t capacity);
+int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean);
 
 #ifdef __cplusplus
 }

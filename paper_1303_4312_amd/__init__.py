@@ -23,7 +23,11 @@ __all__ = [
     "CMError", "library_path", "co_rank_host", "co_rank", "stable_merge",
     "stable_merge_pairs", "stable_merge_segmented", "merge_workspace_size",
     "segmented_workspace_size", "check_sorted", "config_count", "config_info",
-    "set_config", "get_config", "set_search", "KEY_TYPES",
+    "set_config", "get_config", "set_search", "KEY_TYPES", "stable_merge_segmented_each",
+    "copy", "timing_start", "timing_stop", "get_search", "set_partition", "get_partition",
+    "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
+    "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
+    "OP_MERGE", "OP_SEGMENTED",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -31,6 +35,8 @@ library_path = os.path.join(_HERE, "libcorank_merge.so")
 
 # C enum cm_key_type
 KEY_U32, KEY_U64, KEY_F32 = 0, 1, 2
+# operations of the tuning table
+OP_MERGE, OP_SEGMENTED = 0, 1
 KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
 
 EXPORTS = [
@@ -38,7 +44,11 @@ EXPORTS = [
     "cm_merge_workspace_size", "cm_stable_merge", "cm_stable_merge_pairs",
     "cm_segmented_workspace_size", "cm_stable_merge_segmented", "cm_check_sorted",
     "cm_config_count", "cm_config_info", "cm_set_config", "cm_get_config",
-    "cm_set_search",
+    "cm_set_search", "cm_get_search", "cm_set_partition", "cm_get_partition",
+    "cm_stable_merge_segmented_each", "cm_copy", "cm_timing_start", "cm_timing_stop",
+    "cm_autotune_merge", "cm_autotune_segmented", "cm_tuning_set", "cm_tuning_get",
+    "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
+    "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
 ]
 
 _lib = None
@@ -80,6 +90,31 @@ def load():
         "cm_set_config": (c_int, [c_int, c_int, c_int]),
         "cm_get_config": (c_int, [c_int, c_int]),
         "cm_set_search": (c_int, [c_int]),
+        "cm_get_search": (c_int, []),
+        "cm_set_partition": (c_int, [c_int]),
+        "cm_get_partition": (c_int, []),
+        "cm_stable_merge_segmented_each": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
+                                                   c_u64, vp, vp, vp, c_size, vp]),
+        "cm_copy": (c_int, [vp, vp, c_u64, vp]),
+        "cm_autotune_merge": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp, c_size,
+                                      c_int, vp, ctypes.POINTER(c_int)]),
+        "cm_autotune_segmented": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64, c_u64, vp,
+                                          vp, vp, c_size, c_int, vp, ctypes.POINTER(c_int)]),
+        "cm_tuning_set": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
+        "cm_tuning_get": (c_int, [c_int, c_int, c_int, c_u64, ctypes.POINTER(c_int)]),
+        "cm_tuning_save": (c_int, [ctypes.c_char_p]),
+        "cm_tuning_load": (c_int, [ctypes.c_char_p]),
+        "cm_tuning_clear": (c_int, []),
+        "cm_tuning_count": (c_int, []),
+        "cm_plan_create_merge": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp, c_size,
+                                         ctypes.POINTER(vp)]),
+        "cm_plan_create_segmented": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64, c_u64,
+                                             vp, vp, vp, c_size, ctypes.POINTER(vp)]),
+        "cm_plan_launch": (c_int, [vp, vp]),
+        "cm_plan_destroy": (c_int, [vp]),
+        "cm_timing_start": (c_int, [ctypes.c_uint32]),
+        "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -276,6 +311,63 @@ def stable_merge_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C
     return (C, C_val) if with_val else C
 
 
+def stable_merge_segmented_each(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=None,
+                                workspace=None, stream=None):
+    """The batch of stable_merge_segmented run as one merge call per segment
+    (the per-merge-launch baseline).  a_off, b_off: host (numpy uint64)
+    offsets.  Returns C or (C, C_val)."""
+    import numpy as np
+    torch = _torch()
+    A = _dev(A, "A")
+    B = _dev(B, "B", A.dtype)
+    a_off = np.ascontiguousarray(a_off, dtype=np.uint64)
+    b_off = np.ascontiguousarray(b_off, dtype=np.uint64)
+    if a_off.shape != b_off.shape or a_off.size < 1:
+        raise ValueError("a_off and b_off need num_seg + 1 entries each")
+    with_val = A_val is not None
+    ta, tb = A.numel(), B.numel()
+    if C is None:
+        C = torch.empty(ta + tb, dtype=A.dtype, device=A.device)
+    if with_val:
+        A_val = _dev(A_val, "A_val", torch.uint32)
+        B_val = _dev(B_val, "B_val", torch.uint32)
+        if C_val is None:
+            C_val = torch.empty(ta + tb, dtype=torch.uint32, device=A.device)
+    kt = _key_type(A)
+    la = np.diff(a_off.astype(np.int64))
+    lb = np.diff(b_off.astype(np.int64))
+    biggest = int((la + lb).max()) if la.size else 0
+    ws, wsb = _workspace(load().cm_merge_workspace_size(kt, int(with_val), biggest, 0), A.device,
+                         workspace)
+    _check(load().cm_stable_merge_segmented_each(
+        kt, _ptr(A), _ptr(A_val) if with_val else None, a_off.ctypes.data_as(ctypes.c_void_p), ta,
+        _ptr(B), _ptr(B_val) if with_val else None, b_off.ctypes.data_as(ctypes.c_void_p), tb,
+        a_off.size - 1, _ptr(C), _ptr(C_val) if with_val else None, _ptr(ws), wsb,
+        _stream(stream, A.device)), "cm_stable_merge_segmented_each")
+    return (C, C_val) if with_val else C
+
+
+def copy(src, dst, stream=None):
+    """Plain 16-byte-vector device copy of src into dst (measurement helper)."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _check(load().cm_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream, src.device)), "cm_copy")
+
+
+def timing_start(capacity: int):
+    """Record kernel events around the next `capacity` merge calls."""
+    _check(load().cm_timing_start(capacity), "cm_timing_start")
+
+
+def timing_stop():
+    """Returns (calls, mean co-rank pass ms, mean block-merge kernel ms)."""
+    calls, tb, tm = ctypes.c_uint32(), ctypes.c_double(), ctypes.c_double()
+    _check(load().cm_timing_stop(ctypes.byref(calls), ctypes.byref(tb), ctypes.byref(tm)),
+           "cm_timing_stop")
+    return calls.value, tb.value, tm.value
+
+
 def check_sorted(X, stream=None) -> bool:
     """True if the device key array X is nondecreasing (synchronises)."""
     torch = _torch()
@@ -307,5 +399,176 @@ def get_config(key_dtype, with_payload: bool) -> int:
 
 
 def set_search(mode: int):
-    """0 = Algorithm 1 (default), 1 = bisection."""
+    """Per-thread / one-level co-rank search: 0 = Algorithm 1, 1 = bisection."""
     _check(load().cm_set_search(mode), "cm_set_search")
+
+
+def get_search() -> int:
+    return load().cm_get_search()
+
+
+def set_partition(mode: int):
+    """Block-boundary pass: 0 = one thread per boundary, 1 = two-level."""
+    _check(load().cm_set_partition(mode), "cm_set_partition")
+
+
+def get_partition() -> int:
+    return load().cm_get_partition()
+
+
+# ---------------------------------------------------------------------------
+# argument marshalling shared by merge calls, tuner and plans
+
+
+def _pair_args(A, B, A_val, B_val, C, C_val):
+    """Validated (kt, with_val, m, n, A, Av, B, Bv, C, Cv) for one merge;
+    allocates C / C_val when not given."""
+    torch = _torch()
+    A = _dev(A, "A")
+    B = _dev(B, "B", A.dtype)
+    with_val = A_val is not None
+    if with_val != (B_val is not None):
+        raise ValueError("give payloads for both inputs or neither")
+    m, n = A.numel(), B.numel()
+    if C is None:
+        C = torch.empty(m + n, dtype=A.dtype, device=A.device)
+    C = _dev(C, "C", A.dtype)
+    if C.numel() != m + n:
+        raise ValueError("C must hold m + n keys")
+    if with_val:
+        A_val = _dev(A_val, "A_val", torch.uint32)
+        B_val = _dev(B_val, "B_val", torch.uint32)
+        if A_val.numel() != m or B_val.numel() != n:
+            raise ValueError("payload lengths must match key lengths")
+        if C_val is None:
+            C_val = torch.empty(m + n, dtype=torch.uint32, device=A.device)
+        C_val = _dev(C_val, "C_val", torch.uint32)
+        if C_val.numel() != m + n:
+            raise ValueError("C_val must hold m + n payloads")
+    else:
+        A_val = B_val = C_val = None
+    return _key_type(A), with_val, m, n, A, A_val, B, B_val, C, C_val
+
+
+def _seg_args(A, a_off, B, b_off, A_val, B_val, C, C_val):
+    torch = _torch()
+    kt, with_val, ta, tb, A, A_val, B, B_val, C, C_val = _pair_args(A, B, A_val, B_val, C, C_val)
+    a_off = _dev(a_off, "a_off", torch.uint64)
+    b_off = _dev(b_off, "b_off", torch.uint64)
+    if a_off.numel() != b_off.numel() or a_off.numel() < 1:
+        raise ValueError("a_off and b_off need num_seg + 1 entries each")
+    return kt, with_val, ta, tb, a_off.numel() - 1, A, A_val, a_off, B, B_val, b_off, C, C_val
+
+
+def autotune_merge(A, B, A_val=None, B_val=None, reps=5, stream=None):
+    """Time every (config, search, partition) on these inputs and record the
+    fastest for their size class; returns (config, search, partition)."""
+    kt, with_val, m, n, A, A_val, B, B_val, C, C_val = _pair_args(A, B, A_val, B_val, None, None)
+    ws, wsb = _workspace(load().cm_merge_workspace_size(kt, int(with_val), m, n), A.device, None)
+    best = (ctypes.c_int * 3)()
+    _check(load().cm_autotune_merge(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n, _ptr(C),
+                                    _ptr(C_val), _ptr(ws), wsb, reps, _stream(stream, A.device),
+                                    best), "cm_autotune_merge")
+    return tuple(best)
+
+
+def autotune_segmented(A, a_off, B, b_off, A_val=None, B_val=None, reps=5, stream=None):
+    """Tuner for the segmented batch; returns (config, search, partition)."""
+    kt, with_val, ta, tb, S, A, A_val, a_off, B, B_val, b_off, C, C_val = _seg_args(
+        A, a_off, B, b_off, A_val, B_val, None, None)
+    ws, wsb = _workspace(load().cm_segmented_workspace_size(kt, int(with_val), ta, tb, S), A.device,
+                         None)
+    best = (ctypes.c_int * 3)()
+    _check(load().cm_autotune_segmented(kt, _ptr(A), _ptr(A_val), _ptr(a_off), ta, _ptr(B),
+                                        _ptr(B_val), _ptr(b_off), tb, S, _ptr(C), _ptr(C_val),
+                                        _ptr(ws), wsb, reps, _stream(stream, A.device), best),
+           "cm_autotune_segmented")
+    return tuple(best)
+
+
+def tuning_set(op, key_dtype, with_payload, size_class, config, search, partition):
+    kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
+    _check(load().cm_tuning_set(op, kt, int(bool(with_payload)), size_class, config, search,
+                                partition), "cm_tuning_set")
+
+
+def tuning_get(op, key_dtype, with_payload, num_outputs):
+    """(config, search, partition) a call of num_outputs outputs would use."""
+    kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
+    out = (ctypes.c_int * 3)()
+    _check(load().cm_tuning_get(op, kt, int(bool(with_payload)), num_outputs, out),
+           "cm_tuning_get")
+    return tuple(out)
+
+
+def tuning_save(path):
+    _check(load().cm_tuning_save(os.fsencode(path)), "cm_tuning_save")
+
+
+def tuning_load(path):
+    _check(load().cm_tuning_load(os.fsencode(path)), "cm_tuning_load")
+
+
+def tuning_clear():
+    _check(load().cm_tuning_clear(), "cm_tuning_clear")
+
+
+def tuning_count() -> int:
+    return load().cm_tuning_count()
+
+
+class Plan:
+    """A merge call captured once into a HIP graph; launch() replays it.
+    Holds references to every buffer it was built on (they must stay alive
+    and in place); outputs are the attributes C and C_val."""
+
+    def __init__(self, handle, device, keep, C, C_val):
+        self._handle = handle
+        self._device = device
+        self._keep = keep
+        self.C = C
+        self.C_val = C_val
+
+    def launch(self, stream=None):
+        if self._handle is None:
+            raise RuntimeError("plan already closed")
+        _check(load().cm_plan_launch(self._handle, _stream(stream, self._device)),
+               "cm_plan_launch")
+        return (self.C, self.C_val) if self.C_val is not None else self.C
+
+    def close(self):
+        if self._handle is not None:
+            _torch().cuda.synchronize(self._device)
+            _check(load().cm_plan_destroy(self._handle), "cm_plan_destroy")
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def plan_merge(A, B, A_val=None, B_val=None, C=None, C_val=None, workspace=None) -> Plan:
+    kt, with_val, m, n, A, A_val, B, B_val, C, C_val = _pair_args(A, B, A_val, B_val, C, C_val)
+    ws, wsb = _workspace(load().cm_merge_workspace_size(kt, int(with_val), m, n), A.device,
+                         workspace)
+    h = ctypes.c_void_p()
+    _check(load().cm_plan_create_merge(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n,
+                                       _ptr(C), _ptr(C_val), _ptr(ws), wsb, ctypes.byref(h)),
+           "cm_plan_create_merge")
+    return Plan(h, A.device, (A, A_val, B, B_val, ws), C, C_val)
+
+
+def plan_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=None,
+                   workspace=None) -> Plan:
+    kt, with_val, ta, tb, S, A, A_val, a_off, B, B_val, b_off, C, C_val = _seg_args(
+        A, a_off, B, b_off, A_val, B_val, C, C_val)
+    ws, wsb = _workspace(load().cm_segmented_workspace_size(kt, int(with_val), ta, tb, S), A.device,
+                         workspace)
+    h = ctypes.c_void_p()
+    _check(load().cm_plan_create_segmented(kt, _ptr(A), _ptr(A_val), _ptr(a_off), ta, _ptr(B),
+                                           _ptr(B_val), _ptr(b_off), tb, S, _ptr(C), _ptr(C_val),
+                                           _ptr(ws), wsb, ctypes.byref(h)),
+           "cm_plan_create_segmented")
+    return Plan(h, A.device, (A, A_val, a_off, B, B_val, b_off, ws), C, C_val)

@@ -17,8 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_NAME = "libcorank_merge.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-HIP_SOURCES = ["corank_merge.hip"]
-CXX_SOURCES = ["host_co_rank.cpp"]
+HIP_SOURCES = ["launch.hip"]
+CXX_SOURCES = ["api.cpp", "host_co_rank.cpp"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed fp32 VALU ops.
 HIPCC_FLAGS = [

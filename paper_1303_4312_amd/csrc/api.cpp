@@ -1,0 +1,701 @@
+// C ABI of the co-rank stable merge (see include/corank_merge.h): argument
+// checks, the per-call choice of tile configuration and co-rank strategy,
+// the tuning table and autotuner, graph plans, kernel timing, and the
+// per-merge-launch baseline.  Kernel launches live in launch.hip.
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+
+#include "corank_merge.h"
+#include "internal.hpp"
+
+namespace cm {
+namespace {
+
+// ---------------------------------------------------------------------------
+// process-wide settings
+
+struct Settings {
+  int cfg[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [key type][payload] default configuration
+  int search = 1;                             // bisection
+  int partition = 1;                          // two-level boundary pass
+};
+Settings g_set;
+
+// Tuning table: (op, key type, payload, size class) -> choice.  The size
+// class of a merge of N outputs is the bit length of N.
+using TuneKey = std::tuple<int, int, int, int>;
+struct TuneEntry {
+  Choice ch;
+  double ms;
+};
+std::map<TuneKey, TuneEntry> g_tuning;
+std::mutex g_tuning_mu;
+
+int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
+
+Choice resolve(int op, int kt, bool val, uint64_t N) {
+  {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    auto it = g_tuning.find(TuneKey{op, kt, val ? 1 : 0, size_class(N)});
+    if (it != g_tuning.end()) return it->second.ch;
+  }
+  return Choice{g_set.cfg[kt][val ? 1 : 0], g_set.search, g_set.partition};
+}
+
+// ---------------------------------------------------------------------------
+// kernel timing (three events per timed call)
+
+struct Timing {
+  bool on = false;
+  uint32_t capacity = 0;
+  uint32_t used = 0;
+  hipEvent_t* ev = nullptr;
+};
+Timing g_timing;
+bool g_capturing = false;  // graph capture in progress: record no timing events
+
+void timing_mark(int slot, hipStream_t st) {
+  if (!g_timing.on || g_capturing || g_timing.used >= g_timing.capacity) return;
+  (void)hipEventRecord(g_timing.ev[3ull * g_timing.used + slot], st);
+  if (slot == 2) ++g_timing.used;
+}
+
+// ---------------------------------------------------------------------------
+// checks
+
+bool key_type_ok(int kt) { return kt == CM_KEY_U32 || kt == CM_KEY_U64 || kt == CM_KEY_F32; }
+size_t key_bytes(int kt) { return kt == CM_KEY_U64 ? 8 : 4; }
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool overlap(const void* p, uint64_t pbytes, const void* q, uint64_t qbytes) {
+  if (!p || !q || pbytes == 0 || qbytes == 0) return false;
+  const uintptr_t a = (uintptr_t)p, b = (uintptr_t)q;
+  return a < b + qbytes && b < a + pbytes;
+}
+
+// A region and its size, for overlap checks.
+struct Span {
+  const void* p;
+  uint64_t bytes;
+};
+
+bool any_overlap(std::initializer_list<Span> outs, std::initializer_list<Span> ins) {
+  for (const Span& o : outs) {
+    for (const Span& i : ins)
+      if (overlap(o.p, o.bytes, i.p, i.bytes)) return true;
+  }
+  // outputs must not overlap each other either
+  for (auto a = outs.begin(); a != outs.end(); ++a)
+    for (auto b = a + 1; b != outs.end(); ++b)
+      if (overlap(a->p, a->bytes, b->p, b->bytes)) return true;
+  return false;
+}
+
+// Workspace of a single merge: block co-ranks + coarse co-ranks, sized for
+// the smallest block of any configuration.
+size_t merge_ws_bytes(uint64_t N) {
+  const uint64_t nb = (N + kMinTile - 1) / kMinTile + 1;
+  return round256(nb * sizeof(uint64_t)) + round256(num_coarse(nb) * sizeof(uint64_t));
+}
+
+struct SegWs {
+  uint32_t* flag;
+  uint64_t* bj;
+  uint32_t* bs;
+  size_t bytes;
+};
+
+SegWs seg_ws(void* ws, uint64_t N) {
+  const uint64_t nb = (N + kMinTile - 1) / kMinTile + 1;
+  char* p = (char*)ws;
+  SegWs w;
+  w.flag = (uint32_t*)p;
+  size_t off = 256;
+  w.bj = (uint64_t*)(p + off);
+  off += round256(nb * sizeof(uint64_t));
+  w.bs = (uint32_t*)(p + off);
+  off += round256(nb * sizeof(uint32_t));
+  w.bytes = off;
+  return w;
+}
+
+// ---------------------------------------------------------------------------
+// implementations
+
+// With dry_run set, only the argument checks run (nothing is launched).
+int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, const void* B, const uint32_t* Bv,
+               uint64_t n, void* C, uint32_t* Cv, void* ws, size_t ws_bytes, hipStream_t st,
+               const Choice* forced = nullptr, bool dry_run = false) {
+  if (!key_type_ok(kt)) return CM_EDTYPE;
+  if (m + n < m) return CM_EINVAL;
+  const uint64_t N = m + n;
+  const size_t ks = key_bytes(kt);
+  if ((m && !A) || (n && !B) || (N && !C)) return CM_EINVAL;
+  if (val && ((m && !Av) || (n && !Bv) || (N && !Cv))) return CM_EINVAL;
+  if (N == 0) return CM_OK;
+  const size_t need = merge_ws_bytes(N);
+  if (!ws || ws_bytes < need) return CM_ENOSPC;
+  const Span ins[] = {{A, m * ks}, {B, n * ks}, {Av, val ? m * 4 : 0}, {Bv, val ? n * 4 : 0}};
+  if (any_overlap({{C, N * ks}, {Cv, val ? N * 4 : 0}, {ws, need}},
+                  {ins[0], ins[1], ins[2], ins[3]}))
+    return CM_EALIAS;
+  const Choice ch = forced ? *forced : resolve(kOpMerge, kt, val, N);
+  const uint64_t T = tile_size(ch.cfg);
+  const uint64_t tiles = (N + T - 1) / T;
+  if (tiles >= (1ull << 31)) return CM_EINVAL;
+  if (dry_run) return CM_OK;
+  uint64_t* bj = (uint64_t*)ws;
+  uint64_t* coarse = (uint64_t*)((char*)ws + round256(((N + kMinTile - 1) / kMinTile + 1) * sizeof(uint64_t)));
+  timing_mark(0, st);
+  int rc = launch_block_co_ranks(kt, ch, A, m, B, n, T, tiles + 1, bj, coarse, st);
+  if (rc != CM_OK) return rc;
+  timing_mark(1, st);
+  rc = launch_merge_blocks(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st);
+  timing_mark(2, st);
+  return rc;
+}
+
+int seg_impl(int kt, const void* A, const uint32_t* Av, const uint64_t* a_off, uint64_t total_a, const void* B,
+             const uint32_t* Bv, const uint64_t* b_off, uint64_t total_b, uint64_t S, void* C, uint32_t* Cv,
+             void* ws, size_t ws_bytes, hipStream_t st, const Choice* forced = nullptr, bool dry_run = false) {
+  if (!key_type_ok(kt)) return CM_EDTYPE;
+  const bool val = Av || Bv || Cv;
+  if (total_a + total_b < total_a) return CM_EINVAL;
+  const uint64_t N = total_a + total_b;
+  if (val && ((total_a && !Av) || (total_b && !Bv) || (N && !Cv))) return CM_EINVAL;
+  if (S >= (1ull << 32)) return CM_EINVAL;
+  if (S == 0) return N == 0 ? CM_OK : CM_EINVAL;
+  if (!a_off || !b_off) return CM_EINVAL;
+  const size_t ks = key_bytes(kt);
+  if ((total_a && !A) || (total_b && !B) || (N && !C)) return CM_EINVAL;
+  const SegWs w = seg_ws(ws, N);
+  if (!ws || ws_bytes < w.bytes) return CM_ENOSPC;
+  if (any_overlap({{C, N * ks}, {Cv, val ? N * 4 : 0}, {ws, w.bytes}},
+                  {{A, total_a * ks}, {B, total_b * ks}, {Av, val ? total_a * 4 : 0}, {Bv, val ? total_b * 4 : 0},
+                   {a_off, (S + 1) * 8}, {b_off, (S + 1) * 8}}))
+    return CM_EALIAS;
+  const Choice ch = forced ? *forced : resolve(kOpSegmented, kt, val, N);
+  const uint64_t T = tile_size(ch.cfg);
+  const uint64_t tiles = (N + T - 1) / T;
+  if (tiles >= (1ull << 31)) return CM_EINVAL;
+  if (dry_run) return CM_OK;
+  if (N == 0) return launch_seg_validate(a_off, b_off, S, total_a, total_b, w.flag, st);
+  timing_mark(0, st);
+  int rc = launch_seg_validate(a_off, b_off, S, total_a, total_b, w.flag, st);
+  if (rc == CM_OK)
+    rc = launch_seg_block_co_ranks(kt, ch, A, a_off, B, b_off, (uint32_t)S, N, T, tiles + 1, w.bj, w.bs, w.flag,
+                                   st);
+  if (rc != CM_OK) return rc;
+  timing_mark(1, st);
+  rc = launch_seg_merge_blocks(kt, val, ch, A, Av, a_off, B, Bv, b_off, (uint32_t)S, N, C, Cv, w.bj, w.bs, tiles,
+                               w.flag, st);
+  timing_mark(2, st);
+  return rc;
+}
+
+// Mean milliseconds of `reps` calls of f() on stream st (after one warm call).
+template <typename F>
+int time_calls(F&& f, int reps, hipStream_t st, double* ms) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return CM_EHIP;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return CM_EHIP;
+  }
+  int rc = f();
+  if (rc == CM_OK && hipEventRecord(e0, st) != hipSuccess) rc = CM_EHIP;
+  for (int r = 0; r < reps && rc == CM_OK; ++r) rc = f();
+  if (rc == CM_OK && hipEventRecord(e1, st) != hipSuccess) rc = CM_EHIP;
+  float t = 0;
+  if (rc == CM_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
+    rc = CM_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t / reps;
+  return rc;
+}
+
+}  // namespace
+}  // namespace cm
+
+// ---------------------------------------------------------------------------
+// C ABI
+
+using namespace cm;
+
+struct cm_plan {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" {
+
+const char* cm_status_string(int status) {
+  switch (status) {
+    case CM_OK: return "ok";
+    case CM_EINVAL: return "invalid argument";
+    case CM_ERANGE: return "rank out of range";
+    case CM_EDTYPE: return "unknown key type";
+    case CM_EALIAS: return "output overlaps an input";
+    case CM_ENOSPC: return "workspace too small";
+    case CM_EHIP: return "HIP runtime error";
+    case CM_EUNSORTED: return "array not sorted";
+    case CM_ECONFIG: return "unknown tile configuration";
+    default: return "unknown status";
+  }
+}
+
+int cm_version(void) { return 2; }
+
+int cm_co_rank(int key_type, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m, const void* B,
+               uint64_t n, uint64_t* j_out, hipStream_t stream) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (m + n < m) return CM_EINVAL;
+  if ((m && !A) || (n && !B) || (q && (!ranks || !j_out))) return CM_EINVAL;
+  const size_t ks = key_bytes(key_type);
+  if (any_overlap({{j_out, q * 8}}, {{ranks, q * 8}, {A, m * ks}, {B, n * ks}})) return CM_EALIAS;
+  if (q == 0) return CM_OK;
+  if ((q + 255) / 256 >= (1ull << 31)) return CM_EINVAL;
+  return launch_co_rank_many(key_type, g_set.search, ranks, q, A, m, B, n, j_out, stream);
+}
+
+size_t cm_merge_workspace_size(int key_type, int with_payload, uint64_t m, uint64_t n) {
+  (void)with_payload;
+  if (!key_type_ok(key_type) || m + n == 0) return 0;
+  return merge_ws_bytes(m + n);
+}
+
+int cm_stable_merge(int key_type, const void* A, uint64_t m, const void* B, uint64_t n, void* C, void* workspace,
+                    size_t workspace_bytes, hipStream_t stream) {
+  return merge_impl(key_type, false, A, nullptr, m, B, nullptr, n, C, nullptr, workspace, workspace_bytes, stream);
+}
+
+int cm_stable_merge_pairs(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                          const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+  return merge_impl(key_type, true, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes, stream);
+}
+
+size_t cm_segmented_workspace_size(int key_type, int with_payload, uint64_t total_a, uint64_t total_b,
+                                   uint64_t num_seg) {
+  (void)with_payload;
+  (void)num_seg;
+  if (!key_type_ok(key_type)) return 0;
+  return seg_ws(nullptr, total_a + total_b).bytes;
+}
+
+int cm_stable_merge_segmented(int key_type, const void* A, const uint32_t* A_val, const uint64_t* a_off,
+                              uint64_t total_a, const void* B, const uint32_t* B_val, const uint64_t* b_off,
+                              uint64_t total_b, uint64_t num_seg, void* C, uint32_t* C_val, void* workspace,
+                              size_t workspace_bytes, hipStream_t stream) {
+  return seg_impl(key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val, workspace,
+                  workspace_bytes, stream);
+}
+
+int cm_stable_merge_segmented_each(int key_type, const void* A, const uint32_t* A_val, const uint64_t* a_off_host,
+                                   uint64_t total_a, const void* B, const uint32_t* B_val,
+                                   const uint64_t* b_off_host, uint64_t total_b, uint64_t num_seg, void* C,
+                                   uint32_t* C_val, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  const bool val = A_val || B_val || C_val;
+  if (num_seg == 0) return total_a + total_b == 0 ? CM_OK : CM_EINVAL;
+  if (!a_off_host || !b_off_host) return CM_EINVAL;
+  if (a_off_host[0] != 0 || b_off_host[0] != 0 || a_off_host[num_seg] != total_a ||
+      b_off_host[num_seg] != total_b)
+    return CM_EINVAL;
+  for (uint64_t s = 0; s < num_seg; ++s)
+    if (a_off_host[s] > a_off_host[s + 1] || b_off_host[s] > b_off_host[s + 1]) return CM_EINVAL;
+  const size_t ks = key_bytes(key_type);
+  const bool timing_was_on = g_timing.on;  // this form is not timed per kernel
+  g_timing.on = false;
+  int rc = CM_OK;
+  for (uint64_t s = 0; s < num_seg && rc == CM_OK; ++s) {
+    const uint64_t a0 = a_off_host[s], b0 = b_off_host[s];
+    const uint64_t ms = a_off_host[s + 1] - a0, ns = b_off_host[s + 1] - b0;
+    rc = merge_impl(key_type, val, A ? (const char*)A + a0 * ks : nullptr, val && A_val ? A_val + a0 : nullptr, ms,
+                    B ? (const char*)B + b0 * ks : nullptr, val && B_val ? B_val + b0 : nullptr, ns,
+                    C ? (char*)C + (a0 + b0) * ks : nullptr, val && C_val ? C_val + a0 + b0 : nullptr, workspace,
+                    workspace_bytes, stream);
+  }
+  g_timing.on = timing_was_on;
+  return rc;
+}
+
+int cm_check_sorted(int key_type, const void* X, uint64_t len, uint32_t* flag, hipStream_t stream) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (!flag || (len && !X)) return CM_EINVAL;
+  return launch_check_sorted(key_type, X, len, flag, stream);
+}
+
+// ---- configuration and settings
+
+int cm_config_count(void) { return kNumCfgs; }
+
+int cm_config_info(int config_id, int* threads, int* items_per_thread) {
+  if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
+  if (threads) *threads = kCfgs[config_id].nt;
+  if (items_per_thread) *items_per_thread = kCfgs[config_id].e;
+  return CM_OK;
+}
+
+int cm_set_config(int key_type, int with_payload, int config_id) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
+  g_set.cfg[key_type][with_payload ? 1 : 0] = config_id;
+  return CM_OK;
+}
+
+int cm_get_config(int key_type, int with_payload) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  return g_set.cfg[key_type][with_payload ? 1 : 0];
+}
+
+int cm_set_search(int search_mode) {
+  if (search_mode != 0 && search_mode != 1) return CM_EINVAL;
+  g_set.search = search_mode;
+  return CM_OK;
+}
+
+int cm_get_search(void) { return g_set.search; }
+
+int cm_set_partition(int partition_mode) {
+  if (partition_mode != 0 && partition_mode != 1) return CM_EINVAL;
+  g_set.partition = partition_mode;
+  return CM_OK;
+}
+
+int cm_get_partition(void) { return g_set.partition; }
+
+// ---- autotuner
+
+int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                      const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, void* workspace,
+                      size_t workspace_bytes, int reps, hipStream_t stream, int* best) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (reps < 1 || reps > 10000 || m + n == 0) return CM_EINVAL;
+  const bool val = A_val || B_val || C_val;
+  const int check = merge_impl(key_type, val, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes,
+                               stream, nullptr, true);
+  if (check != CM_OK) return check;
+  Choice win{0, 1, 1};
+  double win_ms = 0;
+  bool have = false;
+  for (int cfg = 0; cfg < kNumCfgs; ++cfg)
+    for (int search = 0; search < 2; ++search)
+      for (int part = 0; part < 2; ++part) {
+        const Choice ch{cfg, search, part};
+        double ms = 0;
+        const int rc = time_calls(
+            [&] {
+              return merge_impl(key_type, val, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes,
+                                stream, &ch);
+            },
+            reps, stream, &ms);
+        if (rc != CM_OK) return rc;
+        if (!have || ms < win_ms) {
+          win = ch;
+          win_ms = ms;
+          have = true;
+        }
+      }
+  {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning[TuneKey{kOpMerge, key_type, val ? 1 : 0, size_class(m + n)}] = TuneEntry{win, win_ms};
+  }
+  if (best) {
+    best[0] = win.cfg;
+    best[1] = win.search;
+    best[2] = win.partition;
+  }
+  return CM_OK;
+}
+
+int cm_autotune_segmented(int key_type, const void* A, const uint32_t* A_val, const uint64_t* a_off,
+                          uint64_t total_a, const void* B, const uint32_t* B_val, const uint64_t* b_off,
+                          uint64_t total_b, uint64_t num_seg, void* C, uint32_t* C_val, void* workspace,
+                          size_t workspace_bytes, int reps, hipStream_t stream, int* best) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (reps < 1 || reps > 10000 || total_a + total_b == 0) return CM_EINVAL;
+  const bool val = A_val || B_val || C_val;
+  const int check = seg_impl(key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val,
+                             workspace, workspace_bytes, stream, nullptr, true);
+  if (check != CM_OK) return check;
+  Choice win{0, 1, 1};
+  double win_ms = 0;
+  bool have = false;
+  for (int cfg = 0; cfg < kNumCfgs; ++cfg)
+    for (int search = 0; search < 2; ++search) {
+      const Choice ch{cfg, search, 0};
+      double ms = 0;
+      const int rc = time_calls(
+          [&] {
+            return seg_impl(key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val,
+                            workspace, workspace_bytes, stream, &ch);
+          },
+          reps, stream, &ms);
+      if (rc != CM_OK) return rc;
+      if (!have || ms < win_ms) {
+        win = ch;
+        win_ms = ms;
+        have = true;
+      }
+    }
+  {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    g_tuning[TuneKey{kOpSegmented, key_type, val ? 1 : 0, size_class(total_a + total_b)}] = TuneEntry{win, win_ms};
+  }
+  if (best) {
+    best[0] = win.cfg;
+    best[1] = win.search;
+    best[2] = win.partition;
+  }
+  return CM_OK;
+}
+
+int cm_tuning_count(void) {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  return (int)g_tuning.size();
+}
+
+int cm_tuning_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning.clear();
+  return CM_OK;
+}
+
+int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int config_id, int search_mode,
+                  int partition_mode) {
+  if (op != kOpMerge && op != kOpSegmented) return CM_EINVAL;
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
+  if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) ||
+      (partition_mode != 0 && partition_mode != 1))
+    return CM_EINVAL;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  g_tuning[TuneKey{op, key_type, with_payload ? 1 : 0, size_cls}] =
+      TuneEntry{Choice{config_id, search_mode, partition_mode}, 0.0};
+  return CM_OK;
+}
+
+int cm_tuning_get(int op, int key_type, int with_payload, uint64_t num_outputs, int* choice) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (!choice) return CM_EINVAL;
+  const Choice ch = resolve(op, key_type, with_payload != 0, num_outputs);
+  choice[0] = ch.cfg;
+  choice[1] = ch.search;
+  choice[2] = ch.partition;
+  return CM_OK;
+}
+
+int cm_tuning_save(const char* path) {
+  if (!path) return CM_EINVAL;
+  FILE* f = fopen(path, "w");
+  if (!f) return CM_EINVAL;
+  fprintf(f, "# corank_merge tuning v1: op key_type with_payload size_class config search partition ms\n");
+  {
+    std::lock_guard<std::mutex> lk(g_tuning_mu);
+    for (const auto& kv : g_tuning) {
+      const auto& k = kv.first;
+      const auto& e = kv.second;
+      fprintf(f, "%d %d %d %d %d %d %d %.6f\n", std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k),
+              e.ch.cfg, e.ch.search, e.ch.partition, e.ms);
+    }
+  }
+  return fclose(f) == 0 ? CM_OK : CM_EINVAL;
+}
+
+int cm_tuning_load(const char* path) {
+  if (!path) return CM_EINVAL;
+  FILE* f = fopen(path, "r");
+  if (!f) return CM_EINVAL;
+  char line[256];
+  int rc = CM_OK;
+  std::map<TuneKey, TuneEntry> loaded;
+  while (fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int op, kt, val, sc, cfg, search, part;
+    double ms;
+    if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
+        (op != kOpMerge && op != kOpSegmented) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
+        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || (part != 0 && part != 1)) {
+      rc = CM_EINVAL;
+      break;
+    }
+    loaded[TuneKey{op, kt, val, sc}] = TuneEntry{Choice{cfg, search, part}, ms};
+  }
+  fclose(f);
+  if (rc != CM_OK) return rc;
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  for (const auto& kv : loaded) g_tuning[kv.first] = kv.second;
+  return CM_OK;
+}
+
+// ---- graph plans
+
+static int plan_capture(cm_plan** out, int (*body)(void*, hipStream_t), void* ctx) {
+  if (!out) return CM_EINVAL;
+  *out = nullptr;
+  hipStream_t s;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return CM_EHIP;
+  cm_plan* p = new cm_plan;
+  int rc = CM_OK;
+  g_capturing = true;
+  if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = CM_EHIP;
+  const int body_rc = rc == CM_OK ? body(ctx, s) : rc;
+  if (rc == CM_OK && hipStreamEndCapture(s, &p->graph) != hipSuccess) rc = CM_EHIP;
+  g_capturing = false;
+  if (rc == CM_OK) rc = body_rc;
+  if (rc == CM_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) rc = CM_EHIP;
+  (void)hipStreamDestroy(s);
+  if (rc != CM_OK) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    delete p;
+    return rc;
+  }
+  *out = p;
+  return CM_OK;
+}
+
+struct MergeArgs {
+  int kt;
+  const void* A;
+  const uint32_t* Av;
+  uint64_t m;
+  const void* B;
+  const uint32_t* Bv;
+  uint64_t n;
+  void* C;
+  uint32_t* Cv;
+  void* ws;
+  size_t ws_bytes;
+};
+
+struct SegArgs {
+  int kt;
+  const void* A;
+  const uint32_t* Av;
+  const uint64_t* a_off;
+  uint64_t ta;
+  const void* B;
+  const uint32_t* Bv;
+  const uint64_t* b_off;
+  uint64_t tb;
+  uint64_t S;
+  void* C;
+  uint32_t* Cv;
+  void* ws;
+  size_t ws_bytes;
+};
+
+int cm_plan_create_merge(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                         const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, void* workspace,
+                         size_t workspace_bytes, cm_plan** plan) {
+  if (!plan) return CM_EINVAL;
+  *plan = nullptr;
+  const int rc = merge_impl(key_type, A_val || B_val || C_val, A, A_val, m, B, B_val, n, C, C_val, workspace,
+                            workspace_bytes, nullptr, nullptr, true);
+  if (rc != CM_OK) return rc;
+  MergeArgs a{key_type, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes};
+  return plan_capture(
+      plan,
+      [](void* ctx, hipStream_t s) {
+        const MergeArgs& x = *(const MergeArgs*)ctx;
+        const bool val = x.Av || x.Bv || x.Cv;
+        return merge_impl(x.kt, val, x.A, x.Av, x.m, x.B, x.Bv, x.n, x.C, x.Cv, x.ws, x.ws_bytes, s);
+      },
+      &a);
+}
+
+int cm_plan_create_segmented(int key_type, const void* A, const uint32_t* A_val, const uint64_t* a_off,
+                             uint64_t total_a, const void* B, const uint32_t* B_val, const uint64_t* b_off,
+                             uint64_t total_b, uint64_t num_seg, void* C, uint32_t* C_val, void* workspace,
+                             size_t workspace_bytes, cm_plan** plan) {
+  if (!plan) return CM_EINVAL;
+  *plan = nullptr;
+  const int rc = seg_impl(key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val,
+                          workspace, workspace_bytes, nullptr, nullptr, true);
+  if (rc != CM_OK) return rc;
+  SegArgs a{key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val, workspace,
+            workspace_bytes};
+  return plan_capture(
+      plan,
+      [](void* ctx, hipStream_t s) {
+        const SegArgs& x = *(const SegArgs*)ctx;
+        return seg_impl(x.kt, x.A, x.Av, x.a_off, x.ta, x.B, x.Bv, x.b_off, x.tb, x.S, x.C, x.Cv, x.ws,
+                        x.ws_bytes, s);
+      },
+      &a);
+}
+
+int cm_plan_launch(cm_plan* plan, hipStream_t stream) {
+  if (!plan || !plan->exec) return CM_EINVAL;
+  return hipGraphLaunch(plan->exec, stream) == hipSuccess ? CM_OK : CM_EHIP;
+}
+
+int cm_plan_destroy(cm_plan* plan) {
+  if (!plan) return CM_EINVAL;
+  int rc = CM_OK;
+  if (plan->exec && hipGraphExecDestroy(plan->exec) != hipSuccess) rc = CM_EHIP;
+  if (plan->graph && hipGraphDestroy(plan->graph) != hipSuccess) rc = CM_EHIP;
+  delete plan;
+  return rc;
+}
+
+// ---- measurement helpers
+
+int cm_copy(const void* src, void* dst, uint64_t bytes, hipStream_t stream) {
+  if (bytes == 0) return CM_OK;
+  if (!src || !dst || (bytes % 16) || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) return CM_EINVAL;
+  if (overlap(src, bytes, dst, bytes)) return CM_EALIAS;
+  return launch_copy16(src, dst, bytes / 16, stream);
+}
+
+int cm_timing_start(uint32_t capacity) {
+  if (capacity == 0 || g_timing.on) return CM_EINVAL;
+  g_timing.ev = new hipEvent_t[3ull * capacity];
+  for (uint64_t x = 0; x < 3ull * capacity; ++x) {
+    if (hipEventCreate(&g_timing.ev[x]) != hipSuccess) {
+      for (uint64_t y = 0; y < x; ++y) (void)hipEventDestroy(g_timing.ev[y]);
+      delete[] g_timing.ev;
+      g_timing.ev = nullptr;
+      return CM_EHIP;
+    }
+  }
+  g_timing.capacity = capacity;
+  g_timing.used = 0;
+  g_timing.on = true;
+  return CM_OK;
+}
+
+int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_mean) {
+  if (!g_timing.on && !g_timing.ev) return CM_EINVAL;
+  double sum_b = 0, sum_m = 0;
+  int rc = CM_OK;
+  for (uint32_t c = 0; c < g_timing.used; ++c) {
+    float tb = 0, tm = 0;
+    hipEvent_t* e = g_timing.ev + 3ull * c;
+    if (hipEventSynchronize(e[2]) != hipSuccess || hipEventElapsedTime(&tb, e[0], e[1]) != hipSuccess ||
+        hipEventElapsedTime(&tm, e[1], e[2]) != hipSuccess)
+      rc = CM_EHIP;
+    sum_b += tb;
+    sum_m += tm;
+  }
+  if (calls) *calls = g_timing.used;
+  if (co_rank_ms_mean) *co_rank_ms_mean = g_timing.used ? sum_b / g_timing.used : 0.0;
+  if (merge_ms_mean) *merge_ms_mean = g_timing.used ? sum_m / g_timing.used : 0.0;
+  for (uint64_t x = 0; x < 3ull * g_timing.capacity; ++x) (void)hipEventDestroy(g_timing.ev[x]);
+  delete[] g_timing.ev;
+  g_timing = Timing{};
+  return rc;
+}
+
+}  // extern "C"

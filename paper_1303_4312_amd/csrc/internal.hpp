@@ -1,0 +1,71 @@
+// Internal interface between the C ABI (api.cpp) and the kernel launchers
+// (launch.hip).  Launchers do no argument checking: the C ABI validates every
+// pointer, size and overlap before calling them.  Each returns CM_OK or
+// CM_EHIP (launch failure).
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace cm {
+
+struct TileCfg {
+  int nt;  // threads per workgroup
+  int e;   // outputs per thread; a block of Algorithm 2 is nt * e outputs
+};
+
+extern const TileCfg kCfgs[];
+extern const int kNumCfgs;
+// Smallest block over all configurations (sizes workspaces so that any
+// configuration fits).
+extern const uint64_t kMinTile;
+
+// Every kCoarse-th block boundary is searched by the coarse pass of the
+// two-level boundary scheme.
+constexpr uint32_t kCoarse = 64;
+
+enum Op : int { kOpMerge = 0, kOpSegmented = 1 };
+
+// How one call runs.
+struct Choice {
+  int cfg;        // index into kCfgs
+  int search;     // per-thread and one-level boundary search: 0 Alg. 1, 1 bisection
+  int partition;  // block-boundary pass: 0 one thread per boundary, 1 two-level
+};
+
+inline uint64_t tile_size(int cfg) { return (uint64_t)kCfgs[cfg].nt * (uint64_t)kCfgs[cfg].e; }
+inline uint64_t num_coarse(uint64_t nb) { return (nb - 1 + kCoarse - 1) / kCoarse + 1; }
+
+// Block-boundary co-ranks of one merge: bj[t] = A co-rank of min(t * tile, m + n)
+// for t < nb.  `coarse` holds num_coarse(nb) entries (two-level pass only).
+int launch_block_co_ranks(int kt, const Choice& ch, const void* A, uint64_t m, const void* B, uint64_t n,
+                          uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
+
+// Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj.
+int launch_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
+                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
+                        const uint64_t* bj, uint64_t tiles, hipStream_t st);
+
+// Segmented batch: offset check, boundary co-ranks (and segments), block merge.
+int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,
+                        uint64_t total_b, uint32_t* flag, hipStream_t st);
+int launch_seg_block_co_ranks(int kt, const Choice& ch, const void* A, const uint64_t* a_off, const void* B,
+                              const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile, uint64_t nb,
+                              uint64_t* bj, uint32_t* bs, const uint32_t* flag, hipStream_t st);
+int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av,
+                            const uint64_t* a_off, const void* B, const uint32_t* Bv, const uint64_t* b_off,
+                            uint32_t S, uint64_t N, void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs,
+                            uint64_t tiles, const uint32_t* flag, hipStream_t st);
+
+// Co-ranks of q arbitrary ranks.
+int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,
+                        const void* B, uint64_t n, uint64_t* j_out, hipStream_t st);
+
+// flag := 0, then flag |= (some X[x-1] > X[x]).
+int launch_check_sorted(int kt, const void* X, uint64_t len, uint32_t* flag, hipStream_t st);
+
+// Streaming copy of count16 16-byte vectors.
+int launch_copy16(const void* src, void* dst, uint64_t count16, hipStream_t st);
+
+}  // namespace cm

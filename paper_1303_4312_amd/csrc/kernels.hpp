@@ -1,0 +1,402 @@
+// Kernels of the co-rank stable merge for MI355X (gfx950).
+//
+// Single merge (Sections 2 and 3 of Siebert and Traeff, arXiv:1303.4312):
+//   1. block-boundary co-ranks: j_t = co_rank(i_t) for i_t = t * T, either
+//      one thread per boundary (k_block_co_rank) or in two levels
+//      (k_coarse_co_rank: a whole wave per 64th boundary with a 64-ary
+//      search; k_fine_co_rank: bisection between coarse neighbours).  Running
+//      the boundary searches as their own pass is the synchronised variant of
+//      Algorithm 2 described after Proposition 2: every boundary is searched
+//      once and read by the two blocks that share it (the kernel boundary is
+//      the synchronisation).
+//   2. k_merge_blocks: workgroup t stages A[j_t, j_t+1) and B[k_t, k_t+1)
+//      (exactly T elements together, Proposition 2) in LDS; thread q
+//      co-ranks its own start q * E inside those windows (the window-local
+//      co-rank plus the window offsets is the global co-rank, because the
+//      windows are cut at exact co-ranks), merges E outputs sequentially in
+//      registers, and the block leaves through an LDS transpose as
+//      lane-contiguous non-temporal stores.
+// Segmented batch: the same two steps over the concatenation of many
+// problems, partitioned as one merge under the order (segment, key).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "merge_device.hpp"
+
+namespace cm {
+
+// ---------------------------------------------------------------------------
+// kernels
+
+// j_out[t] = A co-rank of rank min(t * tile, m + n), t in [0, num_bounds).
+template <typename K>
+__global__ __launch_bounds__(256) void k_block_co_rank(const K* __restrict__ A, uint64_t m,
+                                                       const K* __restrict__ B, uint64_t n,
+                                                       uint64_t tile, uint64_t num_bounds,
+                                                       uint64_t* __restrict__ j_out, int search) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= num_bounds) return;
+  const uint64_t N = m + n;
+  const uint64_t i = std::min(t * tile, N);
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  j_out[t] = co_rank<K, uint64_t>(search, i, ra, m, rb, n);
+}
+
+// Two-level boundary co-ranks.  Coarse pass: one wave per coarse boundary
+// c * stride (stride = G blocks), 64-ary search over the whole diagonal.
+template <typename K>
+__global__ __launch_bounds__(256) void k_coarse_co_rank(const K* __restrict__ A, uint64_t m,
+                                                        const K* __restrict__ B, uint64_t n, uint64_t stride,
+                                                        uint64_t num_coarse, uint64_t* __restrict__ jc) {
+  const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // one wave each
+  if (c >= num_coarse) return;                                                 // whole waves leave
+  const uint64_t N = m + n;
+  const uint64_t i = std::min(c * stride, N);
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  const uint64_t j = co_rank_wave64<K>(i, ra, rb, i > n ? i - n : 0, std::min(i, m));
+  if ((threadIdx.x & 63) == 0) jc[c] = j;
+}
+
+// Fine pass: block boundary t lies between coarse boundaries c = t / G and
+// c + 1, so its co-ranks lie between theirs (co-ranks are monotone in the
+// rank); bisection runs only over that window.
+template <typename K>
+__global__ __launch_bounds__(256) void k_fine_co_rank(const K* __restrict__ A, uint64_t m,
+                                                      const K* __restrict__ B, uint64_t n, uint64_t tile,
+                                                      uint64_t num_bounds, uint32_t G,
+                                                      const uint64_t* __restrict__ jc,
+                                                      uint64_t* __restrict__ j_out) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= num_bounds) return;
+  const uint64_t N = m + n;
+  const uint64_t c = t / G;
+  if (t % G == 0) {
+    j_out[t] = jc[c];
+    return;
+  }
+  const uint64_t i = std::min(t * tile, N);
+  const uint64_t i0 = std::min(c * G * tile, N), i1 = std::min((c + 1) * G * tile, N);
+  const uint64_t j0 = jc[c], j1 = jc[c + 1];
+  const uint64_t k0 = i0 - j0, k1 = i1 - j1;
+  uint64_t lo = std::max(i > n ? i - n : 0, j0);
+  if (i > k1) lo = std::max(lo, i - k1);
+  uint64_t hi = std::min(std::min(i, m), j1);
+  hi = std::min(hi, i - std::min(k0, i));
+  if (hi < lo) hi = lo;  // only for unsorted input (monotonicity broken)
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  j_out[t] = co_rank_bisect_in<K>(i, ra, rb, lo, hi);
+}
+
+// Arbitrary ranks: j_out[r] = A co-rank of ranks[r], UINT64_MAX if out of range.
+template <typename K>
+__global__ __launch_bounds__(256) void k_co_rank_many(const uint64_t* __restrict__ ranks, uint64_t q,
+                                                      const K* __restrict__ A, uint64_t m,
+                                                      const K* __restrict__ B, uint64_t n,
+                                                      uint64_t* __restrict__ j_out, int search) {
+  const uint64_t r = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= q) return;
+  const uint64_t i = ranks[r];
+  if (i > m + n) {
+    j_out[r] = UINT64_MAX;
+    return;
+  }
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  j_out[r] = co_rank<K, uint64_t>(search, i, ra, m, rb, n);
+}
+
+// Per-thread sequential stable merge of E outputs starting at window
+// position (a, b), in registers.  Takes A while A has elements left and B is
+// exhausted or A's key <= B's key (the tie rule: A first).  ka / kb hold the
+// next key of each side; one LDS read refills the side just consumed.
+// out_src[e] is the window position (0..len) the output came from, used to
+// move payloads.  Outputs at or beyond `avail` are not produced.
+template <typename K, int E>
+__device__ __forceinline__ void merge_run(const K* s_key, int a_len, int len, int a, int b, int avail,
+                                          K (&out_key)[E], int (&out_src)[E]) {
+  const int b_len = len - a_len;
+  K ka = a < a_len ? s_key[a] : K{};
+  K kb = b < b_len ? s_key[a_len + b] : K{};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e < avail) {
+      const bool take_a = (a < a_len) && (b >= b_len || ka <= kb);
+      out_key[e] = take_a ? ka : kb;
+      out_src[e] = take_a ? a : a_len + b;
+      a += take_a ? 1 : 0;
+      b += take_a ? 0 : 1;
+      const bool more = take_a ? (a < a_len) : (b < b_len);
+      const int pos = take_a ? a : a_len + b;
+      const K next = more ? s_key[pos] : K{};
+      if (take_a)
+        ka = next;
+      else
+        kb = next;
+    }
+  }
+}
+
+template <typename K, bool VAL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+                                                     uint64_t m, const K* __restrict__ B,
+                                                     const uint32_t* __restrict__ Bv, uint64_t n,
+                                                     K* __restrict__ C, uint32_t* __restrict__ Cv,
+                                                     const uint64_t* __restrict__ bj, uint64_t num_tiles,
+                                                     int search) {
+  constexpr int T = NT * E;
+  __shared__ K s_key[T];
+  __shared__ uint32_t s_val[VAL ? T : 1];
+  const uint64_t N = m + n;
+  for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
+    const uint64_t i0 = t * (uint64_t)T;
+    const int len = (int)std::min((uint64_t)T, N - i0);
+    const uint64_t j0 = bj[t];
+    const uint64_t j1 = bj[t + 1];
+    const int a_len = window_a_len(j0, j1, len);
+    const int b_len = len - a_len;
+    load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, i0 - j0, a_len, len, s_key, s_val);
+    __syncthreads();
+
+    const int d = std::min((int)threadIdx.x * E, len);
+    const K* sA = s_key;
+    const K* sB = s_key + a_len;
+    auto ra = [=](int x) { return sA[x]; };
+    auto rb = [=](int x) { return sB[x]; };
+    const int a = co_rank<K, int>(search, d, ra, a_len, rb, b_len);
+    K ok[E];
+    int os[E];
+    const int avail = len - d;
+    merge_run<K, E>(s_key, a_len, len, a, d - a, avail, ok, os);
+    uint32_t ov[E];
+    if constexpr (VAL) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (e < avail) ov[e] = s_val[os[e]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e < avail) {
+        s_key[d + e] = ok[e];
+        if constexpr (VAL) s_val[d + e] = ov[e];
+      }
+    }
+    __syncthreads();
+    store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+    if (t + gridDim.x < num_tiles) __syncthreads();
+  }
+}
+
+// ---- segmented batch -------------------------------------------------------
+
+// One workgroup: flag = 0 if the offsets are consistent (start at 0,
+// nondecreasing, end at the host totals), else 1.  Every later kernel of the
+// call reads the flag and does nothing when it is set.
+__global__ __launch_bounds__(1024) void k_seg_validate(const uint64_t* __restrict__ a_off,
+                                                       const uint64_t* __restrict__ b_off, uint64_t S,
+                                                       uint64_t total_a, uint64_t total_b,
+                                                       uint32_t* __restrict__ flag) {
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  int my_bad = 0;
+  for (uint64_t s = threadIdx.x; s < S; s += blockDim.x) {
+    if (a_off[s] > a_off[s + 1] || b_off[s] > b_off[s + 1]) my_bad = 1;
+  }
+  if (threadIdx.x == 0) {
+    if (a_off[0] != 0 || b_off[0] != 0 || a_off[S] != total_a || b_off[S] != total_b) my_bad = 1;
+  }
+  if (my_bad) atomicOr(&bad, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = bad ? 1u : 0u;
+}
+
+// Largest s in [lo, hi] with a_off[s] + b_off[s] <= g (the segment holding
+// output position g; empty segments before it are skipped).
+__device__ __forceinline__ uint32_t seg_of(const uint64_t* __restrict__ a_off,
+                                           const uint64_t* __restrict__ b_off, uint32_t lo, uint32_t hi,
+                                           uint64_t g) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+    if (a_off[mid] + b_off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Block boundaries of the batch seen as one merge under (segment, key):
+// boundary i lies in segment s; its co-rank is a_off[s] plus the co-rank of
+// i - c_off[s] inside segment s (Algorithm 1 on that segment's arrays).
+template <typename K>
+__global__ __launch_bounds__(256) void k_seg_block_co_rank(const K* __restrict__ A,
+                                                           const uint64_t* __restrict__ a_off,
+                                                           const K* __restrict__ B,
+                                                           const uint64_t* __restrict__ b_off, uint32_t S,
+                                                           uint64_t N, uint64_t tile, uint64_t num_bounds,
+                                                           uint64_t* __restrict__ j_out,
+                                                           uint32_t* __restrict__ s_out,
+                                                           const uint32_t* __restrict__ flag, int search) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= num_bounds || *flag) return;
+  const uint64_t i = std::min(t * tile, N);
+  const uint32_t s = seg_of(a_off, b_off, 0, S - 1, i);
+  const uint64_t a0 = a_off[s], b0 = b_off[s];
+  const uint64_t ms = a_off[s + 1] - a0, ns = b_off[s + 1] - b0;
+  const uint64_t d = i - a0 - b0;
+  const K* As = A + a0;
+  const K* Bs = B + b0;
+  auto ra = [=](uint64_t x) { return As[x]; };
+  auto rb = [=](uint64_t x) { return Bs[x]; };
+  j_out[t] = a0 + co_rank<K, uint64_t>(search, d, ra, ms, rb, ns);
+  s_out[t] = s;
+}
+
+// Segmented merge run: like merge_run, but the run may cross segment ends.
+// s is the segment of the run's first output; a_end / b_end are the window
+// positions where segment s ends on each side (they may lie beyond the
+// window).  When both sides of the current segment are used up the run moves
+// on to the next non-empty segment.
+template <typename K, int E>
+__device__ __forceinline__ void merge_run_seg(const K* s_key, int a_len, int len, int a, int b, int avail,
+                                              const uint64_t* __restrict__ a_off,
+                                              const uint64_t* __restrict__ b_off, uint32_t S, uint32_t s,
+                                              uint64_t j0, uint64_t k0, K (&out_key)[E],
+                                              int (&out_src)[E]) {
+  const int b_len = len - a_len;
+  auto clamp_end = [](uint64_t end, uint64_t base) -> int {
+    return (int)std::min(end - base, (uint64_t)INT_MAX);
+  };
+  int a_end = clamp_end(a_off[s + 1], j0);
+  int b_end = clamp_end(b_off[s + 1], k0);
+  K ka = a < a_len ? s_key[a] : K{};
+  K kb = b < b_len ? s_key[a_len + b] : K{};
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e < avail) {
+      while (a == a_end && b == b_end && s + 1 < S) {
+        ++s;
+        a_end = clamp_end(a_off[s + 1], j0);
+        b_end = clamp_end(b_off[s + 1], k0);
+      }
+      const bool has_a = a < std::min(a_end, a_len);
+      const bool has_b = b < std::min(b_end, b_len);
+      const bool take_a = has_a && (!has_b || ka <= kb);
+      out_key[e] = take_a ? ka : kb;
+      out_src[e] = take_a ? a : a_len + b;
+      a += take_a ? 1 : 0;
+      b += take_a ? 0 : 1;
+      const bool more = take_a ? (a < a_len) : (b < b_len);
+      const int pos = take_a ? a : a_len + b;
+      const K next = more ? s_key[pos] : K{};
+      if (take_a)
+        ka = next;
+      else
+        kb = next;
+    }
+  }
+}
+
+template <typename K, bool VAL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_seg_merge_blocks(
+    const K* __restrict__ A, const uint32_t* __restrict__ Av, const uint64_t* __restrict__ a_off,
+    const K* __restrict__ B, const uint32_t* __restrict__ Bv, const uint64_t* __restrict__ b_off, uint32_t S,
+    uint64_t N, K* __restrict__ C, uint32_t* __restrict__ Cv, const uint64_t* __restrict__ bj,
+    const uint32_t* __restrict__ bs, uint64_t num_tiles, const uint32_t* __restrict__ flag, int search) {
+  constexpr int T = NT * E;
+  __shared__ K s_key[T];
+  __shared__ uint32_t s_val[VAL ? T : 1];
+  if (*flag) return;
+  for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
+    const uint64_t i0 = t * (uint64_t)T;
+    const int len = (int)std::min((uint64_t)T, N - i0);
+    const uint64_t j0 = bj[t];
+    const uint64_t k0 = i0 - j0;
+    const int a_len = window_a_len(j0, bj[t + 1], len);
+    const int b_len = len - a_len;
+    const uint64_t j1 = j0 + (uint64_t)a_len;
+    const uint32_t s_first = bs[t];
+    const uint32_t s_last = bs[t + 1];
+    load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
+    __syncthreads();
+
+    const int d = std::min((int)threadIdx.x * E, len);
+    const int avail = len - d;
+    K ok[E];
+    int os[E];
+    if (avail > 0) {
+      const uint64_t g = i0 + (uint64_t)d;
+      const uint32_t s = seg_of(a_off, b_off, s_first, s_last, g);
+      const uint64_t sa0 = a_off[s], sa1 = a_off[s + 1];
+      const uint64_t sb0 = b_off[s], sb1 = b_off[s + 1];
+      // the part of segment s inside this block, in window coordinates; its
+      // ends are exact co-rank cuts (block ends or segment ends)
+      // (clamped into the windows so that unsorted input cannot lead outside)
+      const int wa0 = (int)std::min(std::max(sa0, j0) - j0, (uint64_t)a_len);
+      const int wa1 = std::max(wa0, (int)std::min(std::max(std::min(sa1, j1), j0) - j0, (uint64_t)a_len));
+      const int wb0 = (int)std::min(std::max(sb0, k0) - k0, (uint64_t)b_len);
+      const int wb1 = std::max(wb0, (int)std::min(std::max(std::min(sb1, k0 + (uint64_t)b_len), k0) - k0,
+                                                  (uint64_t)b_len));
+      const int64_t dd64 = (int64_t)(g - j0 - k0) - wa0 - wb0;
+      const int dd = (int)std::min<int64_t>(std::max<int64_t>(dd64, 0), (wa1 - wa0) + (wb1 - wb0));
+      const K* sA = s_key + wa0;
+      const K* sB = s_key + a_len + wb0;
+      auto ra = [=](int x) { return sA[x]; };
+      auto rb = [=](int x) { return sB[x]; };
+      const int ja = co_rank<K, int>(search, dd, ra, wa1 - wa0, rb, wb1 - wb0);
+      merge_run_seg<K, E>(s_key, a_len, len, wa0 + ja, wb0 + (dd - ja), avail, a_off, b_off, S, s, j0, k0,
+                          ok, os);
+    }
+    uint32_t ov[E];
+    if constexpr (VAL) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (e < avail) ov[e] = s_val[os[e]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e < avail) {
+        s_key[d + e] = ok[e];
+        if constexpr (VAL) s_val[d + e] = ov[e];
+      }
+    }
+    __syncthreads();
+    store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+    if (t + gridDim.x < num_tiles) __syncthreads();
+  }
+}
+
+// flag |= 1 if some X[x-1] > X[x].
+template <typename K>
+__global__ __launch_bounds__(256) void k_check_sorted(const K* __restrict__ X, uint64_t len,
+                                                      uint32_t* __restrict__ flag) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; x < len; x += stride)
+    if (X[x - 1] > X[x]) bad = 1;
+  if (__any(bad) && (threadIdx.x % warpSize) == 0) atomicOr(flag, 1u);
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Plain streaming copy, 16 bytes per lane per step, grid-stride.
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                uint64_t count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + x), dst + x);
+}
+
+}  // namespace cm

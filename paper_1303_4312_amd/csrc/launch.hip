@@ -1,0 +1,152 @@
+// Kernel launchers: template dispatch over key type, payload mode and tile
+// configuration.  No argument checking happens here (see internal.hpp).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "corank_merge.h"
+#include "internal.hpp"
+#include "kernels.hpp"
+
+namespace cm {
+
+// Every configuration is instantiated for every key type and payload mode.
+// E is odd so that the strided LDS accesses of the transposes (stride E
+// words) fall on distinct banks.
+const TileCfg kCfgs[] = {{256, 7}, {256, 11}, {256, 15}, {128, 7}, {512, 7}, {256, 5}, {256, 9}, {512, 11}};
+const int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
+const uint64_t kMinTile = 128 * 7;
+
+static int launch_status() { return hipGetLastError() == hipSuccess ? CM_OK : CM_EHIP; }
+
+template <typename F>
+static int by_key(int kt, F&& f) {
+  switch (kt) {
+    case CM_KEY_U32: return f(uint32_t{});
+    case CM_KEY_U64: return f(uint64_t{});
+    default: return f(float{});
+  }
+}
+
+// Calls f(std::integral_constant<int, NT>, std::integral_constant<int, E>)
+// for configuration cfg; the cases must match kCfgs.
+template <typename F>
+static int by_cfg(int cfg, F&& f) {
+  switch (cfg) {
+    case 0: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 7>{});
+    case 1: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 11>{});
+    case 2: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 15>{});
+    case 3: return f(std::integral_constant<int, 128>{}, std::integral_constant<int, 7>{});
+    case 4: return f(std::integral_constant<int, 512>{}, std::integral_constant<int, 7>{});
+    case 5: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 5>{});
+    case 6: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 9>{});
+    case 7: return f(std::integral_constant<int, 512>{}, std::integral_constant<int, 11>{});
+    default: return CM_ECONFIG;
+  }
+}
+
+int launch_block_co_ranks(int kt, const Choice& ch, const void* A, uint64_t m, const void* B, uint64_t n,
+                          uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    const uint64_t blocks = (nb + 255) / 256;
+    if (ch.partition == 0) {
+      hipLaunchKernelGGL((k_block_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
+                         (const K*)B, n, tile, nb, bj, ch.search);
+      return launch_status();
+    }
+    const uint64_t nc = num_coarse(nb);
+    hipLaunchKernelGGL((k_coarse_co_rank<K>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st, (const K*)A, m,
+                       (const K*)B, n, tile * kCoarse, nc, coarse);
+    if (launch_status() != CM_OK) return CM_EHIP;
+    hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
+                       (const K*)B, n, tile, nb, kCoarse, (const uint64_t*)coarse, bj);
+    return launch_status();
+  });
+}
+
+int launch_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
+                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
+                        const uint64_t* bj, uint64_t tiles, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+      if (val)
+        hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st, (const K*)A,
+                           Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search);
+      else
+        hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
+                           (const K*)A, Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search);
+      return launch_status();
+    });
+  });
+}
+
+int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,
+                        uint64_t total_b, uint32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_seg_validate, dim3(1), dim3(1024), 0, st, a_off, b_off, S, total_a, total_b, flag);
+  return launch_status();
+}
+
+int launch_seg_block_co_ranks(int kt, const Choice& ch, const void* A, const uint64_t* a_off, const void* B,
+                              const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile, uint64_t nb,
+                              uint64_t* bj, uint32_t* bs, const uint32_t* flag, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                       (const K*)A, a_off, (const K*)B, b_off, S, N, tile, nb, bj, bs, flag, ch.search);
+    return launch_status();
+  });
+}
+
+int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av,
+                            const uint64_t* a_off, const void* B, const uint32_t* Bv, const uint64_t* b_off,
+                            uint32_t S, uint64_t N, void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs,
+                            uint64_t tiles, const uint32_t* flag, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+      if (val)
+        hipLaunchKernelGGL((k_seg_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
+                           (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
+                           ch.search);
+      else
+        hipLaunchKernelGGL((k_seg_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
+                           (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
+                           ch.search);
+      return launch_status();
+    });
+  });
+}
+
+int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,
+                        const void* B, uint64_t n, uint64_t* j_out, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    hipLaunchKernelGGL((k_co_rank_many<K>), dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, ranks, q,
+                       (const K*)A, m, (const K*)B, n, j_out, search);
+    return launch_status();
+  });
+}
+
+int launch_check_sorted(int kt, const void* X, uint64_t len, uint32_t* flag, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, flag, 0u);
+  if (launch_status() != CM_OK || len < 2) return launch_status();
+  const uint64_t blocks = std::min<uint64_t>((len + 255) / 256, 4096);
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    hipLaunchKernelGGL((k_check_sorted<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)X, len, flag);
+    return launch_status();
+  });
+}
+
+int launch_copy16(const void* src, void* dst, uint64_t count16, hipStream_t st) {
+  // one 16-byte vector per thread where the grid allows, grid-stride beyond
+  const uint64_t blocks = std::min<uint64_t>((count16 + 255) / 256, 1ull << 30);
+  hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, st, (const u32x4*)src, (u32x4*)dst, count16);
+  return launch_status();
+}
+
+}  // namespace cm

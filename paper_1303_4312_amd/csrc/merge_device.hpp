@@ -81,6 +81,45 @@ __device__ __forceinline__ I co_rank_bisect(I i, RA A, I m, RB B, I n) {
   return lo;
 }
 
+// Bisection restricted to [lo, hi], an interval already known to contain the
+// co-rank of i (lo >= max(0, i - n), hi <= min(i, m)).
+template <typename K, typename I, typename RA, typename RB>
+__device__ __forceinline__ I co_rank_bisect_in(I i, RA A, RB B, I lo, I hi) {
+  while (lo < hi) {
+    const I mid = lo + ((hi - lo + 1) >> 1);
+    if (A(mid - 1) <= B(i - mid))
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Co-rank of i by one whole wave (64 lanes): each round the lanes test 64
+// evenly spaced candidates of the current interval at once, a ballot finds
+// where the first Lemma condition turns false, and the interval shrinks
+// 64-fold, so an interval of L candidates takes ceil(log64(L + 1)) rounds of
+// one memory round trip each instead of ceil(log2(L + 1)).  Every lane
+// returns the result.  All 64 lanes of the wave must call it together.
+template <typename K, typename RA, typename RB>
+__device__ __forceinline__ uint64_t co_rank_wave64(uint64_t i, RA A, RB B, uint64_t lo, uint64_t hi) {
+  const int lane = (int)(threadIdx.x & 63);
+  while (lo < hi) {
+    const uint64_t L = hi - lo;
+    // lo + floor(L * (lane + 1) / 64), nondecreasing in lane, last = hi
+    const uint64_t cand = lo + (L >> 6) * (uint64_t)(lane + 1) + (((L & 63) * (uint64_t)(lane + 1)) >> 6);
+    const bool p = cand == lo || A(cand - 1) <= B(i - cand);
+    const uint64_t mask = __ballot(p);
+    const int t = __popcll(mask);  // the true lanes form a prefix
+    const uint64_t c_last_true = __shfl(cand, t > 0 ? t - 1 : 0);
+    const uint64_t c_first_false = __shfl(cand, t < 64 ? t : 63);
+    if (t == 64) return hi;
+    hi = c_first_false - 1;
+    lo = t > 0 ? c_last_true : lo;
+  }
+  return lo;
+}
+
 template <typename K, typename I, typename RA, typename RB>
 __device__ __forceinline__ I co_rank(int mode, I i, RA A, I m, RB B, I n) {
   return mode == kSearchBisect ? co_rank_bisect<K>(i, A, m, B, n)

@@ -163,3 +163,51 @@ def test_workloads_shapes():
     s = workloads.segmented(num_seg=64, max_side=1 << 10)
     assert s["a_off"][-1] == s["A"].size and s["b_off"][-1] == s["B"].size
     assert np.all(np.diff(s["a_off"].astype(np.int64)) >= 1)
+
+
+def test_tuning_table_host_logic(tmp_path):
+    """The tuning table is host state: set / get / save / load / clear."""
+    cm.tuning_clear()
+    assert cm.tuning_count() == 0
+    default = cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000)
+    assert default == (cm.get_config("uint32", True), cm.get_search(), cm.get_partition())
+    cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, 3, 0, 0)  # size class 10: N in [512, 1024)
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000) == (3, 0, 0)
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1024) == default
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1000) == (
+        cm.get_config("uint32", False), cm.get_search(), cm.get_partition())
+    cm.tuning_set(cm.OP_SEGMENTED, "uint64", False, 30, 5, 1, 0)
+    path = tmp_path / "tune.txt"
+    cm.tuning_save(str(path))
+    assert len([l for l in path.read_text().splitlines() if not l.startswith("#")]) == 2
+    cm.tuning_clear()
+    assert cm.tuning_count() == 0
+    cm.tuning_load(str(path))
+    assert cm.tuning_count() == 2
+    assert cm.tuning_get(cm.OP_SEGMENTED, "uint64", False, 1 << 29) == (5, 1, 0)
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 0 1 10 99 0 0 1.0\n")
+    with pytest.raises(cm.CMError):
+        cm.tuning_load(str(bad))
+    assert cm.tuning_count() == 2
+    with pytest.raises(cm.CMError):
+        cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, cm.config_count(), 0, 0)
+    cm.tuning_clear()
+
+
+def test_plan_and_tuner_argument_errors():
+    lib = cm.load()
+    P = ctypes.c_void_p
+    h = ctypes.c_void_p()
+    assert lib.cm_plan_create_merge(9, None, None, 0, None, None, 0, None, None, None, 0,
+                                    ctypes.byref(h)) == EDTYPE
+    assert h.value is None
+    assert lib.cm_plan_create_merge(0, None, None, 5, None, None, 0, P(0x1000), None, P(0x2000),
+                                    1 << 20, ctypes.byref(h)) == EINVAL
+    assert lib.cm_plan_launch(None, None) == EINVAL
+    assert lib.cm_plan_destroy(None) == EINVAL
+    best = (ctypes.c_int * 3)()
+    assert lib.cm_autotune_merge(0, P(0x1000), None, 4, P(0x2000), None, 4, P(0x3000), None,
+                                 P(0x4000), 1 << 20, 0, None, best) == EINVAL
+    assert lib.cm_autotune_merge(0, None, None, 0, None, None, 0, None, None, None, 0, 3, None,
+                                 best) == EINVAL

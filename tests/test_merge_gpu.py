@@ -22,7 +22,8 @@ DTYPES = [np.uint32, np.uint64, np.float32]
 @pytest.fixture(autouse=True)
 def _default_settings():
     yield
-    cm.set_search(0)
+    cm.set_search(1)
+    cm.set_partition(1)
     for kt in ("uint32", "uint64", "float32"):
         for v in (False, True):
             cm.set_config(kt, v, 2)
@@ -65,9 +66,10 @@ def test_figure_example(figure):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("search", [0, 1])
-def test_all_configs_pairs_and_keys(dtype, search):
+@pytest.mark.parametrize("search,partition", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_all_configs_pairs_and_keys(dtype, search, partition):
     cm.set_search(search)
+    cm.set_partition(partition)
     rng = np.random.default_rng(100 + search)
     kt = np.dtype(dtype).name
     for c in range(cm.config_count()):
@@ -81,6 +83,25 @@ def test_all_configs_pairs_and_keys(dtype, search):
             B = random_sorted(rng, n, dtype, hi)
             check_pairs(A, B)
             check_keys(A, B)
+
+
+@pytest.mark.parametrize("partition", [0, 1])
+def test_two_level_partition_edges(partition):
+    """Block counts around multiples of the coarse stride (64 blocks), with
+    the co-rank windows of the fine pass both wide and degenerate."""
+    cm.set_partition(partition)
+    nt, e = cm.config_info(cm.get_config("uint32", True))
+    T = nt * e
+    rng = np.random.default_rng(21)
+    for N in (64 * T, 64 * T + 1, 64 * T - 1, 65 * T, 128 * T + T // 2, 200 * T + 7):
+        m = int(rng.integers(0, N + 1))
+        for hi in (3, 1 << 30):
+            A = random_sorted(rng, m, np.uint32, hi)
+            B = random_sorted(rng, N - m, np.uint32, hi)
+            check_pairs(A, B)
+    d = workloads.structured("a_below_b", 70 * T, 3 * T + 5)
+    check_pairs(d["A"], d["B"], d["Av"], d["Bv"])
+    check_pairs(d["B"], d["A"], d["Bv"], d["Av"])
 
 
 @pytest.mark.parametrize("dtype", DTYPES)

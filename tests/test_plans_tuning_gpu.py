@@ -1,0 +1,106 @@
+"""GPU: graph plans and the autotuner give the same bits as eager calls and
+as the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1303_4312_amd as cm
+from paper_1303_4312_amd import workloads
+from tests.gpu_util import same_bits, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _clean_tuning():
+    cm.tuning_clear()
+    yield
+    cm.tuning_clear()
+
+
+def test_plan_merge_replays_match_eager():
+    import torch
+    d = workloads.zipf(m=3_000_000, n=1_000_003)
+    A, Av, B, Bv = (to_dev(d[k]) for k in ("A", "Av", "B", "Bv"))
+    Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+    plan = cm.plan_merge(A, B, Av, Bv)
+    for rep in range(4):
+        plan.C.zero_()
+        plan.C_val.zero_()
+        # eager work between replays
+        Ceg, Cveg = cm.stable_merge_pairs(A, Av, B, Bv)
+        torch.cuda.synchronize()
+        C, Cv = plan.launch()
+        torch.cuda.synchronize()
+        assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve), f"replay {rep}"
+        assert same_bits(to_host(Ceg), Ce)
+    # a replay reads the inputs as they are at replay time
+    d2 = workloads.zipf(seed=99, m=3_000_000, n=1_000_003)
+    A.copy_(to_dev(d2["A"]))
+    B.copy_(to_dev(d2["B"]))
+    C, Cv = plan.launch()
+    Ce2, Cve2 = oracle.stable_merge(d2["A"], d2["B"], d["Av"], d["Bv"])
+    assert same_bits(to_host(C), Ce2) and same_bits(to_host(Cv), Cve2)
+    plan.close()
+
+
+def test_plan_keys_only_and_segmented():
+    import torch
+    d = workloads.segmented(seed=4, num_seg=3000, max_side=1 << 10, min_side=0)
+    A, B = to_dev(d["A"]), to_dev(d["B"])
+    a_off, b_off = to_dev(d["a_off"]), to_dev(d["b_off"])
+    Av, Bv = to_dev(d["Av"]), to_dev(d["Bv"])
+    Ce, Cve = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
+                                            d["Bv"])
+    plan = cm.plan_segmented(A, a_off, B, b_off, Av, Bv)
+    for _ in range(3):
+        plan.C.zero_()
+        eager = cm.stable_merge_segmented(A, a_off, B, b_off)  # eager work between replays
+        torch.cuda.synchronize()
+        C, Cv = plan.launch()
+        assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+        assert same_bits(to_host(eager), Ce)
+    plan.close()
+    k = workloads.dup16(m=200_000, n=300_000)
+    pk = cm.plan_merge(to_dev(k["A"]), to_dev(k["B"]))
+    for _ in range(3):
+        pk.C.zero_()
+        assert same_bits(to_host(pk.launch()), oracle.stable_merge(k["A"], k["B"]))
+    pk.close()
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64])
+def test_autotune_merge_records_and_stays_exact(dtype):
+    d = workloads.dup16(m=1 << 20, n=700_001, high=1 << 12)
+    A = d["A"].astype(dtype)
+    B = d["B"].astype(dtype)
+    best = cm.autotune_merge(to_dev(A), to_dev(B), to_dev(d["Av"]), to_dev(d["Bv"]), reps=2)
+    assert 0 <= best[0] < cm.config_count() and best[1] in (0, 1) and best[2] in (0, 1)
+    N = A.size + B.size
+    assert cm.tuning_get(cm.OP_MERGE, np.dtype(dtype).name, True, N) == best
+    assert cm.tuning_count() == 1
+    C, Cv = cm.stable_merge_pairs(to_dev(A), to_dev(d["Av"]), to_dev(B), to_dev(d["Bv"]))
+    Ce, Cve = oracle.stable_merge(A, B, d["Av"], d["Bv"])
+    assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+
+
+def test_autotune_segmented():
+    d = workloads.segmented(seed=8, num_seg=2000, max_side=1 << 11)
+    best = cm.autotune_segmented(to_dev(d["A"]), to_dev(d["a_off"]), to_dev(d["B"]),
+                                 to_dev(d["b_off"]), to_dev(d["Av"]), to_dev(d["Bv"]), reps=2)
+    assert best[2] == 0
+    C, Cv = cm.stable_merge_segmented(to_dev(d["A"]), to_dev(d["a_off"]), to_dev(d["B"]),
+                                      to_dev(d["b_off"]), to_dev(d["Av"]), to_dev(d["Bv"]))
+    Ce, Cve = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
+                                            d["Bv"])
+    assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+
+
+def test_per_merge_launch_form_matches_batch():
+    d = workloads.segmented(seed=9, num_seg=300, max_side=1 << 12, min_side=0)
+    args = (to_dev(d["A"]), d["a_off"], to_dev(d["B"]), d["b_off"], to_dev(d["Av"]),
+            to_dev(d["Bv"]))
+    C, Cv = cm.stable_merge_segmented_each(*args)
+    Ce, Cve = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
+                                            d["Bv"])
+    assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)

@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(autouse=True)
 def _default_settings():
     yield
-    cm.set_search(0)
+    cm.set_search(1)
+    cm.set_partition(1)
     for kt in ("uint32", "uint64", "float32"):
         for v in (False, True):
             cm.set_config(kt, v, 2)
