@@ -132,6 +132,54 @@ int cm_stable_merge_pairs(int key_type,
                           hipStream_t stream);
 
 /*
+ * Batch of separately allocated merges (each one instance of the problem of
+ * Section 2), run in one pass of Algorithm 2: every merge is cut into
+ * blocks of the batch's block size, blocks never span two merges, and one
+ * kernel merges all blocks of all merges.  Used to serve many requests
+ * with one launch.
+ *
+ * cm_merge_desc describes merge r: A (m keys), B (n keys), C (m + n keys)
+ * are device key arrays; A_val, B_val, C_val uint32 device payload arrays
+ * (all three NULL when with_payload is 0).  first_block is filled by
+ * cm_batch_prepare.
+ *
+ * cm_batch_prepare(key_type, with_payload, descs, count, &total_blocks):
+ *   host-only; fills descs[r].first_block (blocks of the merges before r)
+ *   for the block size the batch call will use, and the total block count.
+ * cm_batch_workspace_size(total_blocks, count): workspace bytes (one uint64
+ *   co-rank per block end of every merge), rounded up to 256.
+ * cm_stable_merge_batch(key_type, with_payload, descs_host, descs_dev,
+ *   count, total_blocks, workspace, workspace_bytes, stream):
+ *   descs_host is the prepared host array (used to check the arguments);
+ *   descs_dev is a byte-identical copy of it in device memory, read by the
+ *   kernels (the caller uploads it and keeps it alive until the stream has
+ *   run the call).  No output may overlap an input or another output of the
+ *   batch.  count = 0 is a no-op.
+ * Errors: CM_EDTYPE, CM_EINVAL (null pointer with nonzero length, counts
+ *   or first_block that do not match cm_batch_prepare), CM_EALIAS,
+ *   CM_ENOSPC, CM_EHIP.
+ */
+typedef struct cm_merge_desc {
+    const void *A;
+    const uint32_t *A_val;
+    uint64_t m;
+    const void *B;
+    const uint32_t *B_val;
+    uint64_t n;
+    void *C;
+    uint32_t *C_val;
+    uint64_t first_block;
+} cm_merge_desc;
+
+int cm_batch_prepare(int key_type, int with_payload, cm_merge_desc *descs, uint32_t count,
+                     uint64_t *total_blocks);
+size_t cm_batch_workspace_size(uint64_t total_blocks, uint32_t count);
+int cm_stable_merge_batch(int key_type, int with_payload,
+                          const cm_merge_desc *descs_host, const cm_merge_desc *descs_dev,
+                          uint32_t count, uint64_t total_blocks,
+                          void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Workspace bytes for a segmented merge of num_seg segments with total_a
  * and total_b elements: a status word, and per block boundary one uint64
  * co-rank and one uint32 segment index (sized for the smallest block of any
@@ -244,7 +292,8 @@ int cm_autotune_segmented(int key_type,
 
 /*
  * Tuning table.  Entries map (op, key_type, with_payload, size class) to
- * {config, search, partition}; op 0 = single merge, 1 = segmented batch;
+ * {config, search, partition}; op 0 = single merge, 1 = segmented batch,
+ * 2 = batch of separate merges (size class of its total output count);
  * the size class of a merge of N outputs is the bit length of N (0..64).
  * A merge call uses the entry of its size class when there is one, else
  * the settings of cm_set_config / cm_set_search / cm_set_partition.

@@ -27,7 +27,7 @@ __all__ = [
     "copy", "timing_start", "timing_stop", "get_search", "set_partition", "get_partition",
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
     "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
-    "OP_MERGE", "OP_SEGMENTED",
+    "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "stable_merge_batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -36,7 +36,7 @@ library_path = os.path.join(_HERE, "libcorank_merge.so")
 # C enum cm_key_type
 KEY_U32, KEY_U64, KEY_F32 = 0, 1, 2
 # operations of the tuning table
-OP_MERGE, OP_SEGMENTED = 0, 1
+OP_MERGE, OP_SEGMENTED, OP_BATCH = 0, 1, 2
 KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
 
 EXPORTS = [
@@ -49,6 +49,7 @@ EXPORTS = [
     "cm_autotune_merge", "cm_autotune_segmented", "cm_tuning_set", "cm_tuning_get",
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
+    "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
 ]
 
 _lib = None
@@ -111,6 +112,10 @@ def load():
         "cm_plan_create_segmented": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64, c_u64,
                                              vp, vp, vp, c_size, ctypes.POINTER(vp)]),
         "cm_plan_launch": (c_int, [vp, vp]),
+        "cm_batch_prepare": (c_int, [c_int, c_int, vp, ctypes.c_uint32, ctypes.POINTER(c_u64)]),
+        "cm_batch_workspace_size": (c_size, [c_u64, ctypes.c_uint32]),
+        "cm_stable_merge_batch": (c_int, [c_int, c_int, vp, vp, ctypes.c_uint32, c_u64, vp, c_size,
+                                          vp]),
         "cm_plan_destroy": (c_int, [vp]),
         "cm_timing_start": (c_int, [ctypes.c_uint32]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
@@ -572,3 +577,46 @@ def plan_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=Non
                                            _ptr(ws), wsb, ctypes.byref(h)),
            "cm_plan_create_segmented")
     return Plan(h, A.device, (A, A_val, a_off, B, B_val, b_off, ws), C, C_val)
+
+
+# layout of cm_merge_desc (nine 64-bit fields)
+_DESC_FIELDS = ("A", "A_val", "m", "B", "B_val", "n", "C", "C_val", "first_block")
+
+
+def stable_merge_batch(merges, with_payload=None, stream=None):
+    """Merge several separately allocated pairs of sorted device arrays in one
+    launch (cm_stable_merge_batch).  merges: list of (A, B) or
+    (A, A_val, B, B_val) tuples, all of one key dtype.  Returns a list of C
+    or (C, C_val) in the same order."""
+    import numpy as np
+    torch = _torch()
+    if not merges:
+        return []
+    if with_payload is None:
+        with_payload = len(merges[0]) == 4
+    prepared = []
+    for item in merges:
+        if with_payload:
+            A, A_val, B, B_val = item
+        else:
+            (A, B), A_val, B_val = item, None, None
+        prepared.append(_pair_args(A, B, A_val, B_val, None, None))
+    kt = prepared[0][0]
+    device = prepared[0][4].device
+    if any(p[0] != kt for p in prepared):
+        raise TypeError("all merges of a batch must have the same key dtype")
+    descs = np.zeros(len(prepared), dtype=np.dtype([(f, np.uint64) for f in _DESC_FIELDS]))
+    for r, (_, _, m, n, A, Av, B, Bv, C, Cv) in enumerate(prepared):
+        descs[r] = (A.data_ptr() if m else 0, Av.data_ptr() if with_payload and m else 0, m,
+                    B.data_ptr() if n else 0, Bv.data_ptr() if with_payload and n else 0, n,
+                    C.data_ptr() if m + n else 0, Cv.data_ptr() if with_payload and m + n else 0, 0)
+    total = ctypes.c_uint64()
+    _check(load().cm_batch_prepare(kt, int(with_payload), descs.ctypes.data_as(ctypes.c_void_p),
+                                   len(descs), ctypes.byref(total)), "cm_batch_prepare")
+    descs_dev = torch.from_numpy(descs.view(np.uint8)).to(device)
+    ws, wsb = _workspace(load().cm_batch_workspace_size(total.value, len(descs)), device, None)
+    _check(load().cm_stable_merge_batch(kt, int(with_payload),
+                                        descs.ctypes.data_as(ctypes.c_void_p), _ptr(descs_dev),
+                                        len(descs), total.value, _ptr(ws), wsb,
+                                        _stream(stream, device)), "cm_stable_merge_batch")
+    return [(p[8], p[9]) if with_payload else p[8] for p in prepared]

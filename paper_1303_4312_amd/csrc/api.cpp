@@ -12,6 +12,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <vector>
 
 #include "corank_merge.h"
 #include "internal.hpp"
@@ -201,6 +202,34 @@ int seg_impl(int kt, const void* A, const uint32_t* Av, const uint64_t* a_off, u
   return rc;
 }
 
+// Block size a batch of separate merges uses (from its total output count).
+Choice batch_choice(int kt, bool val, const cm_merge_desc* d, uint32_t count) {
+  uint64_t N = 0;
+  for (uint32_t r = 0; r < count; ++r) N += d[r].m + d[r].n;
+  Choice ch = resolve(kOpBatch, kt, val, N);
+  ch.partition = 0;  // per-merge boundaries: one-level pass
+  return ch;
+}
+
+// Do any of the byte ranges in `outs` overlap each other or any range in
+// `ins`?  Sorting keeps this O((outs + ins) log outs) for large batches.
+bool spans_overlap(std::vector<Span>& outs, const std::vector<Span>& ins) {
+  outs.erase(std::remove_if(outs.begin(), outs.end(), [](const Span& s) { return !s.p || !s.bytes; }),
+             outs.end());
+  std::sort(outs.begin(), outs.end(), [](const Span& a, const Span& b) { return a.p < b.p; });
+  for (size_t x = 1; x < outs.size(); ++x)
+    if (overlap(outs[x - 1].p, outs[x - 1].bytes, outs[x].p, outs[x].bytes)) return true;
+  for (const Span& in : ins) {
+    if (!in.p || !in.bytes) continue;
+    // first output starting at or after the input's end cannot overlap; check the one before
+    auto it = std::lower_bound(outs.begin(), outs.end(), in,
+                               [](const Span& o, const Span& v) { return (uintptr_t)o.p < (uintptr_t)v.p; });
+    if (it != outs.end() && overlap(it->p, it->bytes, in.p, in.bytes)) return true;
+    if (it != outs.begin() && overlap((it - 1)->p, (it - 1)->bytes, in.p, in.bytes)) return true;
+  }
+  return false;
+}
+
 // Mean milliseconds of `reps` calls of f() on stream st (after one warm call).
 template <typename F>
 int time_calls(F&& f, int reps, hipStream_t st, double* ms) {
@@ -326,6 +355,75 @@ int cm_stable_merge_segmented_each(int key_type, const void* A, const uint32_t* 
                     workspace_bytes, stream);
   }
   g_timing.on = timing_was_on;
+  return rc;
+}
+
+int cm_batch_prepare(int key_type, int with_payload, cm_merge_desc* descs, uint32_t count,
+                     uint64_t* total_blocks) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if ((count && !descs) || !total_blocks) return CM_EINVAL;
+  const Choice ch = batch_choice(key_type, with_payload != 0, descs, count);
+  const uint64_t T = tile_size(ch.cfg);
+  uint64_t blocks = 0;
+  for (uint32_t r = 0; r < count; ++r) {
+    if (descs[r].m + descs[r].n < descs[r].m) return CM_EINVAL;
+    descs[r].first_block = blocks;
+    blocks += (descs[r].m + descs[r].n + T - 1) / T;
+  }
+  *total_blocks = blocks;
+  return CM_OK;
+}
+
+size_t cm_batch_workspace_size(uint64_t total_blocks, uint32_t count) {
+  return round256((total_blocks + count) * sizeof(uint64_t));
+}
+
+int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* descs_host,
+                          const cm_merge_desc* descs_dev, uint32_t count, uint64_t total_blocks, void* workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (count == 0) return total_blocks == 0 ? CM_OK : CM_EINVAL;
+  if (!descs_host || !descs_dev) return CM_EINVAL;
+  const bool val = with_payload != 0;
+  const size_t ks = key_bytes(key_type);
+  const Choice ch = batch_choice(key_type, val, descs_host, count);
+  const uint64_t T = tile_size(ch.cfg);
+  std::vector<Span> outs, ins;
+  outs.reserve(2 * (size_t)count + 1);
+  ins.reserve(4 * (size_t)count + 1);
+  uint64_t blocks = 0;
+  for (uint32_t r = 0; r < count; ++r) {
+    const cm_merge_desc& q = descs_host[r];
+    if (q.m + q.n < q.m) return CM_EINVAL;
+    const uint64_t N = q.m + q.n;
+    if ((q.m && !q.A) || (q.n && !q.B) || (N && !q.C)) return CM_EINVAL;
+    if (val && ((q.m && !q.A_val) || (q.n && !q.B_val) || (N && !q.C_val))) return CM_EINVAL;
+    if (!val && (q.A_val || q.B_val || q.C_val)) return CM_EINVAL;
+    if (q.first_block != blocks) return CM_EINVAL;
+    blocks += (N + T - 1) / T;
+    outs.push_back({q.C, N * ks});
+    if (val) outs.push_back({q.C_val, N * 4});
+    ins.push_back({q.A, q.m * ks});
+    ins.push_back({q.B, q.n * ks});
+    if (val) {
+      ins.push_back({q.A_val, q.m * 4});
+      ins.push_back({q.B_val, q.n * 4});
+    }
+  }
+  if (blocks != total_blocks || blocks >= (1ull << 31)) return CM_EINVAL;
+  const size_t need = cm_batch_workspace_size(total_blocks, count);
+  if (!workspace || workspace_bytes < need) return CM_ENOSPC;
+  outs.push_back({workspace, need});
+  ins.push_back({descs_dev, (uint64_t)count * sizeof(cm_merge_desc)});
+  if (spans_overlap(outs, ins)) return CM_EALIAS;
+  if (total_blocks == 0) return CM_OK;
+  uint64_t* bj = (uint64_t*)workspace;
+  timing_mark(0, stream);
+  int rc = launch_batch_co_ranks(key_type, ch, descs_dev, count, T, total_blocks + count, bj, stream);
+  if (rc != CM_OK) return rc;
+  timing_mark(1, stream);
+  rc = launch_batch_merge_blocks(key_type, val, ch, descs_dev, count, bj, total_blocks, stream);
+  timing_mark(2, stream);
   return rc;
 }
 
@@ -473,7 +571,7 @@ int cm_tuning_clear(void) {
 
 int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int config_id, int search_mode,
                   int partition_mode) {
-  if (op != kOpMerge && op != kOpSegmented) return CM_EINVAL;
+  if (op != kOpMerge && op != kOpSegmented && op != kOpBatch) return CM_EINVAL;
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
   if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) ||
@@ -524,7 +622,7 @@ int cm_tuning_load(const char* path) {
     int op, kt, val, sc, cfg, search, part;
     double ms;
     if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
-        (op != kOpMerge && op != kOpSegmented) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
+        (op != kOpMerge && op != kOpSegmented && op != kOpBatch) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
         sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || (part != 0 && part != 1)) {
       rc = CM_EINVAL;
       break;

@@ -25,7 +25,7 @@ extern const uint64_t kMinTile;
 // two-level boundary scheme.
 constexpr uint32_t kCoarse = 64;
 
-enum Op : int { kOpMerge = 0, kOpSegmented = 1 };
+enum Op : int { kOpMerge = 0, kOpSegmented = 1, kOpBatch = 2 };
 
 // How one call runs.
 struct Choice {
@@ -57,6 +57,13 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
                             const uint64_t* a_off, const void* B, const uint32_t* Bv, const uint64_t* b_off,
                             uint32_t S, uint64_t N, void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs,
                             uint64_t tiles, const uint32_t* flag, hipStream_t st);
+
+// Batch of separately allocated merges; d is the device copy of the
+// descriptors (layout of cm_merge_desc), nb = total blocks + count.
+int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
+                          uint64_t* bj, hipStream_t st);
+int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
+                              const uint64_t* bj, uint64_t tiles, hipStream_t st);
 
 // Co-ranks of q arbitrary ranks.
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,

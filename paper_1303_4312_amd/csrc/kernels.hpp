@@ -144,6 +144,48 @@ __device__ __forceinline__ void merge_run(const K* s_key, int a_len, int len, in
   }
 }
 
+// One block of Algorithm 2: outputs C[i0, i0 + len) from the windows
+// A[j0, j1) and B[i0 - j0, ...) (j0, j1 = co-ranks of the block's ends).
+// Called by every thread of the workgroup; ends with the block stored and
+// LDS free for reuse after a barrier.
+template <typename K, bool VAL, int NT, int E>
+__device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+                                            const K* __restrict__ B, const uint32_t* __restrict__ Bv,
+                                            K* __restrict__ C, uint32_t* __restrict__ Cv, uint64_t i0, int len,
+                                            uint64_t j0, uint64_t j1, int search, K* s_key, uint32_t* s_val) {
+  const int a_len = window_a_len(j0, j1, len);
+  const int b_len = len - a_len;
+  load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, i0 - j0, a_len, len, s_key, s_val);
+  __syncthreads();
+
+  const int d = std::min((int)threadIdx.x * E, len);
+  const K* sA = s_key;
+  const K* sB = s_key + a_len;
+  auto ra = [=](int x) { return sA[x]; };
+  auto rb = [=](int x) { return sB[x]; };
+  const int a = co_rank<K, int>(search, d, ra, a_len, rb, b_len);
+  K ok[E];
+  int os[E];
+  const int avail = len - d;
+  merge_run<K, E>(s_key, a_len, len, a, d - a, avail, ok, os);
+  uint32_t ov[E];
+  if constexpr (VAL) {
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (e < avail) ov[e] = s_val[os[e]];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (e < avail) {
+      s_key[d + e] = ok[e];
+      if constexpr (VAL) s_val[d + e] = ov[e];
+    }
+  }
+  __syncthreads();
+  store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+}
+
 template <typename K, bool VAL, int NT, int E>
 __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const uint32_t* __restrict__ Av,
                                                      uint64_t m, const K* __restrict__ B,
@@ -158,40 +200,79 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, co
   for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
-    const uint64_t j0 = bj[t];
-    const uint64_t j1 = bj[t + 1];
-    const int a_len = window_a_len(j0, j1, len);
-    const int b_len = len - a_len;
-    load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, i0 - j0, a_len, len, s_key, s_val);
-    __syncthreads();
-
-    const int d = std::min((int)threadIdx.x * E, len);
-    const K* sA = s_key;
-    const K* sB = s_key + a_len;
-    auto ra = [=](int x) { return sA[x]; };
-    auto rb = [=](int x) { return sB[x]; };
-    const int a = co_rank<K, int>(search, d, ra, a_len, rb, b_len);
-    K ok[E];
-    int os[E];
-    const int avail = len - d;
-    merge_run<K, E>(s_key, a_len, len, a, d - a, avail, ok, os);
-    uint32_t ov[E];
-    if constexpr (VAL) {
-#pragma unroll
-      for (int e = 0; e < E; ++e)
-        if (e < avail) ov[e] = s_val[os[e]];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (e < avail) {
-        s_key[d + e] = ok[e];
-        if constexpr (VAL) s_val[d + e] = ov[e];
-      }
-    }
-    __syncthreads();
-    store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+    merge_block<K, VAL, NT, E>(A, Av, B, Bv, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
     if (t + gridDim.x < num_tiles) __syncthreads();
+  }
+}
+
+// ---- batch of separately allocated merges ----------------------------------
+
+// One merge of a batch.  Same layout as the C ABI's cm_merge_desc.
+struct MergeDesc {
+  const void* A;
+  const uint32_t* A_val;
+  uint64_t m;
+  const void* B;
+  const uint32_t* B_val;
+  uint64_t n;
+  void* C;
+  uint32_t* C_val;
+  uint64_t first_block;  // blocks of merges before this one
+};
+
+// Largest r in [0, count) with first_block[r] + r * extra <= x (merges with
+// no blocks share first_block with their successor and are skipped).
+__device__ __forceinline__ uint32_t desc_of(const MergeDesc* __restrict__ d, uint32_t count, uint64_t x,
+                                            uint64_t extra) {
+  uint32_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+    if (d[mid].first_block + mid * extra <= x)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// Boundary co-ranks of every merge of the batch: merge r owns boundary slots
+// [first_block[r] + r, first_block[r+1] + r + 1), one per block end of r.
+template <typename K>
+__global__ __launch_bounds__(256) void k_batch_co_rank(const MergeDesc* __restrict__ d, uint32_t count,
+                                                       uint64_t tile, uint64_t num_bounds,
+                                                       uint64_t* __restrict__ bj, int search) {
+  const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= num_bounds) return;
+  const uint32_t r = desc_of(d, count, b, 1);
+  const MergeDesc q = d[r];
+  const uint64_t N = q.m + q.n;
+  const uint64_t t = b - q.first_block - r;
+  const uint64_t i = std::min(t * tile, N);
+  const K* A = (const K*)q.A;
+  const K* B = (const K*)q.B;
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  bj[b] = co_rank<K, uint64_t>(search, i, ra, q.m, rb, q.n);
+}
+
+// Block g of the batch is block g - first_block[r] of merge r.
+template <typename K, bool VAL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __restrict__ d, uint32_t count,
+                                                           const uint64_t* __restrict__ bj, uint64_t num_tiles,
+                                                           int search) {
+  constexpr int T = NT * E;
+  __shared__ K s_key[T];
+  __shared__ uint32_t s_val[VAL ? T : 1];
+  for (uint64_t g = blockIdx.x; g < num_tiles; g += gridDim.x) {
+    const uint32_t r = desc_of(d, count, g, 0);
+    const MergeDesc q = d[r];
+    const uint64_t t = g - q.first_block;
+    const uint64_t i0 = t * (uint64_t)T;
+    const int len = (int)std::min((uint64_t)T, q.m + q.n - i0);
+    const uint64_t slot = q.first_block + r + t;
+    merge_block<K, VAL, NT, E>((const K*)q.A, q.A_val, (const K*)q.B, q.B_val, (K*)q.C, q.C_val, i0, len, bj[slot],
+                               bj[slot + 1], search, s_key, s_val);
+    if (g + gridDim.x < num_tiles) __syncthreads();
   }
 }
 

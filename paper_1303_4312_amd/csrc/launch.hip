@@ -2,6 +2,8 @@
 // configuration.  No argument checking happens here (see internal.hpp).
 #include <hip/hip_runtime.h>
 
+#include <stddef.h>
+
 #include <type_traits>
 
 #include "corank_merge.h"
@@ -116,6 +118,36 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
         hipLaunchKernelGGL((k_seg_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
                            (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
                            ch.search);
+      return launch_status();
+    });
+  });
+}
+
+static_assert(sizeof(MergeDesc) == sizeof(cm_merge_desc), "descriptor layouts differ");
+static_assert(offsetof(MergeDesc, first_block) == offsetof(cm_merge_desc, first_block), "descriptor layouts differ");
+
+int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
+                          uint64_t* bj, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    hipLaunchKernelGGL((k_batch_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                       (const MergeDesc*)d, count, tile, nb, bj, ch.search);
+    return launch_status();
+  });
+}
+
+int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
+                              const uint64_t* bj, uint64_t tiles, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+      if (val)
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
+                           (const MergeDesc*)d, count, bj, tiles, ch.search);
+      else
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
+                           (const MergeDesc*)d, count, bj, tiles, ch.search);
       return launch_status();
     });
   });

@@ -1,0 +1,310 @@
+"""Continuous-batching merge server for one GPU.
+
+Clients submit merge requests (two sorted device arrays, optionally with
+payloads); each returns a concurrent.futures.Future.  One scheduler thread:
+
+- admits pending requests in arrival order while their HBM footprint fits
+  the remaining budget and a slot is free (a request larger than the whole
+  budget is refused with BudgetError; a cancelled request is dropped);
+- launches the admitted requests as one batch (one cm_stable_merge_batch
+  call: every merge cut into equal blocks, all blocks in one kernel) as soon
+  as fewer than `max_inflight` batches are on the GPU, so requests that
+  arrive while a batch runs go into the next one and the two overlap on the
+  device (the executor alternates streams);
+- completes a batch when its event has fired: results go to the futures,
+  the budget is released, latency (arrival to completion seen) is recorded.
+
+The executor is pluggable: GpuExecutor runs batches through the library;
+tests drive the same scheduler with a CPU executor.  An executor that
+raises in launch() or reports a failed batch makes every future of that
+batch fail and releases its budget.
+"""
+from __future__ import annotations
+
+import collections
+import concurrent.futures
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Optional
+
+
+class BudgetError(RuntimeError):
+    """The request can never fit the server's HBM budget."""
+
+
+@dataclass
+class MergeRequest:
+    rid: int
+    A: Any
+    B: Any
+    A_val: Any
+    B_val: Any
+    nbytes: int
+    outputs: int
+    arrival: float
+    future: concurrent.futures.Future = field(default_factory=concurrent.futures.Future)
+    launched: float = 0.0
+    done: float = 0.0
+
+
+class Budget:
+    """Bytes of HBM the server may hold for admitted requests."""
+
+    def __init__(self, total: int):
+        if total <= 0:
+            raise ValueError("budget must be positive")
+        self.total = total
+        self.used = 0
+        self.peak = 0
+
+    def try_reserve(self, n: int) -> bool:
+        if self.used + n > self.total:
+            return False
+        self.used += n
+        self.peak = max(self.peak, self.used)
+        return True
+
+    def release(self, n: int):
+        if n > self.used:
+            raise RuntimeError("budget released more than reserved")
+        self.used -= n
+
+
+class GpuExecutor:
+    """Runs a batch with one cm_stable_merge_batch call; completion is a HIP
+    event query.  Streams alternate so consecutive batches can overlap."""
+
+    def __init__(self, device="cuda:0", num_streams: int = 2):
+        import torch
+        self.torch = torch
+        self.device = torch.device(device)
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(num_streams)]
+        self._next = 0
+
+    @staticmethod
+    def footprint(A, B, A_val, B_val) -> int:
+        """Inputs plus outputs of one request, in bytes."""
+        n = A.numel() + B.numel()
+        per = A.element_size() + (4 if A_val is not None else 0)
+        return 2 * n * per
+
+    def launch(self, batch):
+        from . import stable_merge_batch
+        torch = self.torch
+        s = self.streams[self._next]
+        self._next = (self._next + 1) % len(self.streams)
+        with torch.cuda.stream(s):
+            # the inputs were produced on the caller's stream
+            s.wait_stream(torch.cuda.current_stream(self.device))
+            merges = [(r.A, r.A_val, r.B, r.B_val) if r.A_val is not None else (r.A, r.B)
+                      for r in batch]
+            with_val = batch[0].A_val is not None
+            if any((r.A_val is not None) != with_val for r in batch):
+                # mixed payload modes: one launch per mode
+                outs = [None] * len(batch)
+                for mode in (False, True):
+                    idx = [i for i, r in enumerate(batch) if (r.A_val is not None) == mode]
+                    res = stable_merge_batch([merges[i] for i in idx], with_payload=mode,
+                                             stream=s) if idx else []
+                    for i, o in zip(idx, res):
+                        outs[i] = o
+            else:
+                outs = stable_merge_batch(merges, with_payload=with_val, stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return (ev, outs)
+
+    def done(self, handle) -> bool:
+        return handle[0].query()
+
+    def results(self, handle):
+        return handle[1]
+
+
+class Server:
+    def __init__(self, executor, budget_bytes: int, max_slots: int = 256, max_batch: int = 64,
+                 max_inflight: int = 2, clock: Callable[[], float] = time.perf_counter,
+                 idle_wait: float = 50e-6):
+        self.executor = executor
+        self.budget = Budget(budget_bytes)
+        self.max_slots = max_slots
+        self.max_batch = max_batch
+        self.max_inflight = max_inflight
+        self.clock = clock
+        self.idle_wait = idle_wait
+        self._lock = threading.Lock()
+        self._wake = threading.Condition(self._lock)
+        self._incoming: collections.deque = collections.deque()
+        self._pending: collections.deque = collections.deque()
+        self._admitted: list = []
+        self._inflight: list = []
+        self._stop = False
+        self._thread: Optional[threading.Thread] = None
+        self._rid = 0
+        self.latencies: list = []
+        self.completed_outputs = 0
+        self.failed = 0
+        self.rejected = 0
+        self.batches = 0
+        self.batch_sizes: list = []
+        self.max_concurrent_batches = 0
+        self.first_arrival = None
+        self.last_done = None
+
+    # -- client side
+    def submit(self, A, B, A_val=None, B_val=None, arrival: Optional[float] = None):
+        nbytes = self.executor.footprint(A, B, A_val, B_val)
+        outputs = len(A) + len(B) if not hasattr(A, "numel") else A.numel() + B.numel()
+        with self._lock:
+            req = MergeRequest(self._rid, A, B, A_val, B_val, nbytes, outputs,
+                               self.clock() if arrival is None else arrival)
+            self._rid += 1
+            if self.first_arrival is None:
+                self.first_arrival = req.arrival
+            self._incoming.append(req)
+            self._wake.notify()
+        return req.future
+
+    def start(self):
+        if self._thread is not None:
+            raise RuntimeError("server already started")
+        self._stop = False
+        self._thread = threading.Thread(target=self._loop, name="merge-scheduler", daemon=True)
+        self._thread.start()
+        return self
+
+    def stop(self, timeout: float = 60.0):
+        """Finish every request already submitted, then stop the thread."""
+        with self._lock:
+            self._stop = True
+            self._wake.notify()
+        if self._thread is not None:
+            self._thread.join(timeout)
+            if self._thread.is_alive():
+                raise RuntimeError("scheduler did not drain in time")
+            self._thread = None
+
+    def __enter__(self):
+        return self.start()
+
+    def __exit__(self, *exc):
+        self.stop()
+
+    # -- scheduler
+    def _busy(self):
+        return bool(self._incoming or self._pending or self._admitted or self._inflight)
+
+    def _admit(self):
+        while self._pending and len(self._admitted) + self._inflight_count() < self.max_slots:
+            req = self._pending[0]
+            if req.future.cancelled():
+                self._pending.popleft()
+                continue
+            if req.nbytes > self.budget.total:
+                self._pending.popleft()
+                self.rejected += 1
+                req.future.set_exception(BudgetError(
+                    f"request {req.rid} needs {req.nbytes} bytes; budget is {self.budget.total}"))
+                continue
+            if not self.budget.try_reserve(req.nbytes):
+                break  # wait for memory (arrival order is kept)
+            req.future.set_running_or_notify_cancel()
+            self._admitted.append(self._pending.popleft())
+
+    def _inflight_count(self):
+        return sum(len(b) for _, b in self._inflight)
+
+    def _launch(self):
+        while self._admitted and len(self._inflight) < self.max_inflight:
+            batch = self._admitted[:self.max_batch]
+            del self._admitted[:len(batch)]
+            now = self.clock()
+            for r in batch:
+                r.launched = now
+            try:
+                handle = self.executor.launch(batch)
+            except Exception as exc:  # a failed launch fails its requests only
+                self._fail(batch, exc)
+                continue
+            self._inflight.append((handle, batch))
+            self.batches += 1
+            self.batch_sizes.append(len(batch))
+            self.max_concurrent_batches = max(self.max_concurrent_batches, len(self._inflight))
+
+    def _fail(self, batch, exc):
+        for r in batch:
+            self.budget.release(r.nbytes)
+            self.failed += 1
+            if not r.future.done():
+                r.future.set_exception(exc)
+
+    def _complete(self):
+        progressed = False
+        still = []
+        for handle, batch in self._inflight:
+            try:
+                finished = self.executor.done(handle)
+            except Exception as exc:
+                self._fail(batch, exc)
+                progressed = True
+                continue
+            if not finished:
+                still.append((handle, batch))
+                continue
+            progressed = True
+            try:
+                outs = self.executor.results(handle)
+            except Exception as exc:
+                self._fail(batch, exc)
+                continue
+            now = self.clock()
+            for r, out in zip(batch, outs):
+                r.done = now
+                self.budget.release(r.nbytes)
+                self.latencies.append(now - r.arrival)
+                self.completed_outputs += r.outputs
+                r.future.set_result(out)
+            self.last_done = now
+        self._inflight = still
+        return progressed
+
+    def _loop(self):
+        while True:
+            with self._lock:
+                while self._incoming:
+                    self._pending.append(self._incoming.popleft())
+                if self._stop and not self._busy():
+                    return
+                self._admit()
+                self._launch()
+            progressed = self._complete()
+            if not progressed:
+                with self._lock:
+                    if not self._incoming and not (self._stop and not self._busy()):
+                        self._wake.wait(self.idle_wait if (self._inflight or self._admitted)
+                                        else 0.01)
+
+    # -- reporting
+    def stats(self) -> dict:
+        lat = sorted(self.latencies)
+
+        def pct(p):
+            if not lat:
+                return None
+            k = min(len(lat) - 1, max(0, int(round(p / 100.0 * (len(lat) - 1)))))
+            return lat[k]
+
+        span = (self.last_done - self.first_arrival) if lat else None
+        return {
+            "completed": len(lat),
+            "failed": self.failed,
+            "rejected": self.rejected,
+            "batches": self.batches,
+            "mean_batch": (sum(self.batch_sizes) / len(self.batch_sizes)) if self.batch_sizes else 0,
+            "max_concurrent_batches": self.max_concurrent_batches,
+            "p50_s": pct(50),
+            "p99_s": pct(99),
+            "keys_per_s": (self.completed_outputs / span) if span else None,
+            "budget_peak_bytes": self.budget.peak,
+        }

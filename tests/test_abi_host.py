@@ -211,3 +211,52 @@ def test_plan_and_tuner_argument_errors():
                                  P(0x4000), 1 << 20, 0, None, best) == EINVAL
     assert lib.cm_autotune_merge(0, None, None, 0, None, None, 0, None, None, None, 0, 3, None,
                                  best) == EINVAL
+
+
+def test_batch_prepare_and_argument_errors():
+    """cm_batch_prepare is host-only; bad batch arguments fail before launch."""
+    import numpy as np
+    lib = cm.load()
+    fields = ("A", "A_val", "m", "B", "B_val", "n", "C", "C_val", "first_block")
+    descs = np.zeros(3, dtype=np.dtype([(f, np.uint64) for f in fields]))
+    sizes = [(5000, 7000), (0, 0), (1, 1 << 20)]
+    base = 1 << 32
+    for r, (m, n) in enumerate(sizes):
+        descs[r] = (base + r * (1 << 28), 0, m, base + r * (1 << 28) + (1 << 26), 0, n,
+                    base + r * (1 << 28) + (1 << 27), 0, 0)
+    total = ctypes.c_uint64()
+    assert lib.cm_batch_prepare(0, 0, descs.ctypes.data_as(ctypes.c_void_p), 3,
+                                ctypes.byref(total)) == OK
+    cfg, _, _ = cm.tuning_get(cm.OP_BATCH, "uint32", False, sum(m + n for m, n in sizes))
+    nt, e = cm.config_info(cfg)
+    T = nt * e
+    expect = [-(-(m + n) // T) for m, n in sizes]
+    assert descs["first_block"].tolist() == [0, expect[0], expect[0] + expect[1]]
+    assert total.value == sum(expect)
+    P = ctypes.c_void_p
+    need = lib.cm_batch_workspace_size(total.value, 3)
+    dp = descs.ctypes.data_as(ctypes.c_void_p)
+    # first_block that does not match the block size
+    bad = descs.copy()
+    bad["first_block"][2] += 1
+    assert lib.cm_stable_merge_batch(0, 0, bad.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
+                                     total.value, P(0x2000), need, None) == EINVAL
+    # workspace too small
+    assert lib.cm_stable_merge_batch(0, 0, dp, P(0x1000), 3, total.value, P(0x2000), need - 8,
+                                     None) == ENOSPC
+    # output of merge 2 overlapping the input of merge 0
+    alias = descs.copy()
+    alias["C"][2] = alias["A"][0] + 16
+    assert lib.cm_stable_merge_batch(0, 0, alias.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
+                                     total.value, P(0x2000), need, None) == EALIAS
+    # two outputs overlapping each other
+    alias = descs.copy()
+    alias["C"][2] = alias["C"][0] + 64
+    assert lib.cm_stable_merge_batch(0, 0, alias.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
+                                     total.value, P(0x2000), need, None) == EALIAS
+    # payload pointer given in a keys-only batch
+    pay = descs.copy()
+    pay["A_val"][0] = 0x5000
+    assert lib.cm_stable_merge_batch(0, 0, pay.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
+                                     total.value, P(0x2000), need, None) == EINVAL
+    assert lib.cm_stable_merge_batch(0, 0, None, None, 0, 0, None, 0, None) == OK
