@@ -176,6 +176,75 @@ def batched_leg(steps, warmup):
     }
 
 
+def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=5000):
+    """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
+    payload, uniform keys), staged in HBM before they arrive, admitted against
+    a 32 GiB budget and batched on the fly.  First a closed loop (all
+    requests at once) gives the saturation rate; then Poisson arrivals at
+    fractions of it.  Latency is arrival to completion seen by the server."""
+    import numpy as np
+    import torch
+    from paper_1303_4312_amd import serve, workloads as w
+
+    log(f"serving: generating {pool_size} requests")
+    dev = torch.device("cuda:0")
+    pool = []
+    for r in range(pool_size):
+        d = w.request(seed + r)
+        pool.append(tuple(torch.from_numpy(d[k]).to(dev) for k in ("A", "B", "Av", "Bv")))
+    sizes = [p[0].numel() + p[1].numel() for p in pool]
+    budget = 32 << 30
+
+    def run(arrivals):
+        ex = serve.GpuExecutor(dev)
+        srv = serve.Server(ex, budget_bytes=budget, max_batch=64, max_inflight=2)
+        torch.cuda.synchronize()
+        with srv:
+            t0 = time.perf_counter()
+            futs = []
+            for k, at in enumerate(arrivals):
+                target = t0 + at
+                while True:  # wait for the arrival time, yielding the GIL
+                    dt = target - time.perf_counter()
+                    if dt <= 0:
+                        break
+                    time.sleep(dt if dt > 2e-3 else 0)
+                futs.append(srv.submit(*pool[k % pool_size], arrival=target))
+            for f in futs:
+                f.result(timeout=120)
+        return srv.stats()
+
+    sys.setswitchinterval(1e-4)  # let the scheduler thread in often
+    warm = run([0.0] * per_point)  # warm-up: first launches, allocator caches
+    sat = run([0.0] * per_point)
+    outputs = sum(sizes[k % pool_size] for k in range(per_point))
+    sat_rate = per_point * sat["keys_per_s"] / outputs
+    rng = np.random.default_rng(seed)
+    points = []
+    for frac in fractions:
+        lam = frac * sat_rate
+        gaps = rng.exponential(1.0 / lam, per_point)
+        st = run(list(np.cumsum(gaps) - gaps[0]))
+        points.append({"rate_per_s": lam, "fraction_of_saturation": frac,
+                       "keys_per_s": st["keys_per_s"], "p50_ms": st["p50_s"] * 1e3,
+                       "p99_ms": st["p99_s"] * 1e3, "mean_batch": st["mean_batch"],
+                       "max_concurrent_batches": st["max_concurrent_batches"]})
+        log(f"serving: rate {lam:.0f}/s p50 {st['p50_s'] * 1e3:.3f} ms "
+            f"p99 {st['p99_s'] * 1e3:.3f} ms")
+    del warm
+    return {
+        "workload": ("requests with sides log-uniform in [2^10,2^24], uint32 keys uniform, "
+                     "uint32 payloads, device-resident, 32 GiB budget"),
+        "pool": pool_size,
+        "requests_per_point": per_point,
+        "mean_outputs_per_request": float(np.mean(sizes)),
+        "saturation": {"requests_per_s": sat_rate, "keys_per_s": sat["keys_per_s"],
+                       "p50_ms": sat["p50_s"] * 1e3, "p99_ms": sat["p99_s"] * 1e3,
+                       "mean_batch": sat["mean_batch"]},
+        "points": points,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +254,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--serving", action="store_true",
+                    help="also run the serving leg (Poisson arrivals, p50/p99)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one cm_copy of 1 GiB (for counter calibration)")
     args = ap.parse_args()
@@ -294,6 +365,10 @@ def main():
         del A, Av, B, Bv, C, Cv, ws
         torch.cuda.empty_cache()
         result["batched"] = batched_leg(steps=max(3, min(args.steps, 20)), warmup=2)
+
+    if args.serving:
+        torch.cuda.empty_cache()
+        result["serving"] = serving_leg()
 
     print(json.dumps(result), flush=True)
 

@@ -27,7 +27,8 @@ __all__ = [
     "copy", "timing_start", "timing_stop", "get_search", "set_partition", "get_partition",
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
     "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
-    "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "stable_merge_batch",
+    "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "stable_merge_batch", "batch_descriptors",
+    "launch_batch",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -594,6 +595,46 @@ def stable_merge_batch(merges, with_payload=None, stream=None):
         return []
     if with_payload is None:
         with_payload = len(merges[0]) == 4
+    device = merges[0][0].device
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    with torch.cuda.stream(s):  # outputs, descriptor upload and workspace all on s
+        return _merge_batch_on(merges, with_payload, s)
+
+
+def batch_descriptors(count):
+    """Zeroed host array laid out as cm_merge_desc[count]."""
+    import numpy as np
+    return np.zeros(count, dtype=np.dtype([(f, np.uint64) for f in _DESC_FIELDS]))
+
+
+def launch_batch(key_dtype, with_payload, descs, device, stream):
+    """cm_batch_prepare + upload + cm_stable_merge_batch for descriptors the
+    caller filled (pointers and sizes; first_block is set here).  Returns the
+    device buffers the call uses; they must stay alive until the stream has
+    run it (torch's allocator keeps them ordered on `stream`)."""
+    import numpy as np
+    torch = _torch()
+    kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
+    total = ctypes.c_uint64()
+    _check(load().cm_batch_prepare(kt, int(with_payload), descs.ctypes.data_as(ctypes.c_void_p),
+                                   len(descs), ctypes.byref(total)), "cm_batch_prepare")
+    with torch.cuda.stream(stream):
+        # pinned staging so the upload is stream-ordered and does not block the host
+        descs_dev = torch.from_numpy(descs.view(np.uint8)).pin_memory().to(device,
+                                                                            non_blocking=True)
+        ws, wsb = _workspace(load().cm_batch_workspace_size(total.value, len(descs)), device,
+                             None)
+    _check(load().cm_stable_merge_batch(kt, int(with_payload),
+                                        descs.ctypes.data_as(ctypes.c_void_p), _ptr(descs_dev),
+                                        len(descs), total.value, _ptr(ws), wsb,
+                                        ctypes.c_void_p(stream.cuda_stream)),
+           "cm_stable_merge_batch")
+    return descs_dev, ws
+
+
+def _merge_batch_on(merges, with_payload, stream):
+    import numpy as np
+    torch = _torch()
     prepared = []
     for item in merges:
         if with_payload:
@@ -605,18 +646,10 @@ def stable_merge_batch(merges, with_payload=None, stream=None):
     device = prepared[0][4].device
     if any(p[0] != kt for p in prepared):
         raise TypeError("all merges of a batch must have the same key dtype")
-    descs = np.zeros(len(prepared), dtype=np.dtype([(f, np.uint64) for f in _DESC_FIELDS]))
+    descs = batch_descriptors(len(prepared))
     for r, (_, _, m, n, A, Av, B, Bv, C, Cv) in enumerate(prepared):
         descs[r] = (A.data_ptr() if m else 0, Av.data_ptr() if with_payload and m else 0, m,
                     B.data_ptr() if n else 0, Bv.data_ptr() if with_payload and n else 0, n,
                     C.data_ptr() if m + n else 0, Cv.data_ptr() if with_payload and m + n else 0, 0)
-    total = ctypes.c_uint64()
-    _check(load().cm_batch_prepare(kt, int(with_payload), descs.ctypes.data_as(ctypes.c_void_p),
-                                   len(descs), ctypes.byref(total)), "cm_batch_prepare")
-    descs_dev = torch.from_numpy(descs.view(np.uint8)).to(device)
-    ws, wsb = _workspace(load().cm_batch_workspace_size(total.value, len(descs)), device, None)
-    _check(load().cm_stable_merge_batch(kt, int(with_payload),
-                                        descs.ctypes.data_as(ctypes.c_void_p), _ptr(descs_dev),
-                                        len(descs), total.value, _ptr(ws), wsb,
-                                        _stream(stream, device)), "cm_stable_merge_batch")
+    launch_batch(prepared[0][4].dtype, with_payload, descs, device, stream)
     return [(p[8], p[9]) if with_payload else p[8] for p in prepared]

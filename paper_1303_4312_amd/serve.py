@@ -43,6 +43,7 @@ class MergeRequest:
     nbytes: int
     outputs: int
     arrival: float
+    ready: Any = None  # executor token: the inputs are ready (e.g. a GPU event)
     future: concurrent.futures.Future = field(default_factory=concurrent.futures.Future)
     launched: float = 0.0
     done: float = 0.0
@@ -73,7 +74,10 @@ class Budget:
 
 class GpuExecutor:
     """Runs a batch with one cm_stable_merge_batch call; completion is a HIP
-    event query.  Streams alternate so consecutive batches can overlap."""
+    event query.  Streams alternate so consecutive batches can overlap.
+    Each batch's outputs are views into one key slab and one payload slab
+    (two allocations per batch), and its descriptors are filled with
+    vectorised numpy, so the host cost per request stays small."""
 
     def __init__(self, device="cuda:0", num_streams: int = 2):
         import torch
@@ -82,38 +86,73 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(num_streams)]
         self._next = 0
 
-    @staticmethod
-    def footprint(A, B, A_val, B_val) -> int:
-        """Inputs plus outputs of one request, in bytes."""
+    def footprint(self, A, B, A_val, B_val) -> int:
+        """Inputs plus outputs of one request, in bytes (after checking it once)."""
+        torch = self.torch
+        for t in (A, B) + ((A_val, B_val) if A_val is not None else ()):
+            if not isinstance(t, torch.Tensor) or t.device != self.device or t.dim() != 1 \
+                    or not t.is_contiguous():
+                raise ValueError("request arrays must be contiguous 1-D tensors on the "
+                                 "server's device")
+        if B.dtype != A.dtype or A.dtype not in (torch.uint32, torch.uint64, torch.float32):
+            raise TypeError("keys must be uint32, uint64 or float32, the same for A and B")
+        if (A_val is None) != (B_val is None):
+            raise ValueError("give payloads for both inputs or neither")
+        if A_val is not None and (A_val.dtype != torch.uint32 or B_val.dtype != torch.uint32
+                                  or A_val.numel() != A.numel() or B_val.numel() != B.numel()):
+            raise ValueError("payloads must be uint32 and as long as their keys")
         n = A.numel() + B.numel()
         per = A.element_size() + (4 if A_val is not None else 0)
         return 2 * n * per
 
+    def ready_token(self):
+        """Event on the submitting thread's current stream: the request's
+        inputs are ready once it has fired (called in submit)."""
+        ev = self.torch.cuda.Event()
+        ev.record(self.torch.cuda.current_stream(self.device))
+        return ev
+
     def launch(self, batch):
-        from . import stable_merge_batch
+        import numpy as np
+        from . import batch_descriptors, launch_batch
         torch = self.torch
         s = self.streams[self._next]
         self._next = (self._next + 1) % len(self.streams)
+        groups = {}
+        for i, r in enumerate(batch):  # one launch per (key dtype, payload mode)
+            groups.setdefault((r.A.dtype, r.A_val is not None), []).append(i)
+        outs = [None] * len(batch)
+        keep = []
         with torch.cuda.stream(s):
-            # the inputs were produced on the caller's stream
-            s.wait_stream(torch.cuda.current_stream(self.device))
-            merges = [(r.A, r.A_val, r.B, r.B_val) if r.A_val is not None else (r.A, r.B)
-                      for r in batch]
-            with_val = batch[0].A_val is not None
-            if any((r.A_val is not None) != with_val for r in batch):
-                # mixed payload modes: one launch per mode
-                outs = [None] * len(batch)
-                for mode in (False, True):
-                    idx = [i for i, r in enumerate(batch) if (r.A_val is not None) == mode]
-                    res = stable_merge_batch([merges[i] for i in idx], with_payload=mode,
-                                             stream=s) if idx else []
-                    for i, o in zip(idx, res):
-                        outs[i] = o
-            else:
-                outs = stable_merge_batch(merges, with_payload=with_val, stream=s)
+            for r in batch:  # inputs were produced on the submitters' streams
+                if r.ready is not None:
+                    s.wait_event(r.ready)
+            for (dtype, with_val), idx in groups.items():
+                reqs = [batch[i] for i in idx]
+                m = np.array([r.A.numel() for r in reqs], dtype=np.uint64)
+                n = np.array([r.B.numel() for r in reqs], dtype=np.uint64)
+                N = m + n
+                off = np.concatenate([[0], np.cumsum(N)]).astype(np.uint64)
+                keys = torch.empty(int(off[-1]), dtype=dtype, device=self.device)
+                vals = torch.empty(int(off[-1]), dtype=torch.uint32, device=self.device) \
+                    if with_val else None
+                ks = keys.element_size()
+                d = batch_descriptors(len(reqs))
+                d["A"] = [r.A.data_ptr() for r in reqs]
+                d["B"] = [r.B.data_ptr() for r in reqs]
+                d["m"], d["n"] = m, n
+                d["C"] = np.where(N > 0, keys.data_ptr() + off[:-1] * ks, 0)
+                if with_val:
+                    d["A_val"] = [r.A_val.data_ptr() for r in reqs]
+                    d["B_val"] = [r.B_val.data_ptr() for r in reqs]
+                    d["C_val"] = np.where(N > 0, vals.data_ptr() + off[:-1] * 4, 0)
+                keep.append(launch_batch(dtype, with_val, d, self.device, s))
+                for k, i in enumerate(idx):
+                    a, b = int(off[k]), int(off[k + 1])
+                    outs[i] = (keys[a:b], vals[a:b]) if with_val else keys[a:b]
             ev = torch.cuda.Event()
             ev.record(s)
-        return (ev, outs)
+        return (ev, outs, keep)
 
     def done(self, handle) -> bool:
         return handle[0].query()
@@ -156,9 +195,10 @@ class Server:
     def submit(self, A, B, A_val=None, B_val=None, arrival: Optional[float] = None):
         nbytes = self.executor.footprint(A, B, A_val, B_val)
         outputs = len(A) + len(B) if not hasattr(A, "numel") else A.numel() + B.numel()
+        token = self.executor.ready_token() if hasattr(self.executor, "ready_token") else None
         with self._lock:
             req = MergeRequest(self._rid, A, B, A_val, B_val, nbytes, outputs,
-                               self.clock() if arrival is None else arrival)
+                               self.clock() if arrival is None else arrival, token)
             self._rid += 1
             if self.first_arrival is None:
                 self.first_arrival = req.arrival

@@ -72,8 +72,9 @@ def test_serving_result_alone_equals_in_the_mix():
     for A, B, Av, Bv in dev_reqs:
         C, Cv = cm.stable_merge_pairs(A, Av, B, Bv)
         alone.append((to_host(C), to_host(Cv)))
-    budget = sum(serve.GpuExecutor.footprint(*r) for r in dev_reqs) // 3  # forces queueing
-    srv = serve.Server(serve.GpuExecutor(), budget_bytes=budget, max_batch=16, max_inflight=2)
+    ex = serve.GpuExecutor()
+    budget = sum(ex.footprint(*r) for r in dev_reqs) // 3  # forces queueing
+    srv = serve.Server(ex, budget_bytes=budget, max_batch=16, max_inflight=2)
     torch.cuda.synchronize()
     with srv:
         futs = []
@@ -97,7 +98,8 @@ def test_serving_result_alone_equals_in_the_mix():
 def test_serving_refuses_request_over_budget():
     d = workloads.request(5, lo=1 << 12, hi=1 << 12)
     r = (to_dev(d["A"]), to_dev(d["B"]), to_dev(d["Av"]), to_dev(d["Bv"]))
-    srv = serve.Server(serve.GpuExecutor(), budget_bytes=serve.GpuExecutor.footprint(*r) - 1)
+    ex = serve.GpuExecutor()
+    srv = serve.Server(ex, budget_bytes=ex.footprint(*r) - 1)
     with srv:
         with pytest.raises(serve.BudgetError):
             srv.submit(*r).result(timeout=30)
