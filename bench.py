@@ -333,7 +333,7 @@ def main():
             "m": m, "n": n, "key": key_dtype, "payload": "uint32",
             "block": {"threads": nt, "items_per_thread": e},
             "search": ["algorithm1", "bisection"][search],
-            "boundary_pass": ["one_level", "two_level"][partition],
+            "boundary_pass": ["one_level", "two_level_64", "two_level_16", "stream"][partition],
         },
         "roofline": {
             "bound": "hbm",

@@ -244,9 +244,16 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     of Lemma 1.
  *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
  *     0 = one GPU thread per boundary over the whole diagonal; 1 = two
- *     levels (default): every 64th boundary by a whole wave with a 64-ary
- *     search, then the others by bisection between their two coarse
- *     neighbours.  Both give the same co-ranks.
+ *     levels: every coarse boundary by a whole wave with a 64-ary search,
+ *     then the others by bisection between their two coarse neighbours;
+ *     2 (default) = two levels with 16 lanes (a 16-ary search) per coarse
+ *     boundary.  All give the same co-ranks.
+ *   cm_set_coarse_stride: blocks between coarse boundaries of the two-level
+ *     pass (default 64; at least 16).
+ *   cm_set_block_order: 1 (default) hands each of the chip's 8 XCDs a
+ *     contiguous run of blocks (workgroups reach the XCDs round-robin), so
+ *     neighbouring blocks, which share the cache lines at their window
+ *     edges, run under one L2; 0 = blocks in workgroup order.
  *   The cm_get_* calls return the current setting.
  *   (Settings are process-wide and not thread-safe against concurrent
  *   merges; set them before launching.)
@@ -259,6 +266,8 @@ int cm_set_search(int search_mode);
 int cm_get_search(void);
 int cm_set_partition(int partition_mode);
 int cm_get_partition(void);
+int cm_set_coarse_stride(uint32_t blocks);
+int cm_set_block_order(int xcd_contiguous);
 
 /*
  * Autotuner (self-written; not part of the method).  Times every tile

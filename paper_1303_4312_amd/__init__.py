@@ -28,7 +28,7 @@ __all__ = [
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
     "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "stable_merge_batch", "batch_descriptors",
-    "launch_batch",
+    "launch_batch", "set_coarse_stride", "set_block_order",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +51,7 @@ EXPORTS = [
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
+    "cm_set_coarse_stride", "cm_set_block_order",
 ]
 
 _lib = None
@@ -94,6 +95,8 @@ def load():
         "cm_set_search": (c_int, [c_int]),
         "cm_get_search": (c_int, []),
         "cm_set_partition": (c_int, [c_int]),
+        "cm_set_coarse_stride": (c_int, [ctypes.c_uint32]),
+        "cm_set_block_order": (c_int, [c_int]),
         "cm_get_partition": (c_int, []),
         "cm_stable_merge_segmented_each": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
                                                    c_u64, vp, vp, vp, c_size, vp]),
@@ -414,12 +417,23 @@ def get_search() -> int:
 
 
 def set_partition(mode: int):
-    """Block-boundary pass: 0 = one thread per boundary, 1 = two-level."""
+    """Block-boundary pass: 0 = one thread per boundary, 1 = two-level with a
+    64-lane coarse search, 2 = two-level with a 16-lane coarse search."""
     _check(load().cm_set_partition(mode), "cm_set_partition")
 
 
 def get_partition() -> int:
     return load().cm_get_partition()
+
+
+def set_coarse_stride(blocks: int):
+    """Blocks between coarse boundaries of the two-level pass (>= 16)."""
+    _check(load().cm_set_coarse_stride(blocks), "cm_set_coarse_stride")
+
+
+def set_block_order(xcd_contiguous: int):
+    """1: each XCD gets a contiguous run of blocks; 0: workgroup order."""
+    _check(load().cm_set_block_order(xcd_contiguous), "cm_set_block_order")
 
 
 # ---------------------------------------------------------------------------

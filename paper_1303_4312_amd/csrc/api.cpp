@@ -26,7 +26,8 @@ namespace {
 struct Settings {
   int cfg[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [key type][payload] default configuration
   int search = 1;                             // bisection
-  int partition = 1;                          // two-level boundary pass
+  int partition = 2;                          // two-level boundary pass, 16-lane coarse search
+  Shape shape;                                // coarse stride, block order
 };
 Settings g_set;
 
@@ -104,7 +105,7 @@ bool any_overlap(std::initializer_list<Span> outs, std::initializer_list<Span> i
 // the smallest block of any configuration.
 size_t merge_ws_bytes(uint64_t N) {
   const uint64_t nb = (N + kMinTile - 1) / kMinTile + 1;
-  return round256(nb * sizeof(uint64_t)) + round256(num_coarse(nb) * sizeof(uint64_t));
+  return round256(nb * sizeof(uint64_t)) + round256(num_coarse(nb, kMinCoarse) * sizeof(uint64_t));
 }
 
 struct SegWs {
@@ -156,10 +157,10 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
   uint64_t* bj = (uint64_t*)ws;
   uint64_t* coarse = (uint64_t*)((char*)ws + round256(((N + kMinTile - 1) / kMinTile + 1) * sizeof(uint64_t)));
   timing_mark(0, st);
-  int rc = launch_block_co_ranks(kt, ch, A, m, B, n, T, tiles + 1, bj, coarse, st);
+  int rc = launch_block_co_ranks(kt, ch, g_set.shape, A, m, B, n, T, tiles + 1, bj, coarse, st);
   if (rc != CM_OK) return rc;
   timing_mark(1, st);
-  rc = launch_merge_blocks(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st);
+  rc = launch_merge_blocks(kt, val, ch, g_set.shape, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st);
   timing_mark(2, st);
   return rc;
 }
@@ -465,12 +466,24 @@ int cm_set_search(int search_mode) {
 int cm_get_search(void) { return g_set.search; }
 
 int cm_set_partition(int partition_mode) {
-  if (partition_mode != 0 && partition_mode != 1) return CM_EINVAL;
+  if (partition_mode < 0 || partition_mode > 2) return CM_EINVAL;
   g_set.partition = partition_mode;
   return CM_OK;
 }
 
 int cm_get_partition(void) { return g_set.partition; }
+
+int cm_set_coarse_stride(uint32_t blocks) {
+  if (blocks < kMinCoarse || blocks > (1u << 20)) return CM_EINVAL;
+  g_set.shape.coarse_stride = blocks;
+  return CM_OK;
+}
+
+int cm_set_block_order(int xcd_contiguous) {
+  if (xcd_contiguous != 0 && xcd_contiguous != 1) return CM_EINVAL;
+  g_set.shape.xcd_order = xcd_contiguous;
+  return CM_OK;
+}
 
 // ---- autotuner
 
@@ -488,7 +501,7 @@ int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64
   bool have = false;
   for (int cfg = 0; cfg < kNumCfgs; ++cfg)
     for (int search = 0; search < 2; ++search)
-      for (int part = 0; part < 2; ++part) {
+      for (int part = 0; part < 3; ++part) {
         const Choice ch{cfg, search, part};
         double ms = 0;
         const int rc = time_calls(
@@ -574,8 +587,8 @@ int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int conf
   if (op != kOpMerge && op != kOpSegmented && op != kOpBatch) return CM_EINVAL;
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
-  if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) ||
-      (partition_mode != 0 && partition_mode != 1))
+  if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) || partition_mode < 0 ||
+      partition_mode > 2)
     return CM_EINVAL;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning[TuneKey{op, key_type, with_payload ? 1 : 0, size_cls}] =
@@ -623,7 +636,7 @@ int cm_tuning_load(const char* path) {
     double ms;
     if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
         (op != kOpMerge && op != kOpSegmented && op != kOpBatch) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
-        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || (part != 0 && part != 1)) {
+        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || part < 0 || part > 2) {
       rc = CM_EINVAL;
       break;
     }

@@ -21,9 +21,10 @@ extern const int kNumCfgs;
 // configuration fits).
 extern const uint64_t kMinTile;
 
-// Every kCoarse-th block boundary is searched by the coarse pass of the
-// two-level boundary scheme.
-constexpr uint32_t kCoarse = 64;
+// The coarse pass of the two-level boundary scheme searches every
+// coarse_stride-th block boundary (at least kMinCoarse, which sizes the
+// workspace).
+constexpr uint32_t kMinCoarse = 16;
 
 enum Op : int { kOpMerge = 0, kOpSegmented = 1, kOpBatch = 2 };
 
@@ -31,20 +32,28 @@ enum Op : int { kOpMerge = 0, kOpSegmented = 1, kOpBatch = 2 };
 struct Choice {
   int cfg;        // index into kCfgs
   int search;     // per-thread and one-level boundary search: 0 Alg. 1, 1 bisection
-  int partition;  // block-boundary pass: 0 one thread per boundary, 1 two-level
+  int partition;  // block-boundary pass: 0 one thread per boundary; 1 two-level with a
+                  // 64-lane coarse search; 2 two-level with a 16-lane coarse search
+};
+
+// Launch-shape settings that never change results.
+struct Shape {
+  uint32_t coarse_stride = 64;  // blocks between coarse boundaries
+  int xcd_order = 1;            // XCD-contiguous block order in the block merge
 };
 
 inline uint64_t tile_size(int cfg) { return (uint64_t)kCfgs[cfg].nt * (uint64_t)kCfgs[cfg].e; }
-inline uint64_t num_coarse(uint64_t nb) { return (nb - 1 + kCoarse - 1) / kCoarse + 1; }
+inline uint64_t num_coarse(uint64_t nb, uint32_t stride) { return (nb - 1 + stride - 1) / stride + 1; }
 
 // Block-boundary co-ranks of one merge: bj[t] = A co-rank of min(t * tile, m + n)
-// for t < nb.  `coarse` holds num_coarse(nb) entries (two-level pass only).
-int launch_block_co_ranks(int kt, const Choice& ch, const void* A, uint64_t m, const void* B, uint64_t n,
-                          uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
+// for t < nb.  `coarse` holds num_coarse(nb, sh.coarse_stride) entries
+// (two-level pass only).
+int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,
+                          uint64_t n, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
 
 // Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj.
-int launch_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
-                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
+int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
+                        uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st);
 
 // Segmented batch: offset check, boundary co-ranks (and segments), block merge.

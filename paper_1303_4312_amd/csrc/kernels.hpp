@@ -48,20 +48,25 @@ __global__ __launch_bounds__(256) void k_block_co_rank(const K* __restrict__ A, 
   j_out[t] = co_rank<K, uint64_t>(search, i, ra, m, rb, n);
 }
 
-// Two-level boundary co-ranks.  Coarse pass: one wave per coarse boundary
-// c * stride (stride = G blocks), 64-ary search over the whole diagonal.
-template <typename K>
+// Two-level boundary co-ranks.  Coarse pass: a group of G lanes per coarse
+// boundary c * stride, G-ary search over the whole diagonal (G = 64: one
+// wave per boundary).
+template <typename K, int G>
 __global__ __launch_bounds__(256) void k_coarse_co_rank(const K* __restrict__ A, uint64_t m,
                                                         const K* __restrict__ B, uint64_t n, uint64_t stride,
                                                         uint64_t num_coarse, uint64_t* __restrict__ jc) {
-  const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;  // one wave each
-  if (c >= num_coarse) return;                                                 // whole waves leave
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((gid & ~63ull) / G >= num_coarse) return;  // whole waves with no boundary leave
+  const uint64_t c = gid / G;
+  const bool mine = c < num_coarse;  // groups past the end run along with an empty interval
   const uint64_t N = m + n;
-  const uint64_t i = std::min(c * stride, N);
+  const uint64_t i = mine ? std::min(c * stride, N) : 0;
   auto ra = [=](uint64_t x) { return A[x]; };
   auto rb = [=](uint64_t x) { return B[x]; };
-  const uint64_t j = co_rank_wave64<K>(i, ra, rb, i > n ? i - n : 0, std::min(i, m));
-  if ((threadIdx.x & 63) == 0) jc[c] = j;
+  const uint64_t lo = i > n ? i - n : 0;
+  const uint64_t hi = mine ? std::min(i, m) : lo;
+  const uint64_t j = G == 64 ? co_rank_wave64<K>(i, ra, rb, lo, hi) : co_rank_group<K, G>(i, ra, rb, lo, hi);
+  if (mine && (gid & (G - 1)) == 0) jc[c] = j;
 }
 
 // Fine pass: block boundary t lies between coarse boundaries c = t / G and
@@ -186,22 +191,34 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
   store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
 }
 
+// Workgroups are handed to the 8 XCDs of the chip round-robin by index.
+// With `xcd` set, workgroup b takes block x * q + min(x, r) + b / 8 (x = b % 8,
+// q = P / 8, r = P % 8): a bijection of [0, P) that gives every XCD one
+// contiguous run of blocks, so neighbouring blocks, which share the cache
+// lines at their window edges, run under the same L2.
+__device__ __forceinline__ uint64_t block_order(uint64_t b, uint64_t P, int xcd) {
+  if (!xcd) return b;
+  const uint64_t x = b & 7, q = P >> 3, r = P & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 template <typename K, bool VAL, int NT, int E>
 __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const uint32_t* __restrict__ Av,
                                                      uint64_t m, const K* __restrict__ B,
                                                      const uint32_t* __restrict__ Bv, uint64_t n,
                                                      K* __restrict__ C, uint32_t* __restrict__ Cv,
                                                      const uint64_t* __restrict__ bj, uint64_t num_tiles,
-                                                     int search) {
+                                                     int search, int xcd) {
   constexpr int T = NT * E;
   __shared__ K s_key[T];
   __shared__ uint32_t s_val[VAL ? T : 1];
   const uint64_t N = m + n;
-  for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
+  for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
+    const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
     merge_block<K, VAL, NT, E>(A, Av, B, Bv, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
-    if (t + gridDim.x < num_tiles) __syncthreads();
+    if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }
 

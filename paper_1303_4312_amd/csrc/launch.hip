@@ -17,7 +17,7 @@ namespace cm {
 // words) fall on distinct banks.
 const TileCfg kCfgs[] = {{256, 7}, {256, 11}, {256, 15}, {128, 7}, {512, 7}, {256, 5}, {256, 9}, {512, 11}};
 const int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
-const uint64_t kMinTile = 128 * 7;
+const uint64_t kMinTile = 128 * 7;  // smallest nt * e in kCfgs
 
 static int launch_status() { return hipGetLastError() == hipSuccess ? CM_OK : CM_EHIP; }
 
@@ -47,8 +47,8 @@ static int by_cfg(int cfg, F&& f) {
   }
 }
 
-int launch_block_co_ranks(int kt, const Choice& ch, const void* A, uint64_t m, const void* B, uint64_t n,
-                          uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
+int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,
+                          uint64_t n, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
     using K = decltype(key);
     const uint64_t blocks = (nb + 255) / 256;
@@ -57,18 +57,23 @@ int launch_block_co_ranks(int kt, const Choice& ch, const void* A, uint64_t m, c
                          (const K*)B, n, tile, nb, bj, ch.search);
       return launch_status();
     }
-    const uint64_t nc = num_coarse(nb);
-    hipLaunchKernelGGL((k_coarse_co_rank<K>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st, (const K*)A, m,
-                       (const K*)B, n, tile * kCoarse, nc, coarse);
+    const uint32_t G = sh.coarse_stride;
+    const uint64_t nc = num_coarse(nb, G);
+    if (ch.partition == 1)
+      hipLaunchKernelGGL((k_coarse_co_rank<K, 64>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st,
+                         (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
+    else
+      hipLaunchKernelGGL((k_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st,
+                         (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
     if (launch_status() != CM_OK) return CM_EHIP;
     hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
-                       (const K*)B, n, tile, nb, kCoarse, (const uint64_t*)coarse, bj);
+                       (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
     return launch_status();
   });
 }
 
-int launch_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
-                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
+int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
+                        uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
     using K = decltype(key);
@@ -76,10 +81,10 @@ int launch_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const
       constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
       if (val)
         hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st, (const K*)A,
-                           Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search);
+                           Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
       else
         hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const K*)A, Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search);
+                           (const K*)A, Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
       return launch_status();
     });
   });

@@ -120,6 +120,44 @@ __device__ __forceinline__ uint64_t co_rank_wave64(uint64_t i, RA A, RB B, uint6
   return lo;
 }
 
+// The same search by a group of G lanes (G a power of two dividing 64,
+// aligned inside the wave): each round tests G evenly spaced candidates and
+// shrinks the interval G-fold.  Fewer probes per round than the whole-wave
+// form (less memory traffic), at the price of more rounds.  Every lane of
+// the group returns the result; all lanes of the wave must call it together.
+template <typename K, int G, typename RA, typename RB>
+__device__ __forceinline__ uint64_t co_rank_group(uint64_t i, RA A, RB B, uint64_t lo, uint64_t hi) {
+  static_assert(G >= 2 && G <= 64 && (G & (G - 1)) == 0, "group size");
+  constexpr int kShift = G == 2 ? 1 : G == 4 ? 2 : G == 8 ? 3 : G == 16 ? 4 : G == 32 ? 5 : 6;
+  const int lane = (int)(threadIdx.x & 63);
+  const int g = lane & (G - 1);       // position in the group
+  const int base = lane - g;          // first lane of the group
+  bool live = lo < hi;
+  while (__any(live)) {
+    uint64_t cand = lo;
+    bool p = true;
+    if (live) {
+      const uint64_t L = hi - lo;
+      cand = lo + (L >> kShift) * (uint64_t)(g + 1) + (((L & (G - 1)) * (uint64_t)(g + 1)) >> kShift);
+      p = cand == lo || A(cand - 1) <= B(i - cand);
+    }
+    const uint64_t mask = (__ballot(p) >> base) & (G == 64 ? ~0ull : ((1ull << G) - 1));
+    const int t = __popcll(mask);  // true lanes form a prefix of the group
+    const uint64_t c_last_true = __shfl(cand, base + (t > 0 ? t - 1 : 0));
+    const uint64_t c_first_false = __shfl(cand, base + (t < G ? t : G - 1));
+    if (live) {
+      if (t == G) {
+        lo = hi;
+      } else {
+        hi = c_first_false - 1;
+        lo = t > 0 ? c_last_true : lo;
+      }
+      live = lo < hi;
+    }
+  }
+  return lo;
+}
+
 template <typename K, typename I, typename RA, typename RB>
 __device__ __forceinline__ I co_rank(int mode, I i, RA A, I m, RB B, I n) {
   return mode == kSearchBisect ? co_rank_bisect<K>(i, A, m, B, n)

@@ -23,7 +23,9 @@ DTYPES = [np.uint32, np.uint64, np.float32]
 def _default_settings():
     yield
     cm.set_search(1)
-    cm.set_partition(1)
+    cm.set_partition(2)
+    cm.set_coarse_stride(64)
+    cm.set_block_order(1)
     for kt in ("uint32", "uint64", "float32"):
         for v in (False, True):
             cm.set_config(kt, v, 2)
@@ -66,7 +68,7 @@ def test_figure_example(figure):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("search,partition", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("search,partition", [(0, 0), (1, 0), (0, 1), (1, 1), (1, 2)])
 def test_all_configs_pairs_and_keys(dtype, search, partition):
     cm.set_search(search)
     cm.set_partition(partition)
@@ -85,15 +87,19 @@ def test_all_configs_pairs_and_keys(dtype, search, partition):
             check_keys(A, B)
 
 
-@pytest.mark.parametrize("partition", [0, 1])
-def test_two_level_partition_edges(partition):
-    """Block counts around multiples of the coarse stride (64 blocks), with
-    the co-rank windows of the fine pass both wide and degenerate."""
+@pytest.mark.parametrize("partition,stride,xcd", [(0, 64, 1), (1, 64, 1), (2, 64, 0), (1, 16, 0),
+                                                  (2, 16, 1)])
+def test_two_level_partition_edges(partition, stride, xcd):
+    """Block counts around multiples of the coarse stride, with the co-rank
+    windows of the fine pass both wide and degenerate; both block orders."""
     cm.set_partition(partition)
+    cm.set_coarse_stride(stride)
+    cm.set_block_order(xcd)
     nt, e = cm.config_info(cm.get_config("uint32", True))
     T = nt * e
     rng = np.random.default_rng(21)
-    for N in (64 * T, 64 * T + 1, 64 * T - 1, 65 * T, 128 * T + T // 2, 200 * T + 7):
+    for N in (64 * T, 64 * T + 1, 64 * T - 1, 65 * T, 128 * T + T // 2, 200 * T + 7,
+              16 * T + 3, 8 * T + 5):
         m = int(rng.integers(0, N + 1))
         for hi in (3, 1 << 30):
             A = random_sorted(rng, m, np.uint32, hi)

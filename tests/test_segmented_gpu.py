@@ -14,7 +14,9 @@ pytestmark = pytest.mark.gpu
 def _default_settings():
     yield
     cm.set_search(1)
-    cm.set_partition(1)
+    cm.set_partition(2)
+    cm.set_coarse_stride(64)
+    cm.set_block_order(1)
     for kt in ("uint32", "uint64", "float32"):
         for v in (False, True):
             cm.set_config(kt, v, 2)
