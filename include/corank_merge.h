@@ -247,7 +247,11 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     levels: every coarse boundary by a whole wave with a 64-ary search,
  *     then the others by bisection between their two coarse neighbours;
  *     2 (default) = two levels with 16 lanes (a 16-ary search) per coarse
- *     boundary.  All give the same co-ranks.
+ *     boundary; 3 = Algorithm 2 with one block per resident workgroup:
+ *     only those P + 1 boundaries are co-ranked (a whole wave each), and
+ *     each workgroup merges its whole block in steps through LDS ring
+ *     buffers (single merges only; the batch forms treat 3 as 2).  All
+ *     give the same results.
  *   cm_set_coarse_stride: blocks between coarse boundaries of the two-level
  *     pass (default 64; at least 16).
  *   cm_set_block_order: 1 (default) hands each of the chip's 8 XCDs a

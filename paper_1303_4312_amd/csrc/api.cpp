@@ -156,6 +156,16 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
   if (dry_run) return CM_OK;
   uint64_t* bj = (uint64_t*)ws;
   uint64_t* coarse = (uint64_t*)((char*)ws + round256(((N + kMinTile - 1) / kMinTile + 1) * sizeof(uint64_t)));
+  if (ch.partition == 3) {  // one block per resident workgroup; P + 1 <= tiles + 1 co-ranks fit bj
+    const uint32_t P = stream_blocks(kt, val, ch, N);
+    timing_mark(0, st);
+    int rc = launch_stream_co_ranks(kt, A, m, B, n, P, bj, st);
+    if (rc != CM_OK) return rc;
+    timing_mark(1, st);
+    rc = launch_merge_stream(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, bj, P, st);
+    timing_mark(2, st);
+    return rc;
+  }
   timing_mark(0, st);
   int rc = launch_block_co_ranks(kt, ch, g_set.shape, A, m, B, n, T, tiles + 1, bj, coarse, st);
   if (rc != CM_OK) return rc;
@@ -466,7 +476,7 @@ int cm_set_search(int search_mode) {
 int cm_get_search(void) { return g_set.search; }
 
 int cm_set_partition(int partition_mode) {
-  if (partition_mode < 0 || partition_mode > 2) return CM_EINVAL;
+  if (partition_mode < 0 || partition_mode > 3) return CM_EINVAL;
   g_set.partition = partition_mode;
   return CM_OK;
 }
@@ -501,7 +511,7 @@ int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64
   bool have = false;
   for (int cfg = 0; cfg < kNumCfgs; ++cfg)
     for (int search = 0; search < 2; ++search)
-      for (int part = 0; part < 3; ++part) {
+      for (int part = 0; part < 4; ++part) {
         const Choice ch{cfg, search, part};
         double ms = 0;
         const int rc = time_calls(
@@ -588,7 +598,7 @@ int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int conf
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
   if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) || partition_mode < 0 ||
-      partition_mode > 2)
+      partition_mode > 3)
     return CM_EINVAL;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning[TuneKey{op, key_type, with_payload ? 1 : 0, size_cls}] =
@@ -636,7 +646,7 @@ int cm_tuning_load(const char* path) {
     double ms;
     if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
         (op != kOpMerge && op != kOpSegmented && op != kOpBatch) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
-        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || part < 0 || part > 2) {
+        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || part < 0 || part > 3) {
       rc = CM_EINVAL;
       break;
     }

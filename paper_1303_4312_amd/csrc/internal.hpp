@@ -33,7 +33,8 @@ struct Choice {
   int cfg;        // index into kCfgs
   int search;     // per-thread and one-level boundary search: 0 Alg. 1, 1 bisection
   int partition;  // block-boundary pass: 0 one thread per boundary; 1 two-level with a
-                  // 64-lane coarse search; 2 two-level with a 16-lane coarse search
+                  // 64-lane coarse search; 2 two-level with a 16-lane coarse search;
+                  // 3 one block per resident workgroup (streaming kernel)
 };
 
 // Launch-shape settings that never change results.
@@ -55,6 +56,17 @@ int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void*
 int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
                         uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st);
+
+// Algorithm 2 with one block per resident workgroup: the number of blocks P
+// the streaming kernel uses for an N-output merge (resident workgroups of the
+// chip, at most one per T outputs), its P + 1 boundary co-ranks, and the
+// kernel.  J holds P + 1 entries.
+uint32_t stream_blocks(int kt, bool val, const Choice& ch, uint64_t N);
+int launch_stream_co_ranks(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t P, uint64_t* J,
+                           hipStream_t st);
+int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
+                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* J,
+                        uint32_t P, hipStream_t st);
 
 // Segmented batch: offset check, boundary co-ranks (and segments), block merge.
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,

@@ -222,6 +222,208 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, co
   }
 }
 
+// ---- Algorithm 2 with one processing element per resident workgroup --------
+
+// First output of block w of P: floor(w * N / P), exactly (no 128-bit product).
+__device__ __forceinline__ uint64_t stream_block_start(uint64_t w, uint64_t N, uint64_t P) {
+  return (N / P) * w + ((N % P) * w) / P;
+}
+
+// J[w] = A co-rank of stream_block_start(w), w in [0, P]; one wave per
+// boundary with the 64-ary search.
+template <typename K>
+__global__ __launch_bounds__(256) void k_stream_co_rank(const K* __restrict__ A, uint64_t m,
+                                                        const K* __restrict__ B, uint64_t n, uint32_t P,
+                                                        uint64_t* __restrict__ J) {
+  const uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (w > P) return;  // whole waves leave
+  const uint64_t i = stream_block_start(w, m + n, P);
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  const uint64_t j = co_rank_wave64<K>(i, ra, rb, i > n ? i - n : 0, std::min(i, m));
+  if ((threadIdx.x & 63) == 0) J[w] = j;
+}
+
+// Ring of T slots: slot of position x (x < T) after head h (h < T).
+template <int T>
+__device__ __forceinline__ int ring_slot(int h, int x) {
+  const int s = h + x;
+  return s < T ? s : s - T;
+}
+
+// Workgroup w merges its whole output block [o_w, o_{w+1}) of Algorithm 2
+// (P blocks, sizes differing by at most one) from the windows A[J_w, J_{w+1})
+// and B[o_w - J_w, o_{w+1} - J_{w+1}), in steps of T = NT * E outputs.
+// Two LDS rings of T slots hold the next min(T, remaining) elements of each
+// window.  A step co-ranks every thread's start q * E inside the rings (the
+// co-rank of d <= T needs no element past position T of either window),
+// merges E outputs per thread, and finds how many A elements the step used
+// (a_take: the final A cursor of the thread that produces the step's last
+// output).  The step's outputs are then staged in exactly the ring slots it
+// consumed (a_take slots of ring A, len - a_take of ring B), stored to C in
+// order, and those slots are refilled from global memory with the next
+// elements of each window; the refill loads are issued before the stores so
+// that both are in flight together.
+template <typename K, bool VAL, int NT, int E>
+__global__ __launch_bounds__(NT) void k_merge_stream(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+                                                     uint64_t m, const K* __restrict__ B,
+                                                     const uint32_t* __restrict__ Bv, uint64_t n,
+                                                     K* __restrict__ C, uint32_t* __restrict__ Cv,
+                                                     const uint64_t* __restrict__ J, uint32_t P, int search) {
+  constexpr int T = NT * E;
+  __shared__ K ra_key[T];
+  __shared__ K rb_key[T];
+  __shared__ uint32_t ra_val[VAL ? T : 1];
+  __shared__ uint32_t rb_val[VAL ? T : 1];
+  __shared__ int s_take;
+  const uint64_t N = m + n;
+  const uint64_t w = blockIdx.x;
+  if (w >= P) return;
+  uint64_t o = stream_block_start(w, N, P);
+  const uint64_t o_end = stream_block_start(w + 1, N, P);
+  uint64_t ja = J[w];
+  const uint64_t ja_end = std::max(J[w + 1], ja);  // the max only matters for unsorted input
+  uint64_t kb = o - ja;
+  const uint64_t kb_end = std::max(o_end - std::min(J[w + 1], o_end), kb);
+  int ha = 0, hb = 0;  // ring heads
+  int fa = (int)std::min<uint64_t>(T, ja_end - ja);
+  int fb = (int)std::min<uint64_t>(T, kb_end - kb);
+  // initial fill
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int x = (int)threadIdx.x + r * NT;
+    if (x < fa) {
+      ra_key[x] = A[ja + x];
+      if constexpr (VAL) ra_val[x] = Av[ja + x];
+    }
+    if (x < fb) {
+      rb_key[x] = B[kb + x];
+      if constexpr (VAL) rb_val[x] = Bv[kb + x];
+    }
+  }
+  __syncthreads();
+
+  while (o < o_end) {
+    // fa + fb >= the step with sorted input; the clamp and the exit only
+    // keep unsorted input in bounds and finite
+    const int len = (int)std::min<uint64_t>(std::min<uint64_t>(T, o_end - o), (uint64_t)(fa + fb));
+    if (len == 0) break;
+    const int d = std::min((int)threadIdx.x * E, len);
+    const int avail = len - d;
+    auto rka = [&](int x) { return ra_key[ring_slot<T>(ha, x)]; };
+    auto rkb = [&](int x) { return rb_key[ring_slot<T>(hb, x)]; };
+    int a = co_rank<K, int>(search, d, rka, fa, rkb, fb);
+    int b = d - a;
+    K ok[E];
+    int os[E];  // ring slot of each output: slot in A, or T + slot in B
+    K ka = a < fa ? rka(a) : K{};
+    K kbv = b < fb ? rkb(b) : K{};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e < avail) {
+        const bool take_a = (a < fa) && (b >= fb || ka <= kbv);
+        ok[e] = take_a ? ka : kbv;
+        os[e] = take_a ? ring_slot<T>(ha, a) : T + ring_slot<T>(hb, b);
+        a += take_a ? 1 : 0;
+        b += take_a ? 0 : 1;
+        const bool more = take_a ? (a < fa) : (b < fb);
+        const K next = more ? (take_a ? rka(a) : rkb(b)) : K{};
+        if (take_a)
+          ka = next;
+        else
+          kbv = next;
+      }
+    }
+    if (avail > 0 && avail <= E) s_take = a;  // this thread produced the step's last output
+    uint32_t ov[E];
+    if constexpr (VAL) {
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (e < avail) ov[e] = os[e] < T ? ra_val[os[e]] : rb_val[os[e] - T];
+    }
+    __syncthreads();  // every ring read of this step is done; s_take is visible
+    const int a_take = s_take;
+    const int b_take = len - a_take;
+    // stage output x in the x-th consumed slot: A's for x < a_take, then B's
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (e < avail) {
+        const int x = d + e;
+        if (x < a_take) {
+          const int sl = ring_slot<T>(ha, x);
+          ra_key[sl] = ok[e];
+          if constexpr (VAL) ra_val[sl] = ov[e];
+        } else {
+          const int sl = ring_slot<T>(hb, x - a_take);
+          rb_key[sl] = ok[e];
+          if constexpr (VAL) rb_val[sl] = ov[e];
+        }
+      }
+    }
+    // refill: after the step ring A must hold min(T, remaining) elements
+    // again; the new ones are window positions [fa, a_take + fa_next) of the
+    // old head, i.e. [fa - a_take, fa_next) of the new one
+    const uint64_t ja_next = ja + (uint64_t)a_take, kb_next = kb + (uint64_t)b_take;
+    const int fa_next = (int)std::min<uint64_t>(T, ja_end - ja_next);
+    const int fb_next = (int)std::min<uint64_t>(T, kb_end - kb_next);
+    const int new_a = a_take + fa_next - fa;  // >= 0
+    const int new_b = b_take + fb_next - fb;
+    const int ha_next = ring_slot<T>(ha, a_take);
+    const int hb_next = ring_slot<T>(hb, b_take);
+    K nk[E];
+    uint32_t nv[E];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int x = (int)threadIdx.x + r * NT;
+      if (x < new_a) {
+        const uint64_t g = ja + fa + x;
+        nk[r] = A[g];
+        if constexpr (VAL) nv[r] = Av[g];
+      } else if (x < new_a + new_b) {
+        const uint64_t g = kb + fb + (x - new_a);
+        nk[r] = B[g];
+        if constexpr (VAL) nv[r] = Bv[g];
+      }
+    }
+    __syncthreads();  // staging complete
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int x = (int)threadIdx.x + r * NT;
+      if (x < len) {
+        const int sl = x < a_take ? ring_slot<T>(ha, x) : ring_slot<T>(hb, x - a_take);
+        const K key = x < a_take ? ra_key[sl] : rb_key[sl];
+        __builtin_nontemporal_store(key, C + o + x);
+        if constexpr (VAL) {
+          const uint32_t v = x < a_take ? ra_val[sl] : rb_val[sl];
+          __builtin_nontemporal_store(v, Cv + o + x);
+        }
+      }
+    }
+    __syncthreads();  // staging read; the consumed slots may be overwritten
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int x = (int)threadIdx.x + r * NT;
+      if (x < new_a) {
+        const int sl = ring_slot<T>(ha_next, fa - a_take + x);
+        ra_key[sl] = nk[r];
+        if constexpr (VAL) ra_val[sl] = nv[r];
+      } else if (x < new_a + new_b) {
+        const int sl = ring_slot<T>(hb_next, fb - b_take + (x - new_a));
+        rb_key[sl] = nk[r];
+        if constexpr (VAL) rb_val[sl] = nv[r];
+      }
+    }
+    ja = ja_next;
+    kb = kb_next;
+    ha = ha_next;
+    hb = hb_next;
+    fa = fa_next;
+    fb = fb_next;
+    o += (uint64_t)len;
+    __syncthreads();  // refill visible to the next step
+  }
+}
+
 // ---- batch of separately allocated merges ----------------------------------
 
 // One merge of a batch.  Same layout as the C ABI's cm_merge_desc.

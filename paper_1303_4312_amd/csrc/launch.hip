@@ -90,6 +90,66 @@ int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, con
   });
 }
 
+// Resident workgroups per CU of `kernel` at nt threads, times the CU count;
+// cached per kernel (the library drives one device type).
+static uint32_t resident_blocks(const void* kernel, int nt, int* cache) {
+  if (*cache > 0) return (uint32_t)*cache;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || cus <= 0 ||
+      per_cu <= 0) {
+    (void)hipGetLastError();
+    return 256;  // a safe count for any device: correctness never depends on it
+  }
+  *cache = cus * per_cu;
+  return (uint32_t)*cache;
+}
+
+uint32_t stream_blocks(int kt, bool val, const Choice& ch, uint64_t N) {
+  const uint64_t T = tile_size(ch.cfg);
+  const uint64_t tiles = (N + T - 1) / T;
+  const uint32_t res = (uint32_t)by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+      static int cache_v = 0, cache_k = 0;
+      return val ? (int)resident_blocks((const void*)k_merge_stream<K, true, NT, E>, NT, &cache_v)
+                 : (int)resident_blocks((const void*)k_merge_stream<K, false, NT, E>, NT, &cache_k);
+    });
+  });
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, tiles));
+}
+
+int launch_stream_co_ranks(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t P, uint64_t* J,
+                           hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    const uint64_t waves = (uint64_t)P + 1;
+    hipLaunchKernelGGL((k_stream_co_rank<K>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, (const K*)A, m,
+                       (const K*)B, n, P, J);
+    return launch_status();
+  });
+}
+
+int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
+                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* J,
+                        uint32_t P, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+      if (val)
+        hipLaunchKernelGGL((k_merge_stream<K, true, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
+                           (const K*)B, Bv, n, (K*)C, Cv, J, P, ch.search);
+      else
+        hipLaunchKernelGGL((k_merge_stream<K, false, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
+                           (const K*)B, Bv, n, (K*)C, Cv, J, P, ch.search);
+      return launch_status();
+    });
+  });
+}
+
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,
                         uint64_t total_b, uint32_t* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_seg_validate, dim3(1), dim3(1024), 0, st, a_off, b_off, S, total_a, total_b, flag);

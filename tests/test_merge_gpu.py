@@ -68,7 +68,8 @@ def test_figure_example(figure):
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
-@pytest.mark.parametrize("search,partition", [(0, 0), (1, 0), (0, 1), (1, 1), (1, 2)])
+@pytest.mark.parametrize("search,partition", [(0, 0), (1, 0), (0, 1), (1, 1), (1, 2), (0, 3),
+                                              (1, 3)])
 def test_all_configs_pairs_and_keys(dtype, search, partition):
     cm.set_search(search)
     cm.set_partition(partition)
@@ -88,7 +89,7 @@ def test_all_configs_pairs_and_keys(dtype, search, partition):
 
 
 @pytest.mark.parametrize("partition,stride,xcd", [(0, 64, 1), (1, 64, 1), (2, 64, 0), (1, 16, 0),
-                                                  (2, 16, 1)])
+                                                  (2, 16, 1), (3, 64, 1)])
 def test_two_level_partition_edges(partition, stride, xcd):
     """Block counts around multiples of the coarse stride, with the co-rank
     windows of the fine pass both wide and degenerate; both block orders."""
@@ -108,6 +109,29 @@ def test_two_level_partition_edges(partition, stride, xcd):
     d = workloads.structured("a_below_b", 70 * T, 3 * T + 5)
     check_pairs(d["A"], d["B"], d["Av"], d["Bv"])
     check_pairs(d["B"], d["A"], d["Bv"], d["Av"])
+
+
+@pytest.mark.parametrize("dtype", DTYPES)
+def test_streaming_blocks(dtype):
+    """One block per resident workgroup (partition 3): sizes from a few
+    elements to many steps per workgroup, skewed and degenerate inputs."""
+    cm.set_partition(3)
+    rng = np.random.default_rng(33)
+    kt = np.dtype(dtype).name
+    for c in (0, 4, 6):
+        cm.set_config(kt, True, c)
+        cm.set_config(kt, False, c)
+        for m, n, hi in ((1, 0, 5), (0, 5, 5), (3, 4, 5), (1000, 1, 50),
+                         (1 << 20, 3 << 19, 1000), (5, 3_000_001, 1 << 20),
+                         (2_000_003, 1_999_999, 2)):
+            A = random_sorted(rng, m, dtype, hi)
+            B = random_sorted(rng, n, dtype, hi)
+            check_pairs(A, B)
+            check_keys(A, B)
+    for kind in ("a_below_b", "interleaved", "all_equal"):
+        d = workloads.structured(kind, 1_500_000, 1_500_000, dtype)
+        check_pairs(d["A"], d["B"], d["Av"], d["Bv"])
+        check_pairs(d["B"], d["A"], d["Bv"], d["Av"])
 
 
 @pytest.mark.parametrize("dtype", DTYPES)
