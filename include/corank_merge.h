@@ -181,9 +181,10 @@ int cm_stable_merge_batch(int key_type, int with_payload,
 
 /*
  * Workspace bytes for a segmented merge of num_seg segments with total_a
- * and total_b elements: a status word, and per block boundary one uint64
- * co-rank and one uint32 segment index (sized for the smallest block of any
- * configuration), each part rounded up to 256 bytes.
+ * and total_b elements: a status word, and per block boundary and per
+ * coarse boundary one uint64 co-rank and one uint32 segment index (sized
+ * for the smallest block of any configuration), each part rounded up to
+ * 256 bytes.
  */
 size_t cm_segmented_workspace_size(int key_type, int with_payload,
                                    uint64_t total_a, uint64_t total_b,
@@ -250,8 +251,10 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     boundary; 3 = Algorithm 2 with one block per resident workgroup:
  *     only those P + 1 boundaries are co-ranked (a whole wave each), and
  *     each workgroup merges its whole block in steps through LDS ring
- *     buffers (single merges only; the batch forms treat 3 as 2).  All
- *     give the same results.
+ *     buffers (single merges only).  The segmented batch uses two levels
+ *     (segment search and co-rank narrowed by coarse neighbours) for any
+ *     nonzero mode and one level for 0; the batch of separate merges always
+ *     uses one level.  All give the same results.
  *   cm_set_coarse_stride: blocks between coarse boundaries of the two-level
  *     pass (default 64; at least 16).
  *   cm_set_block_order: 1 (default) hands each of the chip's 8 XCDs a
@@ -283,8 +286,7 @@ int cm_set_block_order(int xcd_contiguous);
  * candidate produces the same output, so C (and C_val) hold the merge
  * afterwards.  Arguments are those of cm_stable_merge_pairs (payload
  * pointers all NULL for keys only) / cm_stable_merge_segmented.  The
- * segmented tuner tries only the one-level boundary pass (the batch's
- * boundary pass has no two-level form).
+ * segmented tuner tries the one-level and two-level boundary passes.
  * Errors: those of the merge calls; CM_EINVAL for reps outside [1, 10000]
  * or an empty merge.
  */

@@ -110,13 +110,16 @@ size_t merge_ws_bytes(uint64_t N) {
 
 struct SegWs {
   uint32_t* flag;
-  uint64_t* bj;
-  uint32_t* bs;
+  uint64_t* bj;  // block boundary co-ranks
+  uint32_t* bs;  // block boundary segments
+  uint64_t* jc;  // coarse boundary co-ranks (two-level pass)
+  uint32_t* sc;  // coarse boundary segments
   size_t bytes;
 };
 
 SegWs seg_ws(void* ws, uint64_t N) {
   const uint64_t nb = (N + kMinTile - 1) / kMinTile + 1;
+  const uint64_t nc = num_coarse(nb, kMinCoarse);
   char* p = (char*)ws;
   SegWs w;
   w.flag = (uint32_t*)p;
@@ -125,6 +128,10 @@ SegWs seg_ws(void* ws, uint64_t N) {
   off += round256(nb * sizeof(uint64_t));
   w.bs = (uint32_t*)(p + off);
   off += round256(nb * sizeof(uint32_t));
+  w.jc = (uint64_t*)(p + off);
+  off += round256(nc * sizeof(uint64_t));
+  w.sc = (uint32_t*)(p + off);
+  off += round256(nc * sizeof(uint32_t));
   w.bytes = off;
   return w;
 }
@@ -203,8 +210,8 @@ int seg_impl(int kt, const void* A, const uint32_t* Av, const uint64_t* a_off, u
   timing_mark(0, st);
   int rc = launch_seg_validate(a_off, b_off, S, total_a, total_b, w.flag, st);
   if (rc == CM_OK)
-    rc = launch_seg_block_co_ranks(kt, ch, A, a_off, B, b_off, (uint32_t)S, N, T, tiles + 1, w.bj, w.bs, w.flag,
-                                   st);
+    rc = launch_seg_block_co_ranks(kt, ch, g_set.shape, A, a_off, B, b_off, (uint32_t)S, N, T, tiles + 1, w.bj,
+                                   w.bs, w.jc, w.sc, w.flag, st);
   if (rc != CM_OK) return rc;
   timing_mark(1, st);
   rc = launch_seg_merge_blocks(kt, val, ch, A, Av, a_off, B, Bv, b_off, (uint32_t)S, N, C, Cv, w.bj, w.bs, tiles,
@@ -553,8 +560,9 @@ int cm_autotune_segmented(int key_type, const void* A, const uint32_t* A_val, co
   double win_ms = 0;
   bool have = false;
   for (int cfg = 0; cfg < kNumCfgs; ++cfg)
-    for (int search = 0; search < 2; ++search) {
-      const Choice ch{cfg, search, 0};
+    for (int search = 0; search < 2; ++search)
+      for (int part = 0; part < 3; part += 2) {
+      const Choice ch{cfg, search, part};
       double ms = 0;
       const int rc = time_calls(
           [&] {

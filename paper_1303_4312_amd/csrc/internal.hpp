@@ -71,9 +71,12 @@ int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const
 // Segmented batch: offset check, boundary co-ranks (and segments), block merge.
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,
                         uint64_t total_b, uint32_t* flag, hipStream_t st);
-int launch_seg_block_co_ranks(int kt, const Choice& ch, const void* A, const uint64_t* a_off, const void* B,
-                              const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile, uint64_t nb,
-                              uint64_t* bj, uint32_t* bs, const uint32_t* flag, hipStream_t st);
+// With ch.partition != 0 and coarse scratch (jc, sc: num_coarse(nb, stride)
+// entries each), the boundaries are found in two levels.
+int launch_seg_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, const uint64_t* a_off,
+                              const void* B, const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile,
+                              uint64_t nb, uint64_t* bj, uint32_t* bs, uint64_t* jc, uint32_t* sc,
+                              const uint32_t* flag, hipStream_t st);
 int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av,
                             const uint64_t* a_off, const void* B, const uint32_t* Bv, const uint64_t* b_off,
                             uint32_t S, uint64_t N, void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs,

@@ -497,26 +497,22 @@ __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __re
 
 // ---- segmented batch -------------------------------------------------------
 
-// One workgroup: flag = 0 if the offsets are consistent (start at 0,
-// nondecreasing, end at the host totals), else 1.  Every later kernel of the
-// call reads the flag and does nothing when it is set.
-__global__ __launch_bounds__(1024) void k_seg_validate(const uint64_t* __restrict__ a_off,
-                                                       const uint64_t* __restrict__ b_off, uint64_t S,
-                                                       uint64_t total_a, uint64_t total_b,
-                                                       uint32_t* __restrict__ flag) {
-  __shared__ int bad;
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  int my_bad = 0;
-  for (uint64_t s = threadIdx.x; s < S; s += blockDim.x) {
-    if (a_off[s] > a_off[s + 1] || b_off[s] > b_off[s + 1]) my_bad = 1;
-  }
-  if (threadIdx.x == 0) {
-    if (a_off[0] != 0 || b_off[0] != 0 || a_off[S] != total_a || b_off[S] != total_b) my_bad = 1;
-  }
-  if (my_bad) atomicOr(&bad, 1);
-  __syncthreads();
-  if (threadIdx.x == 0) *flag = bad ? 1u : 0u;
+// flag |= 1 if the offsets are inconsistent (not starting at 0, decreasing
+// somewhere, or not ending at the host totals).  Grid-stride over the
+// segments; the flag is cleared by k_fill_u32 before.  Every later kernel of
+// the call reads the flag and does nothing when it is set.
+__global__ __launch_bounds__(256) void k_seg_validate(const uint64_t* __restrict__ a_off,
+                                                      const uint64_t* __restrict__ b_off, uint64_t S,
+                                                      uint64_t total_a, uint64_t total_b,
+                                                      uint32_t* __restrict__ flag) {
+  int bad = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride)
+    if (a_off[s] > a_off[s + 1] || b_off[s] > b_off[s + 1]) bad = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0 &&
+      (a_off[0] != 0 || b_off[0] != 0 || a_off[S] != total_a || b_off[S] != total_b))
+    bad = 1;
+  if (__any(bad) && (threadIdx.x % warpSize) == 0) atomicOr(flag, 1u);
 }
 
 // Largest s in [lo, hi] with a_off[s] + b_off[s] <= g (the segment holding
@@ -558,6 +554,53 @@ __global__ __launch_bounds__(256) void k_seg_block_co_rank(const K* __restrict__
   auto ra = [=](uint64_t x) { return As[x]; };
   auto rb = [=](uint64_t x) { return Bs[x]; };
   j_out[t] = a0 + co_rank<K, uint64_t>(search, d, ra, ms, rb, ns);
+  s_out[t] = s;
+}
+
+// Two-level form for the batch: block boundary t lies between coarse
+// boundaries c = t / G and c + 1 (computed by k_seg_block_co_rank with a
+// G-times longer stride into jc, sc).  Its segment lies in [sc[c], sc[c+1]]
+// and, inside that segment, its co-ranks lie between the coarse ones (the
+// batch is one merge under (segment, key), so co-ranks are monotone), so
+// both searches run over short ranges.
+template <typename K>
+__global__ __launch_bounds__(256) void k_seg_fine_co_rank(const K* __restrict__ A, const uint64_t* __restrict__ a_off,
+                                                          const K* __restrict__ B, const uint64_t* __restrict__ b_off,
+                                                          uint64_t N, uint64_t tile, uint64_t num_bounds, uint32_t G,
+                                                          const uint64_t* __restrict__ jc,
+                                                          const uint32_t* __restrict__ sc,
+                                                          uint64_t* __restrict__ j_out, uint32_t* __restrict__ s_out,
+                                                          const uint32_t* __restrict__ flag) {
+  const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= num_bounds || *flag) return;
+  const uint64_t c = t / G;
+  if (t % G == 0) {
+    j_out[t] = jc[c];
+    s_out[t] = sc[c];
+    return;
+  }
+  const uint64_t i = std::min(t * tile, N);
+  const uint64_t i0 = std::min(c * G * tile, N), i1 = std::min((c + 1) * G * tile, N);
+  const uint64_t J0 = jc[c], J1 = jc[c + 1];
+  const uint64_t K0 = i0 - J0, K1 = i1 - J1;
+  const uint32_t s = seg_of(a_off, b_off, sc[c], std::max(sc[c], sc[c + 1]), i);
+  const uint64_t a0 = a_off[s], b0 = b_off[s];
+  const uint64_t ms = a_off[s + 1] - a0, ns = b_off[s + 1] - b0;
+  const uint64_t d = i - a0 - b0;
+  // local j in [max(0, d - ns), min(d, ms)], also J0 <= a0 + j <= J1 and
+  // K0 <= b0 + d - j <= K1
+  uint64_t lo = d > ns ? d - ns : 0;
+  if (J0 > a0) lo = std::max(lo, J0 - a0);
+  if (b0 + d > K1) lo = std::max(lo, b0 + d - K1);
+  uint64_t hi = std::min(d, ms);
+  hi = std::min(hi, J1 > a0 ? J1 - a0 : 0);
+  hi = std::min(hi, b0 + d > K0 ? b0 + d - K0 : 0);
+  if (hi < lo) hi = lo;  // only for unsorted input
+  const K* As = A + a0;
+  const K* Bs = B + b0;
+  auto ra = [=](uint64_t x) { return As[x]; };
+  auto rb = [=](uint64_t x) { return Bs[x]; };
+  j_out[t] = a0 + co_rank_bisect_in<K>(d, ra, rb, lo, hi);
   s_out[t] = s;
 }
 

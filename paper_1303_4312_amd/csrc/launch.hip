@@ -152,17 +152,33 @@ int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const
 
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,
                         uint64_t total_b, uint32_t* flag, hipStream_t st) {
-  hipLaunchKernelGGL(k_seg_validate, dim3(1), dim3(1024), 0, st, a_off, b_off, S, total_a, total_b, flag);
+  hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, flag, 0u);
+  if (launch_status() != CM_OK) return CM_EHIP;
+  const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((S + 255) / 256, 2048));
+  hipLaunchKernelGGL(k_seg_validate, dim3((unsigned)blocks), dim3(256), 0, st, a_off, b_off, S, total_a, total_b,
+                     flag);
   return launch_status();
 }
 
-int launch_seg_block_co_ranks(int kt, const Choice& ch, const void* A, const uint64_t* a_off, const void* B,
-                              const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile, uint64_t nb,
-                              uint64_t* bj, uint32_t* bs, const uint32_t* flag, hipStream_t st) {
+int launch_seg_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, const uint64_t* a_off,
+                              const void* B, const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile,
+                              uint64_t nb, uint64_t* bj, uint32_t* bs, uint64_t* jc, uint32_t* sc,
+                              const uint32_t* flag, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
     using K = decltype(key);
-    hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
-                       (const K*)A, a_off, (const K*)B, b_off, S, N, tile, nb, bj, bs, flag, ch.search);
+    if (ch.partition == 0 || !jc || !sc) {
+      hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                         (const K*)A, a_off, (const K*)B, b_off, S, N, tile, nb, bj, bs, flag, ch.search);
+      return launch_status();
+    }
+    const uint32_t G = sh.coarse_stride;
+    const uint64_t nc = num_coarse(nb, G);
+    hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const K*)A,
+                       a_off, (const K*)B, b_off, S, N, tile * G, nc, jc, sc, flag, ch.search);
+    if (launch_status() != CM_OK) return CM_EHIP;
+    hipLaunchKernelGGL((k_seg_fine_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, (const K*)A,
+                       a_off, (const K*)B, b_off, N, tile, nb, G, (const uint64_t*)jc, (const uint32_t*)sc, bj, bs,
+                       flag);
     return launch_status();
   });
 }

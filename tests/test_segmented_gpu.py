@@ -61,9 +61,12 @@ def test_many_tiny_segments_with_empty_sides(dtype):
     check_seg(d, payload=False)
 
 
-@pytest.mark.parametrize("search", [0, 1])
-def test_all_configs(search):
+@pytest.mark.parametrize("search,partition,stride", [(0, 0, 64), (1, 0, 64), (0, 2, 64), (1, 2, 64),
+                                                     (1, 2, 16)])
+def test_all_configs(search, partition, stride):
     cm.set_search(search)
+    cm.set_partition(partition)
+    cm.set_coarse_stride(stride)
     d = workloads.segmented(seed=7, num_seg=700, max_side=1 << 12, key_high=64, min_side=0)
     for c in range(cm.config_count()):
         cm.set_config("uint32", True, c)
@@ -117,6 +120,25 @@ def test_inconsistent_offsets_leave_output_untouched():
     cm.stable_merge_segmented(to_dev(d["A"]), to_dev(a_off), to_dev(d["B"]), to_dev(d["b_off"]),
                               C=C)
     assert np.all(to_host(C) == 7)
+
+
+@pytest.mark.parametrize("partition", [0, 2])
+def test_two_level_segmented_edges(partition):
+    """Many blocks and coarse windows spanning many tiny segments, empty
+    segments, and segments much longer than a coarse window."""
+    cm.set_partition(partition)
+    cm.set_coarse_stride(16)
+    rng = np.random.default_rng(44)
+    la = np.concatenate([rng.integers(0, 3, 3000), [200_000], rng.integers(0, 50, 2000), [0, 0],
+                         [90_001]]).astype(np.int64)
+    lb = np.concatenate([rng.integers(0, 3, 3000), [3], rng.integers(0, 50, 2000), [0, 7],
+                         [150_000]]).astype(np.int64)
+    A = np.concatenate([np.sort(rng.integers(0, 5, x)) for x in la]).astype(np.uint32)
+    B = np.concatenate([np.sort(rng.integers(0, 5, x)) for x in lb]).astype(np.uint32)
+    a_off = np.concatenate([[0], np.cumsum(la)]).astype(np.uint64)
+    b_off = np.concatenate([[0], np.cumsum(lb)]).astype(np.uint64)
+    Av, Bv = workloads.origin_payloads(A.size, B.size)
+    check_seg(dict(A=A, B=B, a_off=a_off, b_off=b_off, Av=Av, Bv=Bv))
 
 
 def test_reduced_batch_workload():
