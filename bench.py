@@ -176,6 +176,26 @@ def batched_leg(steps, warmup):
     }
 
 
+def copy_ceiling(dev, reps=20):
+    """Plain-copy bandwidth of this machine: cm_copy of 1 GiB, mean of reps."""
+    import torch
+    import paper_1303_4312_amd as cm
+    src = torch.empty(1 << 28, dtype=torch.uint32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        cm.copy(src, dst)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        cm.copy(src, dst)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
 def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=5000):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
     payload, uniform keys), staged in HBM before they arrive, admitted against
@@ -254,6 +274,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (use the library defaults)")
+    ap.add_argument("--no-copy-ceiling", action="store_true",
+                    help="skip measuring this box's plain-copy bandwidth")
     ap.add_argument("--serving", action="store_true",
                     help="also run the serving leg (Poisson arrivals, p50/p99)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -289,6 +313,17 @@ def main():
         cm.copy(src, dst)
         torch.cuda.synchronize()
         del src, dst
+
+    copy_gbs = None
+    if not args.no_copy_ceiling:
+        copy_gbs = copy_ceiling(dev)
+        log(f"box copy ceiling: {copy_gbs:.0f} GB/s")
+
+    tuned = None
+    if not args.no_tune:
+        # off the timed path: pick the fastest configuration on this machine
+        tuned = cm.autotune_merge(A, B, Av, Bv, reps=3)
+        log(f"autotuned choice (config, search, partition): {tuned}")
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -333,6 +368,7 @@ def main():
             "m": m, "n": n, "key": key_dtype, "payload": "uint32",
             "block": {"threads": nt, "items_per_thread": e},
             "search": ["algorithm1", "bisection"][search],
+            "autotuned": tuned is not None,
             "boundary_pass": ["one_level", "two_level_64", "two_level_16", "stream"][partition],
         },
         "roofline": {
@@ -346,6 +382,8 @@ def main():
             "kernel_ms": merge_ms,
             "co_rank_pass_ms": co_rank_ms,
             "algorithmic_bytes_per_launch": alg_bytes,
+            "box_copy_gbs": copy_gbs,
+            "frac_of_box_copy": (achieved / copy_gbs) if copy_gbs else None,
         },
         "step_hbm_frac": (alg_bytes / (elapsed / args.steps)) / 1e9 / HBM_PEAK_GBS,
     }

@@ -410,6 +410,7 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
   outs.reserve(2 * (size_t)count + 1);
   ins.reserve(4 * (size_t)count + 1);
   uint64_t blocks = 0;
+  bool vec = true;  // every array of every merge 16-byte aligned
   for (uint32_t r = 0; r < count; ++r) {
     const cm_merge_desc& q = descs_host[r];
     if (q.m + q.n < q.m) return CM_EINVAL;
@@ -419,6 +420,7 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
     if (!val && (q.A_val || q.B_val || q.C_val)) return CM_EINVAL;
     if (q.first_block != blocks) return CM_EINVAL;
     blocks += (N + T - 1) / T;
+    vec = vec && (val ? all_aligned16({q.A, q.B, q.C, q.A_val, q.B_val, q.C_val}) : all_aligned16({q.A, q.B, q.C}));
     outs.push_back({q.C, N * ks});
     if (val) outs.push_back({q.C_val, N * 4});
     ins.push_back({q.A, q.m * ks});
@@ -440,7 +442,7 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
   int rc = launch_batch_co_ranks(key_type, ch, descs_dev, count, T, total_blocks + count, bj, stream);
   if (rc != CM_OK) return rc;
   timing_mark(1, stream);
-  rc = launch_batch_merge_blocks(key_type, val, ch, descs_dev, count, bj, total_blocks, stream);
+  rc = launch_batch_merge_blocks(key_type, val, ch, descs_dev, count, bj, total_blocks, vec, stream);
   timing_mark(2, stream);
   return rc;
 }

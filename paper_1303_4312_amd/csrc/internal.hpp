@@ -8,6 +8,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <initializer_list>
+
 namespace cm {
 
 struct TileCfg {
@@ -52,6 +54,14 @@ inline uint64_t num_coarse(uint64_t nb, uint32_t stride) { return (nb - 1 + stri
 int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,
                           uint64_t n, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
 
+// Every pointer 16-byte aligned (the block merge then moves data with
+// 16-byte accesses; blocks start at multiples of 4 outputs).
+inline bool all_aligned16(std::initializer_list<const void*> ps) {
+  for (const void* p : ps)
+    if (((uintptr_t)p & 15) != 0) return false;
+  return true;
+}
+
 // Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj.
 int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
                         uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
@@ -87,7 +97,7 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
 int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
                           uint64_t* bj, hipStream_t st);
 int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
-                              const uint64_t* bj, uint64_t tiles, hipStream_t st);
+                              const uint64_t* bj, uint64_t tiles, bool vec, hipStream_t st);
 
 // Co-ranks of q arbitrary ranks.
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,

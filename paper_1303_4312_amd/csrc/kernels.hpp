@@ -119,28 +119,27 @@ __global__ __launch_bounds__(256) void k_co_rank_many(const uint64_t* __restrict
 }
 
 // Per-thread sequential stable merge of E outputs starting at window
-// position (a, b), in registers.  Takes A while A has elements left and B is
-// exhausted or A's key <= B's key (the tie rule: A first).  ka / kb hold the
-// next key of each side; one LDS read refills the side just consumed.
-// out_src[e] is the window position (0..len) the output came from, used to
-// move payloads.  Outputs at or beyond `avail` are not produced.
+// position (a, b), in registers.  sA / sB are the block's A and B windows in
+// LDS (a_len and b_len elements).  Takes A while A has elements left and B
+// is exhausted or A's key <= B's key (the tie rule: A first).  ka / kb hold
+// the next key of each side; one LDS read refills the side just consumed.
+// out_src[e] is the window position the output came from: a for A, ~b for
+// B (used to move payloads).  Outputs at or beyond `avail` are not produced.
 template <typename K, int E>
-__device__ __forceinline__ void merge_run(const K* s_key, int a_len, int len, int a, int b, int avail,
+__device__ __forceinline__ void merge_run(const K* sA, int a_len, const K* sB, int b_len, int a, int b, int avail,
                                           K (&out_key)[E], int (&out_src)[E]) {
-  const int b_len = len - a_len;
-  K ka = a < a_len ? s_key[a] : K{};
-  K kb = b < b_len ? s_key[a_len + b] : K{};
+  K ka = a < a_len ? sA[a] : K{};
+  K kb = b < b_len ? sB[b] : K{};
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     if (e < avail) {
       const bool take_a = (a < a_len) && (b >= b_len || ka <= kb);
       out_key[e] = take_a ? ka : kb;
-      out_src[e] = take_a ? a : a_len + b;
+      out_src[e] = take_a ? a : ~b;
       a += take_a ? 1 : 0;
       b += take_a ? 0 : 1;
       const bool more = take_a ? (a < a_len) : (b < b_len);
-      const int pos = take_a ? a : a_len + b;
-      const K next = more ? s_key[pos] : K{};
+      const K next = more ? (take_a ? sA[a] : sB[b]) : K{};
       if (take_a)
         ka = next;
       else
@@ -151,33 +150,50 @@ __device__ __forceinline__ void merge_run(const K* s_key, int a_len, int len, in
 
 // One block of Algorithm 2: outputs C[i0, i0 + len) from the windows
 // A[j0, j1) and B[i0 - j0, ...) (j0, j1 = co-ranks of the block's ends).
-// Called by every thread of the workgroup; ends with the block stored and
-// LDS free for reuse after a barrier.
-template <typename K, bool VAL, int NT, int E>
-__device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint32_t* __restrict__ Av,
-                                            const K* __restrict__ B, const uint32_t* __restrict__ Bv,
+// VEC (every base address 16-byte aligned, and i0 a multiple of 4): the
+// windows are staged with 16-byte loads (in a layout shifted so global and
+// LDS alignment agree) and the block leaves with 16-byte stores; otherwise
+// element by element.  s_key / s_val hold T + 16 elements.  Called by every
+// thread of the workgroup; ends with the block stored (LDS reusable after a
+// barrier).
+template <typename K, bool VAL, int NT, int E, bool VEC>
+__device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint32_t* __restrict__ Av, uint64_t m,
+                                            const K* __restrict__ B, const uint32_t* __restrict__ Bv, uint64_t n,
                                             K* __restrict__ C, uint32_t* __restrict__ Cv, uint64_t i0, int len,
                                             uint64_t j0, uint64_t j1, int search, K* s_key, uint32_t* s_val) {
   const int a_len = window_a_len(j0, j1, len);
   const int b_len = len - a_len;
-  load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, i0 - j0, a_len, len, s_key, s_val);
+  const uint64_t k0 = i0 - j0;
+  int pak = 0, pbk = a_len, pav = 0, pbv = a_len;  // window offsets in LDS
+  if constexpr (VEC) {
+    // the two windows span at most T / V + 4 vectors
+    constexpr int T = NT * E;
+    constexpr int RK = (T / kPerVec<K> + 4 + NT - 1) / NT;
+    stage_pair_vec<K, NT, RK>(A, m, j0, a_len, B, n, k0, b_len, s_key, pak, pbk);
+    if constexpr (VAL) {
+      constexpr int RV = (T / 4 + 4 + NT - 1) / NT;
+      stage_pair_vec<uint32_t, NT, RV>(Av, m, j0, a_len, Bv, n, k0, b_len, s_val, pav, pbv);
+    }
+  } else {
+    load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
+  }
   __syncthreads();
 
   const int d = std::min((int)threadIdx.x * E, len);
-  const K* sA = s_key;
-  const K* sB = s_key + a_len;
+  const K* sA = s_key + pak;
+  const K* sB = s_key + pbk;
   auto ra = [=](int x) { return sA[x]; };
   auto rb = [=](int x) { return sB[x]; };
   const int a = co_rank<K, int>(search, d, ra, a_len, rb, b_len);
   K ok[E];
   int os[E];
   const int avail = len - d;
-  merge_run<K, E>(s_key, a_len, len, a, d - a, avail, ok, os);
+  merge_run<K, E>(sA, a_len, sB, b_len, a, d - a, avail, ok, os);
   uint32_t ov[E];
   if constexpr (VAL) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
-      if (e < avail) ov[e] = s_val[os[e]];
+      if (e < avail) ov[e] = os[e] >= 0 ? s_val[pav + os[e]] : s_val[pbv + ~os[e]];
   }
   __syncthreads();
 #pragma unroll
@@ -188,7 +204,12 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
     }
   }
   __syncthreads();
-  store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+  if constexpr (VEC) {
+    store_span_vec<K, NT>(C, i0, len, s_key);
+    if constexpr (VAL) store_span_vec<uint32_t, NT>(Cv, i0, len, s_val);
+  } else {
+    store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+  }
 }
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by index.
@@ -202,7 +223,7 @@ __device__ __forceinline__ uint64_t block_order(uint64_t b, uint64_t P, int xcd)
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
-template <typename K, bool VAL, int NT, int E>
+template <typename K, bool VAL, int NT, int E, bool VEC>
 __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const uint32_t* __restrict__ Av,
                                                      uint64_t m, const K* __restrict__ B,
                                                      const uint32_t* __restrict__ Bv, uint64_t n,
@@ -210,14 +231,14 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, co
                                                      const uint64_t* __restrict__ bj, uint64_t num_tiles,
                                                      int search, int xcd) {
   constexpr int T = NT * E;
-  __shared__ K s_key[T];
-  __shared__ uint32_t s_val[VAL ? T : 1];
+  __shared__ __attribute__((aligned(16))) K s_key[T + 16];
+  __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
   const uint64_t N = m + n;
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
     const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
-    merge_block<K, VAL, NT, E>(A, Av, B, Bv, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
+    merge_block<K, VAL, NT, E, VEC>(A, Av, m, B, Bv, n, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
     if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }
@@ -475,13 +496,13 @@ __global__ __launch_bounds__(256) void k_batch_co_rank(const MergeDesc* __restri
 }
 
 // Block g of the batch is block g - first_block[r] of merge r.
-template <typename K, bool VAL, int NT, int E>
+template <typename K, bool VAL, int NT, int E, bool VEC>
 __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __restrict__ d, uint32_t count,
                                                            const uint64_t* __restrict__ bj, uint64_t num_tiles,
                                                            int search) {
   constexpr int T = NT * E;
-  __shared__ K s_key[T];
-  __shared__ uint32_t s_val[VAL ? T : 1];
+  __shared__ __attribute__((aligned(16))) K s_key[T + 16];
+  __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
   for (uint64_t g = blockIdx.x; g < num_tiles; g += gridDim.x) {
     const uint32_t r = desc_of(d, count, g, 0);
     const MergeDesc q = d[r];
@@ -489,8 +510,8 @@ __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __re
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, q.m + q.n - i0);
     const uint64_t slot = q.first_block + r + t;
-    merge_block<K, VAL, NT, E>((const K*)q.A, q.A_val, (const K*)q.B, q.B_val, (K*)q.C, q.C_val, i0, len, bj[slot],
-                               bj[slot + 1], search, s_key, s_val);
+    merge_block<K, VAL, NT, E, VEC>((const K*)q.A, q.A_val, q.m, (const K*)q.B, q.B_val, q.n, (K*)q.C, q.C_val, i0,
+                                    len, bj[slot], bj[slot + 1], search, s_key, s_val);
     if (g + gridDim.x < num_tiles) __syncthreads();
   }
 }

@@ -79,12 +79,21 @@ int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, con
     using K = decltype(key);
     return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
       constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      if (val)
-        hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st, (const K*)A,
-                           Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+      static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
+      const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
+      const dim3 g((unsigned)tiles), b(NT);
+      if (val && vec)
+        hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E, true>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv,
+                           n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+      else if (val)
+        hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E, false>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
+                           Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+      else if (vec)
+        hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E, true>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
+                           Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
       else
-        hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const K*)A, Av, m, (const K*)B, Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E, false>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
+                           Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
       return launch_status();
     });
   });
@@ -218,17 +227,24 @@ int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t coun
 }
 
 int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
-                              const uint64_t* bj, uint64_t tiles, hipStream_t st) {
+                              const uint64_t* bj, uint64_t tiles, bool vec, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
     using K = decltype(key);
     return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
       constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      if (val)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const MergeDesc*)d, count, bj, tiles, ch.search);
+      const dim3 g((unsigned)tiles), b(NT);
+      const MergeDesc* q = (const MergeDesc*)d;
+      if (val && vec)
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search);
+      else if (val)
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
+                           ch.search);
+      else if (vec)
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, true>), g, b, 0, st, q, count, bj, tiles,
+                           ch.search);
       else
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const MergeDesc*)d, count, bj, tiles, ch.search);
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
+                           ch.search);
       return launch_status();
     });
   });

@@ -141,7 +141,7 @@ __device__ __forceinline__ uint64_t co_rank_group(uint64_t i, RA A, RB B, uint64
       cand = lo + (L >> kShift) * (uint64_t)(g + 1) + (((L & (G - 1)) * (uint64_t)(g + 1)) >> kShift);
       p = cand == lo || A(cand - 1) <= B(i - cand);
     }
-    const uint64_t mask = (__ballot(p) >> base) & (G == 64 ? ~0ull : ((1ull << G) - 1));
+    const uint64_t mask = (__ballot(p) >> base) & (G == 64 ? ~0ull : ((1ull << (G & 63)) - 1));
     const int t = __popcll(mask);  // true lanes form a prefix of the group
     const uint64_t c_last_true = __shfl(cand, base + (t > 0 ? t - 1 : 0));
     const uint64_t c_first_false = __shfl(cand, base + (t < G ? t : G - 1));
@@ -216,6 +216,90 @@ __device__ __forceinline__ void store_block(K* __restrict__ C, uint32_t* __restr
       if constexpr (VAL) __builtin_nontemporal_store(s_val[x], Cv + i0 + x);
     }
   }
+}
+
+// ---- 16-byte vector paths ---------------------------------------------------
+
+typedef uint32_t vec16 __attribute__((ext_vector_type(4)));  // one 16-byte access
+
+template <typename X>
+constexpr int kPerVec = 16 / (int)sizeof(X);
+
+__device__ __forceinline__ bool aligned16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
+// Vectors that cover the span X[g0, g0 + cnt) (none when cnt == 0).
+template <typename X>
+__device__ __forceinline__ int span_vectors(uint64_t g0, int cnt) {
+  constexpr int V = kPerVec<X>;
+  return cnt ? (int)((g0 + (uint64_t)cnt + V - 1) / V - g0 / V) : 0;
+}
+
+// Loads vector q of the span starting at g0 of array X (length total, 16-byte
+// aligned base) as a whole 16-byte access; the last vector of the array may
+// be partial, and its elements past the end are not read (zero).  Elements of
+// the vector outside the span are real array elements and land in padding.
+template <typename X>
+__device__ __forceinline__ vec16 load_span_vec(const X* __restrict__ Xp, uint64_t total, uint64_t g0, int q) {
+  constexpr int V = kPerVec<X>;
+  const uint64_t first = (g0 / V + (uint64_t)q) * V;
+  if (first + V <= total) return __builtin_nontemporal_load((const vec16*)(Xp + first));
+  union {
+    vec16 v;
+    X e[V];
+  } u;
+  u.v = vec16{0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < V; ++k)
+    if (first + k < total) u.e[k] = Xp[first + k];
+  return u.v;
+}
+
+// Stages the windows X_A[ga, ga + na) and X_B[gb, gb + nb) of one array pair
+// in LDS with 16-byte loads and LDS writes.  Element ga + x of the A window
+// lands at dst[pa + x] with pa = ga % V, element gb + y of the B window at
+// dst[pb + y] with pb = roundup(pa + na, V) + gb % V, so every aligned
+// global vector maps onto an aligned LDS vector.  dst must hold
+// na + nb + 3 V elements.  R = vectors per thread (compile-time bound).
+template <typename X, int NT, int R>
+__device__ __forceinline__ void stage_pair_vec(const X* __restrict__ XA, uint64_t totA, uint64_t ga, int na,
+                                               const X* __restrict__ XB, uint64_t totB, uint64_t gb, int nb,
+                                               X* dst, int& pa, int& pb) {
+  constexpr int V = kPerVec<X>;
+  pa = (int)(ga % V);
+  const int rb = (pa + na + V - 1) / V * V;  // first LDS vector slot of the B window
+  pb = rb + (int)(gb % V);
+  const int nva = span_vectors<X>(ga, na);
+  const int nvb = span_vectors<X>(gb, nb);
+  vec16 reg[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = (int)threadIdx.x + r * NT;
+    if (q < nva)
+      reg[r] = load_span_vec(XA, totA, ga, q);
+    else if (q < nva + nvb)
+      reg[r] = load_span_vec(XB, totB, gb, q - nva);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int q = (int)threadIdx.x + r * NT;
+    if (q < nva)
+      *(vec16*)(dst + q * V) = reg[r];
+    else if (q < nva + nvb)
+      *(vec16*)(dst + rb + (q - nva) * V) = reg[r];
+  }
+}
+
+// Stores dst[0, len) (LDS, output order) to G[i0, i0 + len) with 16-byte
+// stores (G + i0 16-byte aligned, dst 16-byte aligned); the tail of fewer
+// than V elements element by element.
+template <typename X, int NT>
+__device__ __forceinline__ void store_span_vec(X* __restrict__ G, uint64_t i0, int len, const X* src) {
+  constexpr int V = kPerVec<X>;
+  const int nv = len / V;
+  for (int q = (int)threadIdx.x; q < nv; q += NT)
+    __builtin_nontemporal_store(*(const vec16*)(src + q * V), (vec16*)(G + i0 + (uint64_t)q * V));
+  const int x = nv * V + (int)threadIdx.x;
+  if (x < len) __builtin_nontemporal_store(src[x], G + i0 + x);
 }
 
 }  // namespace cm

@@ -132,7 +132,10 @@ class GpuExecutor:
                 m = np.array([r.A.numel() for r in reqs], dtype=np.uint64)
                 n = np.array([r.B.numel() for r in reqs], dtype=np.uint64)
                 N = m + n
-                off = np.concatenate([[0], np.cumsum(N)]).astype(np.uint64)
+                # each request's outputs start 16-byte aligned (4 elements), so the
+                # kernel can use 16-byte accesses when the inputs are aligned too
+                padded = (N + np.uint64(3)) // np.uint64(4) * np.uint64(4)
+                off = np.concatenate([[0], np.cumsum(padded)]).astype(np.uint64)
                 keys = torch.empty(int(off[-1]), dtype=dtype, device=self.device)
                 vals = torch.empty(int(off[-1]), dtype=torch.uint32, device=self.device) \
                     if with_val else None
@@ -148,7 +151,7 @@ class GpuExecutor:
                     d["C_val"] = np.where(N > 0, vals.data_ptr() + off[:-1] * 4, 0)
                 keep.append(launch_batch(dtype, with_val, d, self.device, s))
                 for k, i in enumerate(idx):
-                    a, b = int(off[k]), int(off[k + 1])
+                    a, b = int(off[k]), int(off[k] + N[k])
                     outs[i] = (keys[a:b], vals[a:b]) if with_val else keys[a:b]
             ev = torch.cuda.Event()
             ev.record(s)
