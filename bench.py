@@ -121,7 +121,7 @@ def cpu_baseline_leg(d, C_gpu, Cv_gpu, seconds):
     }, exact
 
 
-def batched_leg(steps, warmup):
+def batched_leg(steps, warmup, tune):
     """65536 independent merges, sides log-uniform in [1, 2^16]: one batched
     call (co-rank pass + one block-merge launch) against one single-merge call
     per segment; outputs compared byte for byte."""
@@ -141,6 +141,10 @@ def batched_leg(steps, warmup):
     Cv = torch.empty(n, dtype=torch.uint32, device=dev)
     ws = torch.empty(cm.segmented_workspace_size("uint32", True, A.numel(), B.numel(),
                                                  a_off.numel() - 1), dtype=torch.uint8, device=dev)
+    tuned = cm.autotune_segmented(A, a_off, B, b_off, Av, Bv, reps=3) if tune else None
+    if tuned is not None:
+        log(f"batched: autotuned choice (config, search, partition): {tuned}")
+    choice = cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, n)
     for _ in range(warmup):
         cm.stable_merge_segmented(A, a_off, B, b_off, Av, Bv, C, Cv, workspace=ws)
     torch.cuda.synchronize()
@@ -168,6 +172,8 @@ def batched_leg(steps, warmup):
         "outputs": n,
         "batched_keys_per_s": n / t_batch,
         "batched_ms": t_batch * 1e3,
+        "choice": {"config": list(cm.config_info(choice[0])), "search": choice[1],
+                   "partition": choice[2], "autotuned": tuned is not None},
         "per_merge_keys_per_s": n / t_each,
         "per_merge_ms": t_each * 1e3,
         "per_merge_launches": 2 * (a_off.numel() - 1),
@@ -402,7 +408,8 @@ def main():
     if not args.no_batched:
         del A, Av, B, Bv, C, Cv, ws
         torch.cuda.empty_cache()
-        result["batched"] = batched_leg(steps=max(3, min(args.steps, 20)), warmup=2)
+        result["batched"] = batched_leg(steps=max(3, min(args.steps, 20)), warmup=2,
+                                        tune=not args.no_tune)
 
     if args.serving:
         torch.cuda.empty_cache()

@@ -146,3 +146,21 @@ def test_reduced_batch_workload():
     4096 segments of up to 2**12 per side."""
     d = workloads.segmented(num_seg=4096, max_side=1 << 12)
     check_seg(d)
+
+
+@pytest.mark.parametrize("offset", [1, 2])
+def test_misaligned_bases_segmented(offset):
+    """Bases off 16-byte alignment take the element-wise staging path."""
+    d = workloads.segmented(seed=19, num_seg=900, max_side=1 << 11, min_side=0)
+    C, Cv = cm.stable_merge_segmented(to_dev(d["A"], offset), to_dev(d["a_off"]),
+                                      to_dev(d["B"], offset), to_dev(d["b_off"]),
+                                      to_dev(d["Av"], offset), to_dev(d["Bv"], offset))
+    Ce, Cve = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
+                                            d["Bv"])
+    assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+    for dtype in (np.uint64, np.float32):
+        e = as_dtype(d, dtype)
+        C = cm.stable_merge_segmented(to_dev(e["A"], offset), to_dev(e["a_off"]),
+                                      to_dev(e["B"], offset), to_dev(e["b_off"]))
+        assert same_bits(to_host(C), oracle.stable_merge_segmented(e["A"], e["a_off"], e["B"],
+                                                                   e["b_off"]))
