@@ -24,6 +24,7 @@ import hashlib
 import json
 import os
 import re
+import statistics
 import sys
 import time
 
@@ -72,10 +73,10 @@ def workload_inputs(name):
     return d, desc
 
 
-def read_traffic(alg_bytes):
-    """Measured HBM bytes per launch of the block-merge kernel from the
-    committed rocprofv3 counter summary, if it was taken on this kernel
-    source; else None."""
+def read_traffic(alg_bytes, nt, e):
+    """Measured HBM bytes per launch of the block-merge kernel in tile
+    configuration nt x e, from the committed rocprofv3 counter summary of
+    this workload, if it was taken on this kernel source; else None."""
     if not os.path.exists(COUNTERS_FILE):
         return None
     text = open(COUNTERS_FILE).read()
@@ -85,7 +86,10 @@ def read_traffic(alg_bytes):
     rec = json.loads(m.group(1))
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("traffic_bytes_per_launch")
+    if rec.get("algorithmic_bytes_per_launch") != alg_bytes:
+        return None
+    row = rec.get("per_config", {}).get(f"{nt}x{e}")
+    return None if row is None else row["traffic_bytes_per_launch"]
 
 
 def cpu_baseline_leg(d, C_gpu, Cv_gpu, seconds):
@@ -153,7 +157,19 @@ def batched_leg(steps, warmup, tune):
         cm.stable_merge_segmented(A, a_off, B, b_off, Av, Bv, C, Cv, workspace=ws)
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / steps
-    log(f"batched: {t_batch * 1e3:.3f} ms per batch; running per-merge launches")
+    log(f"batched: {t_batch * 1e3:.3f} ms per batch; replaying a graph plan")
+    plan = cm.plan_segmented(A, a_off, B, b_off, Av, Bv, workspace=ws)
+    for _ in range(warmup):
+        plan.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.launch()
+    torch.cuda.synchronize()
+    t_plan = (time.perf_counter() - t0) / steps
+    same_plan = bool(torch.equal(plan.C, C) and torch.equal(plan.C_val, Cv))
+    plan.close()
+    log(f"batched: plan {t_plan * 1e3:.3f} ms per replay; running per-merge launches")
     C2 = torch.empty_like(C)
     Cv2 = torch.empty_like(Cv)
     cm.stable_merge_segmented_each(A, d["a_off"], B, d["b_off"], Av, Bv, C2, Cv2)
@@ -172,6 +188,9 @@ def batched_leg(steps, warmup, tune):
         "outputs": n,
         "batched_keys_per_s": n / t_batch,
         "batched_ms": t_batch * 1e3,
+        "plan_replay_ms": t_plan * 1e3,
+        "plan_replay_keys_per_s": n / t_plan,
+        "plan_identical_output": same_plan,
         "choice": {"config": list(cm.config_info(choice[0])), "search": choice[1],
                    "partition": choice[2], "autotuned": tuned is not None},
         "per_merge_keys_per_s": n / t_each,
@@ -179,6 +198,45 @@ def batched_leg(steps, warmup, tune):
         "per_merge_launches": 2 * (a_off.numel() - 1),
         "speedup": t_each / t_batch,
         "identical_output": same,
+    }
+
+
+def latency_leg(reps=200, warmup=20):
+    """Small single merge, m = n = 2^20 uint32 keys uniform in [0, 2^16) with
+    payloads: it fits in the Infinity Cache, so this is a warm-cache latency
+    figure, not a roofline one.  Per-call device time from the library's
+    HIP events; the wall rate is back-to-back calls on one stream."""
+    import torch
+    import paper_1303_4312_amd as cm
+    from paper_1303_4312_amd import workloads as w
+    d = w.dup16()
+    dev = torch.device("cuda:0")
+    A, Av, B, Bv = (torch.from_numpy(d[k]).to(dev) for k in ("A", "Av", "B", "Bv"))
+    N = A.numel() + B.numel()
+    C = torch.empty(N, dtype=A.dtype, device=dev)
+    Cv = torch.empty(N, dtype=torch.uint32, device=dev)
+    ws = torch.empty(cm.merge_workspace_size("uint32", True, A.numel(), B.numel()),
+                     dtype=torch.uint8, device=dev)
+    for _ in range(warmup):
+        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws)
+    torch.cuda.synchronize()
+    cm.timing_start(reps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    _, _, _, call_each, merge_each = cm.timing_stop(per_call=True)
+    med = statistics.median(call_each)
+    return {
+        "workload": "single merge m=n=2^20, uint32 keys uniform in [0,2^16), uint32 payloads "
+                    "(warm cache)",
+        "outputs": N,
+        "call_us_median": med * 1e3,
+        "call_us_min": min(call_each) * 1e3,
+        "merge_kernel_us_median": statistics.median(merge_each) * 1e3,
+        "keys_per_s_at_median": N / (med * 1e-3),
+        "wall_us_per_call": wall * 1e6,
     }
 
 
@@ -202,7 +260,8 @@ def copy_ceiling(dev, reps=20):
     return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
-def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=5000):
+def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.1),
+                seed=5000):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
     payload, uniform keys), staged in HBM before they arrive, admitted against
     a 32 GiB budget and batched on the fly.  First a closed loop (all
@@ -222,7 +281,7 @@ def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=50
     budget = 32 << 30
 
     def run(arrivals):
-        ex = serve.GpuExecutor(dev)
+        ex = serve.GpuExecutor(dev, timed=True)
         srv = serve.Server(ex, budget_bytes=budget, max_batch=64, max_inflight=2)
         torch.cuda.synchronize()
         with srv:
@@ -238,7 +297,11 @@ def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=50
                 futs.append(srv.submit(*pool[k % pool_size], arrival=target))
             for f in futs:
                 f.result(timeout=120)
-        return srv.stats()
+        st = srv.stats()
+        busy_ms, _ = ex.busy_ms()
+        wall_ms = (srv.last_done - srv.first_arrival) * 1e3
+        st["gpu_busy_fraction"] = busy_ms / wall_ms if wall_ms > 0 else None
+        return st
 
     sys.setswitchinterval(1e-4)  # let the scheduler thread in often
     warm = run([0.0] * per_point)  # warm-up: first launches, allocator caches
@@ -254,9 +317,10 @@ def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=50
         points.append({"rate_per_s": lam, "fraction_of_saturation": frac,
                        "keys_per_s": st["keys_per_s"], "p50_ms": st["p50_s"] * 1e3,
                        "p99_ms": st["p99_s"] * 1e3, "mean_batch": st["mean_batch"],
-                       "max_concurrent_batches": st["max_concurrent_batches"]})
+                       "max_concurrent_batches": st["max_concurrent_batches"],
+                       "gpu_busy_fraction": st["gpu_busy_fraction"]})
         log(f"serving: rate {lam:.0f}/s p50 {st['p50_s'] * 1e3:.3f} ms "
-            f"p99 {st['p99_s'] * 1e3:.3f} ms")
+            f"p99 {st['p99_s'] * 1e3:.3f} ms busy {st['gpu_busy_fraction']:.2f}")
     del warm
     return {
         "workload": ("requests with sides log-uniform in [2^10,2^24], uint32 keys uniform, "
@@ -266,7 +330,8 @@ def serving_leg(pool_size=16, per_point=200, fractions=(0.5, 0.8, 0.95), seed=50
         "mean_outputs_per_request": float(np.mean(sizes)),
         "saturation": {"requests_per_s": sat_rate, "keys_per_s": sat["keys_per_s"],
                        "p50_ms": sat["p50_s"] * 1e3, "p99_ms": sat["p99_s"] * 1e3,
-                       "mean_batch": sat["mean_batch"]},
+                       "mean_batch": sat["mean_batch"],
+                       "gpu_busy_fraction": sat["gpu_busy_fraction"]},
         "points": points,
     }
 
@@ -284,8 +349,10 @@ def main():
                     help="skip the autotuner (use the library defaults)")
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip measuring this box's plain-copy bandwidth")
-    ap.add_argument("--serving", action="store_true",
-                    help="also run the serving leg (Poisson arrivals, p50/p99)")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the small warm-cache latency leg")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving leg (Poisson arrivals, p50/p99)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one cm_copy of 1 GiB (for counter calibration)")
     args = ap.parse_args()
@@ -344,7 +411,7 @@ def main():
         cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    calls, co_rank_ms, merge_ms = cm.timing_stop()
+    calls, co_rank_ms, merge_ms, call_each, merge_each = cm.timing_stop(per_call=True)
     assert calls == args.steps
     value = N * args.steps / elapsed
     log(f"{elapsed / args.steps * 1e3:.3f} ms/step; merge kernel {merge_ms:.3f} ms, "
@@ -353,9 +420,10 @@ def main():
     per_elem = 2 * (key_bytes + 4)           # read + write one key and one payload
     alg_bytes = N * per_elem
     achieved = alg_bytes / (merge_ms * 1e-3) / 1e9
-    traffic = read_traffic(alg_bytes)
     cfg, search, partition = cm.tuning_get(cm.OP_MERGE, key_dtype, True, N)
     nt, e = cm.config_info(cfg)
+    streaming = partition == 3
+    traffic = None if streaming else read_traffic(alg_bytes, nt, e)
     result = {
         "metric": METRIC,
         "value": value,
@@ -384,13 +452,18 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_merge_blocks",
+            "kernel": "k_merge_stream" if streaming else "k_merge_blocks",
             "kernel_ms": merge_ms,
             "co_rank_pass_ms": co_rank_ms,
             "algorithmic_bytes_per_launch": alg_bytes,
             "box_copy_gbs": copy_gbs,
             "frac_of_box_copy": (achieved / copy_gbs) if copy_gbs else None,
+            "kernel_ms_median": statistics.median(merge_each),
+            "kernel_ms_min": min(merge_each),
         },
+        "call_ms": {"mean": statistics.mean(call_each), "median": statistics.median(call_each),
+                    "min": min(call_each), "note": "one library call, first kernel start to "
+                    "block-merge end, HIP events on the call's stream"},
         "step_hbm_frac": (alg_bytes / (elapsed / args.steps)) / 1e9 / HBM_PEAK_GBS,
     }
 
@@ -405,13 +478,16 @@ def main():
         result["cpu_baseline"] = None
         result["bit_exact"] = None
 
+    if not args.no_latency:
+        result["latency"] = latency_leg()
+
     if not args.no_batched:
         del A, Av, B, Bv, C, Cv, ws
         torch.cuda.empty_cache()
         result["batched"] = batched_leg(steps=max(3, min(args.steps, 20)), warmup=2,
                                         tune=not args.no_tune)
 
-    if args.serving:
+    if not args.no_serving:
         torch.cuda.empty_cache()
         result["serving"] = serving_leg()
 

@@ -394,12 +394,16 @@ int cm_stable_merge_segmented_each(int key_type,
  *   or timing is already on.
  * cm_timing_stop: waits for the recorded events, writes the number of timed
  *   calls and the mean duration in milliseconds of the co-rank pass and of
- *   the block-merge kernel over them (either output may be NULL), and
- *   releases the events.  CM_EINVAL if timing is off.
+ *   the block-merge kernel over them, and releases the events.  If call_ms
+ *   / merge_ms are given (host arrays of at least `capacity` floats), entry
+ *   c receives call c's whole duration (first event to last) / its
+ *   block-merge kernel's duration, in milliseconds.  Every output may be
+ *   NULL.  CM_EINVAL if timing is off.
  */
 int cm_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 int cm_timing_start(uint32_t capacity);
-int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean);
+int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean, float *call_ms,
+                   float *merge_ms);
 
 #ifdef __cplusplus
 }

@@ -123,7 +123,8 @@ def load():
         "cm_plan_destroy": (c_int, [vp]),
         "cm_timing_start": (c_int, [ctypes.c_uint32]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
-                                   ctypes.POINTER(ctypes.c_double)]),
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
+                                   ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -364,17 +365,30 @@ def copy(src, dst, stream=None):
     _check(load().cm_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream, src.device)), "cm_copy")
 
 
+_timing_capacity = [0]
+
+
 def timing_start(capacity: int):
     """Record kernel events around the next `capacity` merge calls."""
     _check(load().cm_timing_start(capacity), "cm_timing_start")
+    _timing_capacity[0] = capacity
 
 
-def timing_stop():
-    """Returns (calls, mean co-rank pass ms, mean block-merge kernel ms)."""
+def timing_stop(per_call=False):
+    """Returns (calls, mean co-rank pass ms, mean block-merge kernel ms); with
+    per_call, also the lists of each call's whole duration and block-merge
+    kernel duration (ms)."""
     calls, tb, tm = ctypes.c_uint32(), ctypes.c_double(), ctypes.c_double()
-    _check(load().cm_timing_stop(ctypes.byref(calls), ctypes.byref(tb), ctypes.byref(tm)),
+    cap = _timing_capacity[0] if per_call else 0
+    call_ms = (ctypes.c_float * max(cap, 1))()
+    merge_ms = (ctypes.c_float * max(cap, 1))()
+    _check(load().cm_timing_stop(ctypes.byref(calls), ctypes.byref(tb), ctypes.byref(tm),
+                                 call_ms if per_call else None, merge_ms if per_call else None),
            "cm_timing_stop")
-    return calls.value, tb.value, tm.value
+    if not per_call:
+        return calls.value, tb.value, tm.value
+    return (calls.value, tb.value, tm.value, list(call_ms[:calls.value]),
+            list(merge_ms[:calls.value]))
 
 
 def check_sorted(X, stream=None) -> bool:

@@ -807,7 +807,8 @@ int cm_timing_start(uint32_t capacity) {
   return CM_OK;
 }
 
-int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_mean) {
+int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_mean, float* call_ms,
+                   float* merge_ms) {
   if (!g_timing.on && !g_timing.ev) return CM_EINVAL;
   double sum_b = 0, sum_m = 0;
   int rc = CM_OK;
@@ -819,6 +820,8 @@ int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_me
       rc = CM_EHIP;
     sum_b += tb;
     sum_m += tm;
+    if (call_ms) call_ms[c] = tb + tm;
+    if (merge_ms) merge_ms[c] = tm;
   }
   if (calls) *calls = g_timing.used;
   if (co_rank_ms_mean) *co_rank_ms_mean = g_timing.used ? sum_b / g_timing.used : 0.0;

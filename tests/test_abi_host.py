@@ -260,3 +260,12 @@ def test_batch_prepare_and_argument_errors():
     assert lib.cm_stable_merge_batch(0, 0, pay.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
                                      total.value, P(0x2000), need, None) == EINVAL
     assert lib.cm_stable_merge_batch(0, 0, None, None, 0, 0, None, 0, None) == OK
+
+
+def test_timing_argument_errors():
+    lib = cm.load()
+    u = ctypes.c_uint32()
+    d = ctypes.c_double()
+    assert lib.cm_timing_start(0) == EINVAL
+    assert lib.cm_timing_stop(ctypes.byref(u), ctypes.byref(d), ctypes.byref(d), None,
+                              None) == EINVAL

@@ -104,3 +104,23 @@ def test_per_merge_launch_form_matches_batch():
     Ce, Cve = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
                                             d["Bv"])
     assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+
+
+def test_timing_events_per_call():
+    import torch
+    d = workloads.zipf(m=1_000_000, n=300_001)
+    A, Av, B, Bv = (to_dev(d[k]) for k in ("A", "Av", "B", "Bv"))
+    cm.timing_start(5)
+    for _ in range(3):
+        C, Cv = cm.stable_merge_pairs(A, Av, B, Bv)
+    torch.cuda.synchronize()
+    calls, co_rank_ms, merge_ms, call_each, merge_each = cm.timing_stop(per_call=True)
+    assert calls == 3 and len(call_each) == 3 and len(merge_each) == 3
+    assert co_rank_ms > 0 and merge_ms > 0
+    assert all(c >= m > 0 for c, m in zip(call_each, merge_each))
+    assert abs(sum(merge_each) / 3 - merge_ms) <= 1e-3 * merge_ms + 1e-6
+    Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+    assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+    # off again: a second stop is an error
+    with pytest.raises(cm.CMError):
+        cm.timing_stop()
