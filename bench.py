@@ -12,8 +12,9 @@ Output: one JSON line with merged keys/s (whole job), the roofline of the
 block-merge kernel (algorithmic bytes = read m + n and write m + n elements,
 over its mean duration from HIP events recorded by the library on the
 stream it launches on), the CPU oracle timed on the host beside it
-(bit-exactness of the GPU output is checked in that leg), and the batched
-segmented merge against one launch pair per merge on the batch workload.
+(bit-exactness of the GPU output is checked in that leg), a small
+warm-cache latency leg, the batched segmented merge against one library call
+per merge on the batch workload, and the serving leg.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -195,7 +196,9 @@ def batched_leg(steps, warmup, tune):
                    "partition": choice[2], "autotuned": tuned is not None},
         "per_merge_keys_per_s": n / t_each,
         "per_merge_ms": t_each * 1e3,
-        "per_merge_launches": 2 * (a_off.numel() - 1),
+        "per_merge_calls": a_off.numel() - 1,
+        "per_merge_note": ("one cm_stable_merge_pairs call per merge on its sub-arrays, default "
+                           "choice per size (below 2^22 outputs: one kernel launch per call)"),
         "speedup": t_each / t_batch,
         "identical_output": same,
     }
@@ -204,8 +207,10 @@ def batched_leg(steps, warmup, tune):
 def latency_leg(reps=200, warmup=20):
     """Small single merge, m = n = 2^20 uint32 keys uniform in [0, 2^16) with
     payloads: it fits in the Infinity Cache, so this is a warm-cache latency
-    figure, not a roofline one.  Per-call device time from the library's
-    HIP events; the wall rate is back-to-back calls on one stream."""
+    figure, not a roofline one.  Three views: back-to-back library calls on
+    one stream (wall clock per call, no timing events), back-to-back replays
+    of a graph plan of the same call, and the device time of one call from
+    the library's HIP events (each event boundary adds a few microseconds)."""
     import torch
     import paper_1303_4312_amd as cm
     from paper_1303_4312_amd import workloads as w
@@ -217,26 +222,38 @@ def latency_leg(reps=200, warmup=20):
     Cv = torch.empty(N, dtype=torch.uint32, device=dev)
     ws = torch.empty(cm.merge_workspace_size("uint32", True, A.numel(), B.numel()),
                      dtype=torch.uint8, device=dev)
-    for _ in range(warmup):
-        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws)
-    torch.cuda.synchronize()
+
+    def wall(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    t_call = wall(lambda: cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws))
+    plan = cm.plan_merge(A, B, Av, Bv, C, Cv, workspace=ws)
+    t_plan = wall(plan.launch)
+    plan.close()
     cm.timing_start(reps)
-    t0 = time.perf_counter()
     for _ in range(reps):
         cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws)
     torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / reps
-    _, _, _, call_each, merge_each = cm.timing_stop(per_call=True)
-    med = statistics.median(call_each)
+    _, _, _, _, call_each, merge_each = cm.timing_stop(per_call=True)
+    cfg, search, partition = cm.tuning_get(cm.OP_MERGE, "uint32", True, N)
     return {
         "workload": "single merge m=n=2^20, uint32 keys uniform in [0,2^16), uint32 payloads "
                     "(warm cache)",
         "outputs": N,
-        "call_us_median": med * 1e3,
-        "call_us_min": min(call_each) * 1e3,
-        "merge_kernel_us_median": statistics.median(merge_each) * 1e3,
-        "keys_per_s_at_median": N / (med * 1e-3),
-        "wall_us_per_call": wall * 1e6,
+        "choice": {"config": list(cm.config_info(cfg)), "search": search, "partition": partition},
+        "wall_us_per_call": t_call * 1e6,
+        "keys_per_s_back_to_back": N / t_call,
+        "wall_us_per_plan_replay": t_plan * 1e6,
+        "event_call_us_median": statistics.median(call_each) * 1e3,
+        "event_call_us_min": min(call_each) * 1e3,
+        "event_merge_kernel_us_median": statistics.median(merge_each) * 1e3,
     }
 
 
@@ -260,6 +277,19 @@ def copy_ceiling(dev, reps=20):
     return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
+def interval_union(starts, durations):
+    """Total length covered by the intervals [start, start + duration)."""
+    total, lo, hi = 0.0, None, None
+    for a, d in sorted(zip(starts, durations)):
+        if hi is None or a > hi:
+            if hi is not None:
+                total += hi - lo
+            lo, hi = a, a + d
+        else:
+            hi = max(hi, a + d)
+    return total + (hi - lo if hi is not None else 0.0)
+
+
 def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.1),
                 seed=5000):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
@@ -269,6 +299,7 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
     fractions of it.  Latency is arrival to completion seen by the server."""
     import numpy as np
     import torch
+    import paper_1303_4312_amd as cm
     from paper_1303_4312_amd import serve, workloads as w
 
     log(f"serving: generating {pool_size} requests")
@@ -281,9 +312,10 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
     budget = 32 << 30
 
     def run(arrivals):
-        ex = serve.GpuExecutor(dev, timed=True)
+        ex = serve.GpuExecutor(dev)
         srv = serve.Server(ex, budget_bytes=budget, max_batch=64, max_inflight=2)
         torch.cuda.synchronize()
+        cm.timing_start(len(arrivals) + 8)  # device interval of every batch call
         with srv:
             t0 = time.perf_counter()
             futs = []
@@ -298,9 +330,9 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
             for f in futs:
                 f.result(timeout=120)
         st = srv.stats()
-        busy_ms, _ = ex.busy_ms()
+        _, _, _, starts, durs, _ = cm.timing_stop(per_call=True)
         wall_ms = (srv.last_done - srv.first_arrival) * 1e3
-        st["gpu_busy_fraction"] = busy_ms / wall_ms if wall_ms > 0 else None
+        st["gpu_busy_fraction"] = interval_union(starts, durs) / wall_ms if wall_ms > 0 else None
         return st
 
     sys.setswitchinterval(1e-4)  # let the scheduler thread in often
@@ -411,7 +443,7 @@ def main():
         cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    calls, co_rank_ms, merge_ms, call_each, merge_each = cm.timing_stop(per_call=True)
+    calls, co_rank_ms, merge_ms, _, call_each, merge_each = cm.timing_stop(per_call=True)
     assert calls == args.steps
     value = N * args.steps / elapsed
     log(f"{elapsed / args.steps * 1e3:.3f} ms/step; merge kernel {merge_ms:.3f} ms, "
@@ -443,7 +475,8 @@ def main():
             "block": {"threads": nt, "items_per_thread": e},
             "search": ["algorithm1", "bisection"][search],
             "autotuned": tuned is not None,
-            "boundary_pass": ["one_level", "two_level_64", "two_level_16", "stream"][partition],
+            "boundary_pass": ["one_level", "two_level_64", "two_level_16", "stream",
+                               "in_block"][partition],
         },
         "roofline": {
             "bound": "hbm",

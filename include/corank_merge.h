@@ -244,17 +244,21 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     bisection over the diagonal (default).  Both return the unique pair
  *     of Lemma 1.
  *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
- *     0 = one GPU thread per boundary over the whole diagonal; 1 = two
- *     levels: every coarse boundary by a whole wave with a 64-ary search,
- *     then the others by bisection between their two coarse neighbours;
- *     2 (default) = two levels with 16 lanes (a 16-ary search) per coarse
- *     boundary; 3 = Algorithm 2 with one block per resident workgroup:
+ *     -1 (default) = automatic: mode 4 for single merges of fewer than
+ *     2^22 outputs, else mode 2; 0 = one GPU thread per boundary over the
+ *     whole diagonal; 1 = two levels: every coarse boundary by a whole wave
+ *     with a 64-ary search, then the others by bisection between their two
+ *     coarse neighbours; 2 = two levels with 16 lanes (a 16-ary search) per
+ *     coarse boundary; 3 = Algorithm 2 with one block per resident workgroup:
  *     only those P + 1 boundaries are co-ranked (a whole wave each), and
  *     each workgroup merges its whole block in steps through LDS ring
- *     buffers (single merges only).  The segmented batch uses two levels
- *     (segment search and co-rank narrowed by coarse neighbours) for any
- *     nonzero mode and one level for 0; the batch of separate merges always
- *     uses one level.  All give the same results.
+ *     buffers (single merges only); 4 = no boundary pass: every block
+ *     co-ranks its own two ends (a whole wave each, 64-ary search) and then
+ *     merges, as Algorithm 2 has every processing element do (single merges
+ *     only; saves a launch on small merges).  The segmented batch uses two
+ *     levels (segment search and co-rank narrowed by coarse neighbours) for
+ *     any nonzero mode and one level for 0; the batch of separate merges
+ *     always uses one level.  All give the same results.
  *   cm_set_coarse_stride: blocks between coarse boundaries of the two-level
  *     pass (default 64; at least 16).
  *   cm_set_block_order: 1 (default) hands each of the chip's 8 XCDs a
@@ -394,16 +398,17 @@ int cm_stable_merge_segmented_each(int key_type,
  *   or timing is already on.
  * cm_timing_stop: waits for the recorded events, writes the number of timed
  *   calls and the mean duration in milliseconds of the co-rank pass and of
- *   the block-merge kernel over them, and releases the events.  If call_ms
- *   / merge_ms are given (host arrays of at least `capacity` floats), entry
- *   c receives call c's whole duration (first event to last) / its
- *   block-merge kernel's duration, in milliseconds.  Every output may be
- *   NULL.  CM_EINVAL if timing is off.
+ *   the block-merge kernel over them, and releases the events.  If
+ *   call_start_ms / call_ms / merge_ms are given (host arrays of at least
+ *   `capacity` floats), entry c receives call c's start relative to call
+ *   0's start / its whole duration (first event to last) / its block-merge
+ *   kernel's duration, in milliseconds (calls on different streams may
+ *   overlap).  Every output may be NULL.  CM_EINVAL if timing is off.
  */
 int cm_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 int cm_timing_start(uint32_t capacity);
-int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean, float *call_ms,
-                   float *merge_ms);
+int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean,
+                   float *call_start_ms, float *call_ms, float *merge_ms);
 
 #ifdef __cplusplus
 }

@@ -124,7 +124,7 @@ def load():
         "cm_timing_start": (c_int, [ctypes.c_uint32]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
-                                   ctypes.POINTER(ctypes.c_float)]),
+                                   ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -376,19 +376,16 @@ def timing_start(capacity: int):
 
 def timing_stop(per_call=False):
     """Returns (calls, mean co-rank pass ms, mean block-merge kernel ms); with
-    per_call, also the lists of each call's whole duration and block-merge
-    kernel duration (ms)."""
+    per_call, also the lists of each call's start (ms after call 0's start),
+    whole duration and block-merge kernel duration (ms)."""
     calls, tb, tm = ctypes.c_uint32(), ctypes.c_double(), ctypes.c_double()
-    cap = _timing_capacity[0] if per_call else 0
-    call_ms = (ctypes.c_float * max(cap, 1))()
-    merge_ms = (ctypes.c_float * max(cap, 1))()
+    cap = max(_timing_capacity[0] if per_call else 0, 1)
+    arrays = [(ctypes.c_float * cap)() for _ in range(3)]
     _check(load().cm_timing_stop(ctypes.byref(calls), ctypes.byref(tb), ctypes.byref(tm),
-                                 call_ms if per_call else None, merge_ms if per_call else None),
-           "cm_timing_stop")
+                                 *(a if per_call else None for a in arrays)), "cm_timing_stop")
     if not per_call:
         return calls.value, tb.value, tm.value
-    return (calls.value, tb.value, tm.value, list(call_ms[:calls.value]),
-            list(merge_ms[:calls.value]))
+    return (calls.value, tb.value, tm.value) + tuple(list(a[:calls.value]) for a in arrays)
 
 
 def check_sorted(X, stream=None) -> bool:
@@ -431,8 +428,11 @@ def get_search() -> int:
 
 
 def set_partition(mode: int):
-    """Block-boundary pass: 0 = one thread per boundary, 1 = two-level with a
-    64-lane coarse search, 2 = two-level with a 16-lane coarse search."""
+    """Block-boundary pass: -1 = automatic (the default: 4 below 2^22
+    outputs for a single merge, else 2), 0 = one thread per boundary, 1 = two-level with a
+    64-lane coarse search, 2 = two-level with a 16-lane coarse search, 3 =
+    one block per resident workgroup (streaming), 4 = no pass, each block
+    co-ranks its own ends."""
     _check(load().cm_set_partition(mode), "cm_set_partition")
 
 

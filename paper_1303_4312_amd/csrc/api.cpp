@@ -26,7 +26,7 @@ namespace {
 struct Settings {
   int cfg[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [key type][payload] default configuration
   int search = 1;                             // bisection
-  int partition = 2;                          // two-level boundary pass, 16-lane coarse search
+  int partition = -1;                         // automatic (see resolve)
   Shape shape;                                // coarse stride, block order
 };
 Settings g_set;
@@ -49,7 +49,10 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
     auto it = g_tuning.find(TuneKey{op, kt, val ? 1 : 0, size_class(N)});
     if (it != g_tuning.end()) return it->second.ch;
   }
-  return Choice{g_set.cfg[kt][val ? 1 : 0], g_set.search, g_set.partition};
+  int part = g_set.partition;
+  if (part < 0)  // automatic: below 2^22 outputs a single merge skips the boundary pass
+    part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
+  return Choice{g_set.cfg[kt][val ? 1 : 0], g_set.search, part};
 }
 
 // ---------------------------------------------------------------------------
@@ -170,6 +173,13 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
     if (rc != CM_OK) return rc;
     timing_mark(1, st);
     rc = launch_merge_stream(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, bj, P, st);
+    timing_mark(2, st);
+    return rc;
+  }
+  if (ch.partition == 4) {  // every block co-ranks its own ends: no boundary pass
+    timing_mark(0, st);
+    timing_mark(1, st);
+    const int rc = launch_merge_blocks(kt, val, ch, g_set.shape, A, Av, m, B, Bv, n, C, Cv, nullptr, tiles, st);
     timing_mark(2, st);
     return rc;
   }
@@ -485,7 +495,7 @@ int cm_set_search(int search_mode) {
 int cm_get_search(void) { return g_set.search; }
 
 int cm_set_partition(int partition_mode) {
-  if (partition_mode < 0 || partition_mode > 3) return CM_EINVAL;
+  if (partition_mode < -1 || partition_mode > kMaxPartition) return CM_EINVAL;
   g_set.partition = partition_mode;
   return CM_OK;
 }
@@ -520,7 +530,7 @@ int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64
   bool have = false;
   for (int cfg = 0; cfg < kNumCfgs; ++cfg)
     for (int search = 0; search < 2; ++search)
-      for (int part = 0; part < 4; ++part) {
+      for (int part = 0; part <= kMaxPartition; ++part) {
         const Choice ch{cfg, search, part};
         double ms = 0;
         const int rc = time_calls(
@@ -608,7 +618,7 @@ int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int conf
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
   if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) || partition_mode < 0 ||
-      partition_mode > 3)
+      partition_mode > kMaxPartition)
     return CM_EINVAL;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   g_tuning[TuneKey{op, key_type, with_payload ? 1 : 0, size_cls}] =
@@ -656,7 +666,7 @@ int cm_tuning_load(const char* path) {
     double ms;
     if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
         (op != kOpMerge && op != kOpSegmented && op != kOpBatch) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
-        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || part < 0 || part > 3) {
+        sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || part < 0 || part > kMaxPartition) {
       rc = CM_EINVAL;
       break;
     }
@@ -807,8 +817,8 @@ int cm_timing_start(uint32_t capacity) {
   return CM_OK;
 }
 
-int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_mean, float* call_ms,
-                   float* merge_ms) {
+int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_mean, float* call_start_ms,
+                   float* call_ms, float* merge_ms) {
   if (!g_timing.on && !g_timing.ev) return CM_EINVAL;
   double sum_b = 0, sum_m = 0;
   int rc = CM_OK;
@@ -820,6 +830,11 @@ int cm_timing_stop(uint32_t* calls, double* co_rank_ms_mean, double* merge_ms_me
       rc = CM_EHIP;
     sum_b += tb;
     sum_m += tm;
+    if (call_start_ms) {
+      float t0 = 0;
+      if (c > 0 && hipEventElapsedTime(&t0, g_timing.ev[0], e[0]) != hipSuccess) rc = CM_EHIP;
+      call_start_ms[c] = t0;
+    }
     if (call_ms) call_ms[c] = tb + tm;
     if (merge_ms) merge_ms[c] = tm;
   }

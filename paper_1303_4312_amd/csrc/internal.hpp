@@ -36,8 +36,14 @@ struct Choice {
   int search;     // per-thread and one-level boundary search: 0 Alg. 1, 1 bisection
   int partition;  // block-boundary pass: 0 one thread per boundary; 1 two-level with a
                   // 64-lane coarse search; 2 two-level with a 16-lane coarse search;
-                  // 3 one block per resident workgroup (streaming kernel)
+                  // 3 one block per resident workgroup (streaming kernel); 4 no pass,
+                  // each block co-ranks its own ends
 };
+constexpr int kMaxPartition = 4;
+// Automatic boundary pass: single merges of fewer outputs than this skip the
+// pass (mode 4); larger ones, and batches, use the two-level pass (mode 2).
+// (Measured on MI355X: mode 4 is ahead up to 2^21 outputs, behind from 2^22.)
+constexpr uint64_t kInBlockBelow = 1ull << 22;
 
 // Launch-shape settings that never change results.
 struct Shape {
@@ -62,7 +68,8 @@ inline bool all_aligned16(std::initializer_list<const void*> ps) {
   return true;
 }
 
-// Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj.
+// Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj
+// (bj == nullptr: each block searches its own two boundary co-ranks).
 int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
                         uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st);

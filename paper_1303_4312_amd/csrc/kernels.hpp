@@ -243,6 +243,43 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, co
   }
 }
 
+// Algorithm 2 as the paper states it, with no separate boundary pass: every
+// workgroup co-ranks the two ends of its own block (wave 0 the start, wave 1
+// the end, each with the 64-ary wave search over the whole diagonal), then
+// merges the block as k_merge_blocks does.  Each inner boundary is searched
+// twice, once by each block that shares it; no workspace is read or written.
+// Worth it where the launch and the pass cost more than a few extra memory
+// round trips per block (small merges).
+template <typename K, bool VAL, int NT, int E, bool VEC>
+__global__ __launch_bounds__(NT) void k_merge_blocks_self(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+                                                          uint64_t m, const K* __restrict__ B,
+                                                          const uint32_t* __restrict__ Bv, uint64_t n,
+                                                          K* __restrict__ C, uint32_t* __restrict__ Cv,
+                                                          uint64_t num_tiles, int search, int xcd) {
+  static_assert(NT >= 128, "two waves search the block ends");
+  constexpr int T = NT * E;
+  __shared__ __attribute__((aligned(16))) K s_key[T + 16];
+  __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
+  __shared__ uint64_t s_j[2];
+  const uint64_t N = m + n;
+  const int wave = (int)(threadIdx.x >> 6);
+  for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
+    const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
+    const uint64_t i0 = t * (uint64_t)T;
+    const int len = (int)std::min((uint64_t)T, N - i0);
+    if (wave < 2) {  // wave-uniform
+      const uint64_t i = i0 + (wave ? (uint64_t)len : 0);
+      auto ra = [=](uint64_t x) { return A[x]; };
+      auto rb = [=](uint64_t x) { return B[x]; };
+      const uint64_t j = co_rank_wave64<K>(i, ra, rb, i > n ? i - n : 0, std::min(i, m));
+      if ((threadIdx.x & 63) == 0) s_j[wave] = j;
+    }
+    __syncthreads();
+    merge_block<K, VAL, NT, E, VEC>(A, Av, m, B, Bv, n, C, Cv, i0, len, s_j[0], s_j[1], search, s_key, s_val);
+    if (b + gridDim.x < num_tiles) __syncthreads();
+  }
+}
+
 // ---- Algorithm 2 with one processing element per resident workgroup --------
 
 // First output of block w of P: floor(w * N / P), exactly (no 128-bit product).

@@ -82,18 +82,26 @@ int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, con
       static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
       const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
       const dim3 g((unsigned)tiles), b(NT);
+      // bj == nullptr: every block co-ranks its own ends (no boundary pass)
+      auto go = [&](auto val_c, auto vec_c) {
+        constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
+        if (bj)
+          hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv, n,
+                             (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        else
+          hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
+                             Bv, n, (K*)C, Cv, tiles, ch.search, sh.xcd_order);
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
       if (val && vec)
-        hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E, true>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv,
-                           n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        go(T_{}, T_{});
       else if (val)
-        hipLaunchKernelGGL((k_merge_blocks<K, true, NT, E, false>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
-                           Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        go(T_{}, F_{});
       else if (vec)
-        hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E, true>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
-                           Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        go(F_{}, T_{});
       else
-        hipLaunchKernelGGL((k_merge_blocks<K, false, NT, E, false>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
-                           Bv, n, (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        go(F_{}, F_{});
       return launch_status();
     });
   });

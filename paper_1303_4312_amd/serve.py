@@ -79,32 +79,12 @@ class GpuExecutor:
     (two allocations per batch), and its descriptors are filled with
     vectorised numpy, so the host cost per request stays small."""
 
-    def __init__(self, device="cuda:0", num_streams: int = 2, timed: bool = False):
+    def __init__(self, device="cuda:0", num_streams: int = 2):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(num_streams)]
         self._next = 0
-        self.timed = timed
-        self._spans = []  # (start, end) timing events of each batch, when timed
-
-    def busy_ms(self):
-        """When timed: (union of the batches' device intervals, first batch
-        start to last batch end), both in ms.  Waits for every batch."""
-        if not self._spans:
-            return 0.0, 0.0
-        ref = self._spans[0][0]
-        self._spans[-1][1].synchronize()
-        iv = sorted((ref.elapsed_time(a), ref.elapsed_time(b)) for a, b in self._spans)
-        busy, cur_lo, cur_hi = 0.0, iv[0][0], iv[0][1]
-        for lo, hi in iv[1:]:
-            if lo > cur_hi:
-                busy += cur_hi - cur_lo
-                cur_lo, cur_hi = lo, hi
-            else:
-                cur_hi = max(cur_hi, hi)
-        busy += cur_hi - cur_lo
-        return busy, max(hi for _, hi in iv) - iv[0][0]
 
     def footprint(self, A, B, A_val, B_val) -> int:
         """Inputs plus outputs of one request, in bytes (after checking it once)."""
@@ -147,9 +127,6 @@ class GpuExecutor:
             for r in batch:  # inputs were produced on the submitters' streams
                 if r.ready is not None:
                     s.wait_event(r.ready)
-            if self.timed:
-                start = torch.cuda.Event(enable_timing=True)
-                start.record(s)
             for (dtype, with_val), idx in groups.items():
                 reqs = [batch[i] for i in idx]
                 m = np.array([r.A.numel() for r in reqs], dtype=np.uint64)
@@ -176,10 +153,8 @@ class GpuExecutor:
                 for k, i in enumerate(idx):
                     a, b = int(off[k]), int(off[k] + N[k])
                     outs[i] = (keys[a:b], vals[a:b]) if with_val else keys[a:b]
-            ev = torch.cuda.Event(enable_timing=self.timed)
+            ev = torch.cuda.Event()
             ev.record(s)
-            if self.timed:
-                self._spans.append((start, ev))
         return (ev, outs, keep)
 
     def done(self, handle) -> bool:

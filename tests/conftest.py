@@ -20,3 +20,20 @@ def pytest_configure(config):
 def figure():
     with open(os.path.join(GOLDEN, "figure_example.json")) as f:
         return json.load(f)
+
+
+@pytest.fixture
+def restore_settings():
+    """Tests may change the library's process-wide settings; put back the
+    ones found before the test (the defaults unless a test failed to)."""
+    import paper_1303_4312_amd as cm
+    kts = ("uint32", "uint64", "float32")
+    search, partition = cm.get_search(), cm.get_partition()
+    cfgs = {(kt, v): cm.get_config(kt, v) for kt in kts for v in (False, True)}
+    yield
+    cm.set_search(search)
+    cm.set_partition(partition)
+    cm.set_coarse_stride(64)
+    cm.set_block_order(1)
+    for (kt, v), c in cfgs.items():
+        cm.set_config(kt, v, c)

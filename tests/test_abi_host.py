@@ -115,7 +115,7 @@ def test_merge_argument_errors_are_synchronous():
     assert lib.cm_co_rank(0, P(0x80000000), 4, A, 4, B, 4, P(0x80000000 + 8), None) == EALIAS
 
 
-def test_config_table():
+def test_config_table(restore_settings):
     n = cm.config_count()
     assert n >= 4
     tiles = set()
@@ -132,9 +132,15 @@ def test_config_table():
     cm.set_config("uint32", True, old)
     assert cm.load().cm_set_config(0, 1, n) == ECONFIG
     assert cm.load().cm_set_search(2) == EINVAL
+    for mode in range(-1, 5):
+        cm.set_partition(mode)
+        assert cm.get_partition() == mode
+    assert cm.load().cm_set_partition(5) == EINVAL
+    assert cm.load().cm_set_partition(-2) == EINVAL
+    assert cm.load().cm_tuning_set(0, 0, 1, 20, 0, 1, 5) == EINVAL
 
 
-def test_workspace_sizes():
+def test_workspace_sizes(restore_settings):
     lib = cm.load()
     for c in range(cm.config_count()):
         cm.set_config("uint32", False, c)
@@ -144,7 +150,6 @@ def test_workspace_sizes():
             tiles = -(-N // T)
             assert lib.cm_merge_workspace_size(0, 0, N, 0) >= 8 * (tiles + 1)
             assert lib.cm_merge_workspace_size(0, 0, N, 0) % 256 == 0
-    cm.set_config("uint32", False, 2)
     assert lib.cm_merge_workspace_size(0, 0, 0, 0) == 0
 
 
@@ -170,12 +175,18 @@ def test_tuning_table_host_logic(tmp_path):
     cm.tuning_clear()
     assert cm.tuning_count() == 0
     default = cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000)
-    assert default == (cm.get_config("uint32", True), cm.get_search(), cm.get_partition())
+    # automatic boundary pass: none below 2^22 outputs, two-level from there
+    # and for batches
+    assert cm.get_partition() == -1
+    assert default == (cm.get_config("uint32", True), cm.get_search(), 4)
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, (1 << 22) - 1)[2] == 4
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1 << 22)[2] == 2
+    assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1000)[2] == 2
     cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, 3, 0, 0)  # size class 10: N in [512, 1024)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000) == (3, 0, 0)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1024) == default
     assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1000) == (
-        cm.get_config("uint32", False), cm.get_search(), cm.get_partition())
+        cm.get_config("uint32", False), cm.get_search(), 4)
     cm.tuning_set(cm.OP_SEGMENTED, "uint64", False, 30, 5, 1, 0)
     path = tmp_path / "tune.txt"
     cm.tuning_save(str(path))
@@ -267,5 +278,5 @@ def test_timing_argument_errors():
     u = ctypes.c_uint32()
     d = ctypes.c_double()
     assert lib.cm_timing_start(0) == EINVAL
-    assert lib.cm_timing_stop(ctypes.byref(u), ctypes.byref(d), ctypes.byref(d), None,
+    assert lib.cm_timing_stop(ctypes.byref(u), ctypes.byref(d), ctypes.byref(d), None, None,
                               None) == EINVAL

@@ -14,21 +14,9 @@ import paper_1303_4312_amd as cm
 from paper_1303_4312_amd import workloads
 from tests.gpu_util import first_difference, same_bits, to_dev, to_host
 
-pytestmark = pytest.mark.gpu
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("restore_settings")]
 
 DTYPES = [np.uint32, np.uint64, np.float32]
-
-
-@pytest.fixture(autouse=True)
-def _default_settings():
-    yield
-    cm.set_search(1)
-    cm.set_partition(2)
-    cm.set_coarse_stride(64)
-    cm.set_block_order(1)
-    for kt in ("uint32", "uint64", "float32"):
-        for v in (False, True):
-            cm.set_config(kt, v, 2)
 
 
 def check_pairs(A, B, Av=None, Bv=None, offset=0):
@@ -69,7 +57,7 @@ def test_figure_example(figure):
 
 @pytest.mark.parametrize("dtype", DTYPES)
 @pytest.mark.parametrize("search,partition", [(0, 0), (1, 0), (0, 1), (1, 1), (1, 2), (0, 3),
-                                              (1, 3)])
+                                              (1, 3), (0, 4), (1, 4)])
 def test_all_configs_pairs_and_keys(dtype, search, partition):
     cm.set_search(search)
     cm.set_partition(partition)
@@ -89,7 +77,7 @@ def test_all_configs_pairs_and_keys(dtype, search, partition):
 
 
 @pytest.mark.parametrize("partition,stride,xcd", [(0, 64, 1), (1, 64, 1), (2, 64, 0), (1, 16, 0),
-                                                  (2, 16, 1), (3, 64, 1)])
+                                                  (2, 16, 1), (3, 64, 1), (4, 64, 1), (4, 64, 0)])
 def test_two_level_partition_edges(partition, stride, xcd):
     """Block counts around multiples of the coarse stride, with the co-rank
     windows of the fine pass both wide and degenerate; both block orders."""

@@ -7,19 +7,7 @@ import paper_1303_4312_amd as cm
 from paper_1303_4312_amd import workloads
 from tests.gpu_util import first_difference, same_bits, to_dev, to_host
 
-pytestmark = pytest.mark.gpu
-
-
-@pytest.fixture(autouse=True)
-def _default_settings():
-    yield
-    cm.set_search(1)
-    cm.set_partition(2)
-    cm.set_coarse_stride(64)
-    cm.set_block_order(1)
-    for kt in ("uint32", "uint64", "float32"):
-        for v in (False, True):
-            cm.set_config(kt, v, 2)
+pytestmark = [pytest.mark.gpu, pytest.mark.usefixtures("restore_settings")]
 
 
 def run_seg(d, payload=True):
