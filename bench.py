@@ -277,26 +277,17 @@ def copy_ceiling(dev, reps=20):
     return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
-def interval_union(starts, durations):
-    """Total length covered by the intervals [start, start + duration)."""
-    total, lo, hi = 0.0, None, None
-    for a, d in sorted(zip(starts, durations)):
-        if hi is None or a > hi:
-            if hi is not None:
-                total += hi - lo
-            lo, hi = a, a + d
-        else:
-            hi = max(hi, a + d)
-    return total + (hi - lo if hi is not None else 0.0)
-
-
 def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.1),
                 seed=5000):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
-    payload, uniform keys), staged in HBM before they arrive, admitted against
-    a 32 GiB budget and batched on the fly.  First a closed loop (all
-    requests at once) gives the saturation rate; then Poisson arrivals at
-    fractions of it.  Latency is arrival to completion seen by the server."""
+    payload, uniform keys), staged in HBM before they arrive.  The library's
+    serving runtime (cm_server_*: a native scheduler thread) admits them
+    against a 16 GiB output arena (the outputs half of a 32 GiB budget for
+    inputs plus outputs) and batches them on the fly.  First a closed loop
+    (every request at once) gives the saturation rate; then Poisson arrivals
+    at fractions of it.  Latency is arrival to completion as seen by the
+    scheduler.  The pure-Python scheduler's saturation rate on the same pool
+    is reported beside it."""
     import numpy as np
     import torch
     import paper_1303_4312_amd as cm
@@ -309,62 +300,100 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
         d = w.request(seed + r)
         pool.append(tuple(torch.from_numpy(d[k]).to(dev) for k in ("A", "B", "Av", "Bv")))
     sizes = [p[0].numel() + p[1].numel() for p in pool]
-    budget = 32 << 30
+    ptrs = [(A.data_ptr(), Av.data_ptr(), A.numel(), B.data_ptr(), Bv.data_ptr(), B.numel())
+            for A, B, Av, Bv in pool]
+    arena = torch.empty(16 << 30, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
 
-    def run(arrivals):
-        ex = serve.GpuExecutor(dev)
-        srv = serve.Server(ex, budget_bytes=budget, max_batch=64, max_inflight=2)
-        torch.cuda.synchronize()
-        cm.timing_start(len(arrivals) + 8)  # device interval of every batch call
-        with srv:
-            t0 = time.perf_counter()
-            futs = []
-            for k, at in enumerate(arrivals):
-                target = t0 + at
-                while True:  # wait for the arrival time, yielding the GIL
-                    dt = target - time.perf_counter()
-                    if dt <= 0:
-                        break
-                    time.sleep(dt if dt > 2e-3 else 0)
-                futs.append(srv.submit(*pool[k % pool_size], arrival=target))
-            for f in futs:
-                f.result(timeout=120)
+    def run_native(arrivals):
+        total = len(arrivals)
+        srv = serve.NativeServer("uint32", True, arena=arena, max_batch=64, max_inflight=2,
+                                 max_requests=4096, device=dev)
+        submit, poll, release = srv.submit_ptrs, srv.poll, srv.release
+        lat, late, outputs, sub = [], {}, 0, 0
+        t0 = time.perf_counter()
+        t_done = t0
+        while len(lat) < total:
+            now = time.perf_counter()
+            while sub < total and t0 + arrivals[sub] <= now:
+                rc = submit(*ptrs[sub % pool_size])
+                if rc == -9:  # every slot taken: collect results first
+                    break
+                if rc != 0:
+                    raise cm.CMError(rc, "cm_server_submit")
+                late[srv.last_ticket] = (now - (t0 + arrivals[sub]), sizes[sub % pool_size])
+                sub += 1
+            wait = 200 if sub >= total else max(0, min(200, int((t0 + arrivals[sub] - now) * 1e6)))
+            for d in poll(wait_us=wait):
+                if d.status != 0:
+                    raise cm.CMError(d.status, "serving request")
+                lateness, n_out = late.pop(d.ticket)
+                lat.append(lateness + d.latency_ns * 1e-9)
+                outputs += n_out
+                release(d.ticket)
+                t_done = time.perf_counter()
         st = srv.stats()
-        _, _, _, starts, durs, _ = cm.timing_stop(per_call=True)
-        wall_ms = (srv.last_done - srv.first_arrival) * 1e3
-        st["gpu_busy_fraction"] = interval_union(starts, durs) / wall_ms if wall_ms > 0 else None
-        return st
+        srv.close()
+        wall = t_done - t0 - arrivals[0]
+        lat.sort()
 
-    sys.setswitchinterval(1e-4)  # let the scheduler thread in often
-    warm = run([0.0] * per_point)  # warm-up: first launches, allocator caches
-    sat = run([0.0] * per_point)
-    outputs = sum(sizes[k % pool_size] for k in range(per_point))
-    sat_rate = per_point * sat["keys_per_s"] / outputs
+        def pick(q):
+            return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+        return {"keys_per_s": outputs / wall, "requests_per_s": total / wall,
+                "p50_ms": pick(0.5) * 1e3, "p99_ms": pick(0.99) * 1e3,
+                "mean_batch": st["submitted"] / max(st["batches"], 1),
+                "gpu_busy_fraction": st["busy_ms"] / (wall * 1e3)}
+
+    run_native([0.0] * per_point)  # warm-up
+    sat = run_native([0.0] * per_point)
+    sat_rate = sat["requests_per_s"]
+    log(f"serving (native): saturation {sat_rate:.0f} req/s, {sat['keys_per_s'] / 1e9:.1f} "
+        f"G keys/s, busy {sat['gpu_busy_fraction']:.2f}")
     rng = np.random.default_rng(seed)
     points = []
     for frac in fractions:
         lam = frac * sat_rate
         gaps = rng.exponential(1.0 / lam, per_point)
-        st = run(list(np.cumsum(gaps) - gaps[0]))
-        points.append({"rate_per_s": lam, "fraction_of_saturation": frac,
-                       "keys_per_s": st["keys_per_s"], "p50_ms": st["p50_s"] * 1e3,
-                       "p99_ms": st["p99_s"] * 1e3, "mean_batch": st["mean_batch"],
-                       "max_concurrent_batches": st["max_concurrent_batches"],
-                       "gpu_busy_fraction": st["gpu_busy_fraction"]})
-        log(f"serving: rate {lam:.0f}/s p50 {st['p50_s'] * 1e3:.3f} ms "
-            f"p99 {st['p99_s'] * 1e3:.3f} ms busy {st['gpu_busy_fraction']:.2f}")
-    del warm
+        st = run_native(list(np.cumsum(gaps) - gaps[0]))
+        st.update({"rate_per_s": lam, "fraction_of_saturation": frac})
+        points.append(st)
+        log(f"serving (native): rate {lam:.0f}/s p50 {st['p50_ms']:.3f} ms "
+            f"p99 {st['p99_ms']:.3f} ms busy {st['gpu_busy_fraction']:.2f}")
+    del arena
+    torch.cuda.empty_cache()
+
+    # the pure-Python scheduler (serve.Server) on the same pool, closed loop
+    def run_python(count):
+        ex = serve.GpuExecutor(dev)
+        srv = serve.Server(ex, budget_bytes=32 << 30, max_batch=64, max_inflight=2)
+        torch.cuda.synchronize()
+        with srv:
+            futs = [srv.submit(*pool[k % pool_size]) for k in range(count)]
+            for f in futs:
+                f.result(timeout=120)
+        return srv.stats()
+
+    sys.setswitchinterval(1e-4)  # let the scheduler thread in often
+    run_python(per_point)
+    py = run_python(per_point)
+    outputs = sum(sizes[k % pool_size] for k in range(per_point))
+    log(f"serving (python scheduler): saturation "
+        f"{per_point * py['keys_per_s'] / outputs:.0f} req/s")
     return {
         "workload": ("requests with sides log-uniform in [2^10,2^24], uint32 keys uniform, "
-                     "uint32 payloads, device-resident, 32 GiB budget"),
+                     "uint32 payloads, device-resident"),
+        "runtime": "cm_server (native scheduler thread), 16 GiB output arena, max_batch 64, "
+                   "2 batches in flight",
         "pool": pool_size,
         "requests_per_point": per_point,
         "mean_outputs_per_request": float(np.mean(sizes)),
-        "saturation": {"requests_per_s": sat_rate, "keys_per_s": sat["keys_per_s"],
-                       "p50_ms": sat["p50_s"] * 1e3, "p99_ms": sat["p99_s"] * 1e3,
-                       "mean_batch": sat["mean_batch"],
-                       "gpu_busy_fraction": sat["gpu_busy_fraction"]},
+        "saturation": sat,
         "points": points,
+        "python_scheduler_saturation": {
+            "requests_per_s": per_point * py["keys_per_s"] / outputs,
+            "keys_per_s": py["keys_per_s"], "p50_ms": py["p50_s"] * 1e3,
+            "p99_ms": py["p99_s"] * 1e3, "mean_batch": py["mean_batch"],
+            "note": "serve.Server, 32 GiB budget for inputs plus outputs"},
     }
 
 

@@ -54,10 +54,13 @@ enum cm_status {
     CM_ERANGE = -2,    /* rank outside [0, m + n] */
     CM_EDTYPE = -3,    /* unknown key type */
     CM_EALIAS = -4,    /* an output overlaps an input */
-    CM_ENOSPC = -5,    /* workspace smaller than the *_workspace_size result */
+    CM_ENOSPC = -5,    /* workspace smaller than the *_workspace_size result, or a
+                          server request larger than the server's arena */
     CM_EHIP = -6,      /* a HIP runtime call or kernel launch failed */
     CM_EUNSORTED = -7, /* cm_check_sorted: the array is not sorted */
-    CM_ECONFIG = -8    /* unknown tile configuration */
+    CM_ECONFIG = -8,   /* unknown tile configuration */
+    CM_EBUSY = -9,     /* server: every request slot is taken */
+    CM_ECANCELED = -10 /* server: request dropped at shutdown without running */
 };
 
 /* Key types. */
@@ -409,6 +412,84 @@ int cm_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 int cm_timing_start(uint32_t capacity);
 int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean,
                    float *call_start_ms, float *call_ms, float *merge_ms);
+
+/*
+ * Serving runtime (not part of the method; it feeds the batch call above).
+ * A server owns a scheduler thread.  Clients submit single merges (device
+ * inputs, sizes); the scheduler admits them in arrival order while their
+ * outputs fit in an output arena in HBM (the caller's device buffer), packs
+ * the admitted ones into one cm_stable_merge_batch launch per step (at most
+ * max_batch merges; at most max_inflight batches in flight, each on its own
+ * stream), and reports each finished merge once.  A finished merge's outputs
+ * stay in the arena until the client releases its ticket.  Results are
+ * those of cm_stable_merge_pairs / cm_stable_merge on the same inputs.
+ *
+ * cm_server_create(key_type, with_payload, arena, arena_bytes, max_batch,
+ *   max_inflight, max_requests, &server): arena is a device buffer of
+ *   arena_bytes (>= 256; the caller keeps it alive until destroy; it must not
+ *   overlap any request's inputs); max_batch in [1, 65536], max_inflight in
+ *   [1, 16], max_requests in [1, 65535] (submitted and not yet released).
+ *   Creates streams (default priority), events, pinned host descriptor
+ *   buffers and per-batch device workspaces on the current device once;
+ *   nothing is allocated afterwards.  CM_EINVAL / CM_EDTYPE / CM_EHIP.
+ * cm_server_submit(server, A, A_val, m, B, B_val, n, inputs_stream,
+ *   inputs_pending, &ticket): payload pointers all NULL iff the server has
+ *   no payloads.  With inputs_pending set, the merge waits for the work
+ *   enqueued on inputs_stream so far (the inputs' producer); otherwise the
+ *   inputs must already be in place.  Inputs must stay unchanged until the
+ *   merge is reported.  Thread-safe.  CM_EINVAL (bad pointers or sizes),
+ *   CM_ENOSPC (the outputs can never fit in the arena), CM_EBUSY (all
+ *   max_requests slots are taken: poll and release, then retry),
+ *   CM_ECANCELED (the server is shutting down).
+ * cm_server_poll(server, done, capacity, &count, wait_us): moves up to
+ *   `capacity` finished merges into done[] and sets count; waits up to
+ *   wait_us microseconds for the first one if none is ready (0: do not
+ *   wait).  Each entry: ticket; status (CM_OK, or the batch call's error, or
+ *   CM_ECANCELED); C / C_val: the outputs (inside the arena; NULL for an
+ *   empty merge); keys_offset / vals_offset: their byte offsets in the
+ *   arena; queued_ns: submit to launch; latency_ns: submit to completion as
+ *   seen by the scheduler.  Thread-safe.
+ * cm_server_release(server, ticket): the client is done with a reported
+ *   merge's outputs; its arena space and slot are reused.  CM_EINVAL for an
+ *   unknown, unreported or already released ticket.
+ * cm_server_get_stats(server, &stats): counters since creation; busy_ms is the
+ *   total time at least one batch was running on the GPU (from HIP events
+ *   recorded around each batch's upload and kernels, union over streams) and
+ *   span_ms the time from the first batch's start to the last one's end.
+ * cm_server_destroy(server): finishes every admitted and launched merge,
+ *   cancels submitted merges that can no longer be admitted (arena held by
+ *   unreleased outputs), joins the thread and frees the server's resources
+ *   (not the arena).
+ */
+typedef struct cm_server cm_server;
+typedef struct cm_server_done {
+    uint64_t ticket;
+    int32_t status;
+    int32_t reserved;
+    void *C;
+    uint32_t *C_val;
+    uint64_t keys_offset;
+    uint64_t vals_offset;
+    uint64_t queued_ns;
+    uint64_t latency_ns;
+} cm_server_done;
+typedef struct cm_server_stats {
+    uint64_t submitted, completed, failed, canceled, batches, max_batch_seen;
+    uint64_t arena_bytes, arena_peak_bytes;
+    double busy_ms, span_ms;
+} cm_server_stats;
+
+int cm_server_create(int key_type, int with_payload, void *arena, uint64_t arena_bytes,
+                     uint32_t max_batch, uint32_t max_inflight, uint32_t max_requests,
+                     cm_server **server);
+int cm_server_submit(cm_server *server, const void *A, const uint32_t *A_val, uint64_t m,
+                     const void *B, const uint32_t *B_val, uint64_t n, hipStream_t inputs_stream,
+                     int inputs_pending, uint64_t *ticket);
+int cm_server_poll(cm_server *server, cm_server_done *done, uint32_t capacity, uint32_t *count,
+                   int64_t wait_us);
+int cm_server_release(cm_server *server, uint64_t ticket);
+int cm_server_get_stats(cm_server *server, cm_server_stats *stats);
+int cm_server_destroy(cm_server *server);
 
 #ifdef __cplusplus
 }

@@ -52,6 +52,8 @@ EXPORTS = [
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
     "cm_set_coarse_stride", "cm_set_block_order",
+    "cm_server_create", "cm_server_submit", "cm_server_poll", "cm_server_release",
+    "cm_server_get_stats", "cm_server_destroy",
 ]
 
 _lib = None
@@ -122,6 +124,15 @@ def load():
                                           vp]),
         "cm_plan_destroy": (c_int, [vp]),
         "cm_timing_start": (c_int, [ctypes.c_uint32]),
+        "cm_server_create": (c_int, [c_int, c_int, vp, c_u64, ctypes.c_uint32, ctypes.c_uint32,
+                                     ctypes.c_uint32, ctypes.POINTER(vp)]),
+        "cm_server_submit": (c_int, [vp, vp, vp, c_u64, vp, vp, c_u64, vp, c_int,
+                                     ctypes.POINTER(c_u64)]),
+        "cm_server_poll": (c_int, [vp, vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
+                                   ctypes.c_int64]),
+        "cm_server_release": (c_int, [vp, c_u64]),
+        "cm_server_get_stats": (c_int, [vp, vp]),
+        "cm_server_destroy": (c_int, [vp]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),

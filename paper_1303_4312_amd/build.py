@@ -18,7 +18,7 @@ LIB_NAME = "libcorank_merge.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
 HIP_SOURCES = ["launch.hip"]
-CXX_SOURCES = ["api.cpp", "host_co_rank.cpp"]
+CXX_SOURCES = ["api.cpp", "host_co_rank.cpp", "server.cpp"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed fp32 VALU ops.
 HIPCC_FLAGS = [
@@ -42,14 +42,14 @@ def build(verbose: bool = False) -> str:
         cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
                os.path.join(CSRC, src), "-o", obj]
         if src.endswith(".cpp"):
-            cmd = [hipcc(), "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE,
+            cmd = [hipcc(), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE,
                    "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
         objs.append(obj)
     tmp = LIB_PATH + ".tmp"
-    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

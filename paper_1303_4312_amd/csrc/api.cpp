@@ -302,10 +302,12 @@ const char* cm_status_string(int status) {
     case CM_ERANGE: return "rank out of range";
     case CM_EDTYPE: return "unknown key type";
     case CM_EALIAS: return "output overlaps an input";
-    case CM_ENOSPC: return "workspace too small";
+    case CM_ENOSPC: return "workspace or arena too small";
     case CM_EHIP: return "HIP runtime error";
     case CM_EUNSORTED: return "array not sorted";
     case CM_ECONFIG: return "unknown tile configuration";
+    case CM_EBUSY: return "every request slot is taken";
+    case CM_ECANCELED: return "canceled at shutdown";
     default: return "unknown status";
   }
 }

@@ -1,0 +1,453 @@
+// Serving runtime: admission against an output arena, one batched merge
+// launch per scheduler step, completion reporting.  The merge work itself is
+// cm_stable_merge_batch (Algorithm 2 over a batch of independent merges); this
+// file is scheduling only.
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <utility>
+#include <vector>
+
+#include "corank_merge.h"
+#include "internal.hpp"
+#include "ring_alloc.hpp"
+
+static_assert(sizeof(cm_server_done) == 64, "cm_server_done layout (mirrored by the Python binding)");
+static_assert(sizeof(cm_server_stats) == 80, "cm_server_stats layout (mirrored by the Python binding)");
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+uint64_t round256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+enum State { kFree, kPending, kAdmitted, kDone };
+
+struct Request {
+  uint64_t ticket = 0;
+  State state = kFree;
+  cm_merge_desc d{};
+  bool wait_ready = false;
+  hipEvent_t ready = nullptr;  // recorded on the client's stream at submit
+  uint64_t out_bytes = 0;      // arena bytes of the outputs (keys, then payloads)
+  uint64_t keys_off = 0, vals_off = 0;
+  Clock::time_point t_submit, t_launch;
+};
+
+struct Slot {  // one batch in flight
+  hipStream_t stream = nullptr;
+  hipEvent_t start = nullptr, end = nullptr;
+  cm_merge_desc* host = nullptr;  // pinned
+  cm_merge_desc* dev = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  std::vector<uint32_t> reqs;
+  int status = CM_OK;
+  bool timed = false;  // start was recorded by this batch
+  bool busy = false;
+};
+
+}  // namespace
+
+struct cm_server {
+  int kt = 0;
+  bool val = false;
+  uint64_t ks = 4;
+  char* arena = nullptr;
+  uint32_t max_batch = 0, max_inflight = 0, max_requests = 0;
+  int device = 0;
+
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  cm::RingAlloc ring{256};
+  std::vector<Request> reqs;
+  std::vector<uint32_t> free_slots;  // request slots
+  std::deque<uint32_t> pending;      // submitted, in arrival order
+  std::deque<cm_server_done> done;
+  uint64_t seq = 0;
+  bool stop = false;
+  cm_server_stats st{};
+
+  // scheduler thread only
+  std::deque<uint32_t> admitted;
+  std::vector<Slot> slots;
+  hipEvent_t ref = nullptr;  // time origin of the busy intervals
+  std::vector<std::pair<float, float>> intervals;
+
+  std::thread thread;
+};
+
+namespace {
+
+void destroy_resources(cm_server* s) {
+  for (Slot& b : s->slots) {
+    if (b.stream) (void)hipStreamDestroy(b.stream);
+    if (b.start) (void)hipEventDestroy(b.start);
+    if (b.end) (void)hipEventDestroy(b.end);
+    if (b.host) (void)hipHostFree(b.host);
+    if (b.dev) (void)hipFree(b.dev);
+    if (b.ws) (void)hipFree(b.ws);
+  }
+  for (Request& r : s->reqs)
+    if (r.ready) (void)hipEventDestroy(r.ready);
+  if (s->ref) (void)hipEventDestroy(s->ref);
+}
+
+// Keys then payloads of an N-output merge, each 256-byte aligned.
+uint64_t out_bytes(const cm_server* s, uint64_t N) {
+  return N ? round256(N * s->ks) + (s->val ? round256(N * 4) : 0) : 0;
+}
+
+// Admit pending requests in arrival order while their outputs fit (mu held).
+void admit(cm_server* s) {
+  while (!s->pending.empty()) {
+    Request& r = s->reqs[s->pending.front()];
+    const int64_t off = s->ring.alloc(r.out_bytes, r.ticket);
+    if (off < 0) break;
+    const uint64_t N = r.d.m + r.d.n;
+    r.keys_off = (uint64_t)off;
+    r.vals_off = s->val && N ? (uint64_t)off + round256(N * s->ks) : 0;
+    r.d.C = N ? s->arena + r.keys_off : nullptr;
+    r.d.C_val = s->val && N ? (uint32_t*)(s->arena + r.vals_off) : nullptr;
+    r.state = kAdmitted;
+    s->admitted.push_back(s->pending.front());
+    s->pending.pop_front();
+    s->st.arena_peak_bytes = std::max(s->st.arena_peak_bytes, s->ring.used());
+  }
+}
+
+// Launch up to max_batch admitted requests on slot b (scheduler thread).
+void launch(cm_server* s, Slot& b) {
+  const uint32_t n = (uint32_t)std::min<size_t>(s->max_batch, s->admitted.size());
+  b.reqs.clear();
+  const Clock::time_point now = Clock::now();
+  for (uint32_t k = 0; k < n; ++k) {
+    const uint32_t idx = s->admitted.front();
+    s->admitted.pop_front();
+    Request& r = s->reqs[idx];  // stays kAdmitted (not releasable) until reported
+    r.t_launch = now;
+    b.host[k] = r.d;
+    b.reqs.push_back(idx);
+  }
+  uint64_t total = 0;
+  int rc = cm_batch_prepare(s->kt, s->val ? 1 : 0, b.host, n, &total);
+  for (uint32_t idx : b.reqs)
+    if (rc == CM_OK && s->reqs[idx].wait_ready && hipStreamWaitEvent(b.stream, s->reqs[idx].ready, 0) != hipSuccess)
+      rc = CM_EHIP;
+  b.timed = false;
+  if (rc == CM_OK) {
+    if (hipEventRecord(b.start, b.stream) == hipSuccess)
+      b.timed = true;
+    else
+      rc = CM_EHIP;
+  }
+  if (rc == CM_OK &&
+      hipMemcpyAsync(b.dev, b.host, (size_t)n * sizeof(cm_merge_desc), hipMemcpyHostToDevice, b.stream) != hipSuccess)
+    rc = CM_EHIP;
+  if (rc == CM_OK) rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, b.dev, n, total, b.ws, b.ws_bytes, b.stream);
+  // the end event is recorded whatever happened, so completion is detected the same way
+  if (hipEventRecord(b.end, b.stream) != hipSuccess && rc == CM_OK) rc = CM_EHIP;
+  b.status = rc;
+  b.busy = true;
+  s->st.batches += 1;
+  s->st.max_batch_seen = std::max<uint64_t>(s->st.max_batch_seen, n);
+}
+
+// Report the requests of a finished slot (mu held).
+void finish(cm_server* s, Slot& b, int status) {
+  const Clock::time_point now = Clock::now();
+  for (uint32_t idx : b.reqs) {
+    Request& r = s->reqs[idx];
+    r.state = kDone;
+    cm_server_done e{};
+    e.ticket = r.ticket;
+    e.status = status;
+    e.C = r.d.C;
+    e.C_val = r.d.C_val;
+    e.keys_offset = r.keys_off;
+    e.vals_offset = r.vals_off;
+    e.queued_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r.t_launch - r.t_submit).count();
+    e.latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - r.t_submit).count();
+    s->done.push_back(e);
+    if (status == CM_OK)
+      s->st.completed += 1;
+    else
+      s->st.failed += 1;
+  }
+  b.reqs.clear();
+  b.busy = false;
+}
+
+void cancel_pending(cm_server* s) {  // mu held
+  const Clock::time_point now = Clock::now();
+  while (!s->pending.empty()) {
+    Request& r = s->reqs[s->pending.front()];
+    s->pending.pop_front();
+    r.state = kDone;
+    r.d.C = nullptr;
+    r.d.C_val = nullptr;
+    r.out_bytes = 0;  // nothing allocated
+    cm_server_done e{};
+    e.ticket = r.ticket;
+    e.status = CM_ECANCELED;
+    e.latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - r.t_submit).count();
+    s->done.push_back(e);
+    s->st.canceled += 1;
+  }
+}
+
+void scheduler(cm_server* s) {
+  (void)hipSetDevice(s->device);
+  std::unique_lock<std::mutex> lk(s->mu);
+  for (;;) {
+    admit(s);
+    int inflight = 0;
+    for (const Slot& b : s->slots) inflight += b.busy ? 1 : 0;
+    if (s->stop && s->admitted.empty() && inflight == 0) {
+      if (s->pending.empty()) break;
+      cancel_pending(s);  // the arena is held by outputs nobody will release
+      s->cv_done.notify_all();
+      continue;
+    }
+    lk.unlock();
+    bool progressed = false;
+    for (Slot& b : s->slots) {
+      if (s->admitted.empty()) break;
+      if (!b.busy) {
+        launch(s, b);
+        progressed = true;
+      }
+    }
+    struct Finished {
+      Slot* b;
+      int status;
+      bool timed;
+      float t0, t1;
+    };
+    std::vector<Finished> finished;
+    for (Slot& b : s->slots) {
+      if (!b.busy) continue;
+      const hipError_t q = hipEventQuery(b.end);
+      if (q == hipErrorNotReady) continue;
+      Finished f{&b, b.status, false, 0.f, 0.f};
+      if (q != hipSuccess && f.status == CM_OK) f.status = CM_EHIP;
+      f.timed = b.timed && hipEventElapsedTime(&f.t0, s->ref, b.start) == hipSuccess &&
+                hipEventElapsedTime(&f.t1, s->ref, b.end) == hipSuccess;
+      finished.push_back(f);
+    }
+    lk.lock();
+    for (const Finished& f : finished) {
+      if (f.timed) s->intervals.emplace_back(f.t0, f.t1);
+      finish(s, *f.b, f.status);
+    }
+    if (!finished.empty()) {
+      progressed = true;
+      s->cv_done.notify_all();
+    }
+    if (!progressed) {
+      bool any_busy = false;
+      for (const Slot& b : s->slots) any_busy = any_busy || b.busy;
+      // poll in-flight batches every 20 us; otherwise sleep until woken
+      if (any_busy)
+        s->cv_sched.wait_for(lk, std::chrono::microseconds(20));
+      else if (!s->stop && s->pending.empty())
+        s->cv_sched.wait(lk);
+      else if (!s->stop)
+        s->cv_sched.wait_for(lk, std::chrono::milliseconds(1));  // waiting for arena space
+    }
+  }
+}
+
+double union_ms(std::vector<std::pair<float, float>> iv, double* span) {
+  *span = 0;
+  if (iv.empty()) return 0;
+  std::sort(iv.begin(), iv.end());
+  double total = 0, lo = iv[0].first, hi = iv[0].second, last = iv[0].second;
+  for (size_t k = 1; k < iv.size(); ++k) {
+    if (iv[k].first > hi) {
+      total += hi - lo;
+      lo = iv[k].first;
+      hi = iv[k].second;
+    } else {
+      hi = std::max<double>(hi, iv[k].second);
+    }
+    last = std::max<double>(last, iv[k].second);
+  }
+  *span = last - iv[0].first;
+  return total + (hi - lo);
+}
+
+}  // namespace
+
+extern "C" {
+
+int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena_bytes, uint32_t max_batch,
+                     uint32_t max_inflight, uint32_t max_requests, cm_server** server) {
+  if (!server) return CM_EINVAL;
+  *server = nullptr;
+  if (key_type != CM_KEY_U32 && key_type != CM_KEY_U64 && key_type != CM_KEY_F32) return CM_EDTYPE;
+  if (!arena || arena_bytes < 256 || max_batch < 1 || max_batch > 65536 || max_inflight < 1 || max_inflight > 16 ||
+      max_requests < 1 || max_requests > 65535)
+    return CM_EINVAL;
+  cm_server* s = new cm_server();
+  s->kt = key_type;
+  s->val = with_payload != 0;
+  s->ks = key_type == CM_KEY_U64 ? 8 : 4;
+  s->arena = (char*)arena;
+  s->max_batch = max_batch;
+  s->max_inflight = max_inflight;
+  s->max_requests = max_requests;
+  s->ring = cm::RingAlloc(arena_bytes);
+  s->st.arena_bytes = s->ring.size();
+  s->reqs.resize(max_requests);
+  for (uint32_t k = max_requests; k > 0; --k) s->free_slots.push_back(k - 1);
+  s->slots.resize(max_inflight);
+  // A batch's outputs all lie in the arena, so it has at most
+  // arena / (bytes per output) outputs and that / smallest tile + count blocks.
+  const uint64_t per_out = s->ks + (s->val ? 4 : 0);
+  const uint64_t max_blocks = arena_bytes / per_out / cm::kMinTile + max_batch;
+  int rc = hipGetDevice(&s->device) == hipSuccess ? CM_OK : CM_EHIP;
+  for (Slot& b : s->slots) {
+    if (rc != CM_OK) break;
+    b.ws_bytes = cm_batch_workspace_size(max_blocks, max_batch);
+    if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&b.start) != hipSuccess || hipEventCreate(&b.end) != hipSuccess ||
+        hipHostMalloc((void**)&b.host, (size_t)max_batch * sizeof(cm_merge_desc), hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&b.dev, (size_t)max_batch * sizeof(cm_merge_desc)) != hipSuccess ||
+        hipMalloc(&b.ws, b.ws_bytes) != hipSuccess)
+      rc = CM_EHIP;
+  }
+  for (Request& r : s->reqs) {
+    if (rc != CM_OK) break;
+    if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess) rc = CM_EHIP;
+  }
+  if (rc == CM_OK && (hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, s->slots[0].stream) != hipSuccess ||
+                      hipEventSynchronize(s->ref) != hipSuccess))
+    rc = CM_EHIP;
+  if (rc != CM_OK) {
+    destroy_resources(s);
+    delete s;
+    return rc;
+  }
+  s->thread = std::thread(scheduler, s);
+  *server = s;
+  return CM_OK;
+}
+
+int cm_server_submit(cm_server* s, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                     const uint32_t* B_val, uint64_t n, hipStream_t inputs_stream, int inputs_pending,
+                     uint64_t* ticket) {
+  if (!s || !ticket) return CM_EINVAL;
+  if (m + n < m) return CM_EINVAL;
+  const uint64_t N = m + n;
+  if ((m && !A) || (n && !B)) return CM_EINVAL;
+  if (s->val ? ((m && !A_val) || (n && !B_val)) : (A_val || B_val)) return CM_EINVAL;
+  const uint64_t bytes = out_bytes(s, N);
+  if (bytes > s->ring.size()) return CM_ENOSPC;
+  uint32_t idx;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return CM_ECANCELED;
+    if (s->free_slots.empty()) return CM_EBUSY;
+    idx = s->free_slots.back();
+    s->free_slots.pop_back();
+    s->seq += 1;
+    s->reqs[idx].ticket = (s->seq << 16) | idx;  // state stays kFree until queued
+  }
+  Request& r = s->reqs[idx];  // only this thread touches it until it is queued
+  r.d = cm_merge_desc{};
+  r.d.A = A;
+  r.d.A_val = A_val;
+  r.d.m = m;
+  r.d.B = B;
+  r.d.B_val = B_val;
+  r.d.n = n;
+  r.out_bytes = bytes;
+  r.wait_ready = inputs_pending != 0;
+  if (r.wait_ready && hipEventRecord(r.ready, inputs_stream) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    r.ticket = 0;
+    s->free_slots.push_back(idx);
+    return CM_EHIP;
+  }
+  r.t_submit = Clock::now();
+  uint64_t t;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    t = r.ticket;
+    r.state = kPending;
+    s->pending.push_back(idx);
+    s->st.submitted += 1;
+  }
+  s->cv_sched.notify_one();
+  *ticket = t;
+  return CM_OK;
+}
+
+int cm_server_poll(cm_server* s, cm_server_done* done, uint32_t capacity, uint32_t* count, int64_t wait_us) {
+  if (!s || !count || (capacity && !done)) return CM_EINVAL;
+  *count = 0;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (s->done.empty() && wait_us > 0)
+    s->cv_done.wait_for(lk, std::chrono::microseconds(wait_us), [s] { return !s->done.empty(); });
+  uint32_t k = 0;
+  while (k < capacity && !s->done.empty()) {
+    done[k++] = s->done.front();
+    s->done.pop_front();
+  }
+  *count = k;
+  return CM_OK;
+}
+
+int cm_server_release(cm_server* s, uint64_t ticket) {
+  if (!s) return CM_EINVAL;
+  const uint32_t idx = (uint32_t)(ticket & 0xffff);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (idx >= s->max_requests) return CM_EINVAL;
+    Request& r = s->reqs[idx];
+    if (r.ticket != ticket || r.state != kDone) return CM_EINVAL;
+    if (r.out_bytes) s->ring.release(ticket);
+    r.state = kFree;
+    r.ticket = 0;
+    s->free_slots.push_back(idx);
+  }
+  s->cv_sched.notify_one();  // arena space may admit a waiting request
+  return CM_OK;
+}
+
+int cm_server_get_stats(cm_server* s, cm_server_stats* out) {
+  if (!s || !out) return CM_EINVAL;
+  std::vector<std::pair<float, float>> iv;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    iv = s->intervals;
+  }
+  double span = 0;
+  out->busy_ms = union_ms(std::move(iv), &span);
+  out->span_ms = span;
+  return CM_OK;
+}
+
+int cm_server_destroy(cm_server* s) {
+  if (!s) return CM_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->stop = true;
+  }
+  s->cv_sched.notify_one();
+  if (s->thread.joinable()) s->thread.join();
+  destroy_resources(s);
+  delete s;
+  return CM_OK;
+}
+
+}  // extern "C"

@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import collections
 import concurrent.futures
+import ctypes
 import threading
 import time
 from dataclasses import dataclass, field
@@ -351,3 +352,134 @@ class Server:
             "keys_per_s": (self.completed_outputs / span) if span else None,
             "budget_peak_bytes": self.budget.peak,
         }
+
+
+class ServerDone(ctypes.Structure):
+    """cm_server_done (64 bytes)."""
+    _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("C", ctypes.c_void_p), ("C_val", ctypes.c_void_p),
+                ("keys_offset", ctypes.c_uint64), ("vals_offset", ctypes.c_uint64),
+                ("queued_ns", ctypes.c_uint64), ("latency_ns", ctypes.c_uint64)]
+
+
+class ServerStats(ctypes.Structure):
+    """cm_server_stats (80 bytes)."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("failed", ctypes.c_uint64), ("canceled", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("max_batch_seen", ctypes.c_uint64),
+                ("arena_bytes", ctypes.c_uint64), ("arena_peak_bytes", ctypes.c_uint64),
+                ("busy_ms", ctypes.c_double), ("span_ms", ctypes.c_double)]
+
+
+class NativeServer:
+    """The library's own serving runtime (cm_server_*): a scheduler thread in
+    the library admits requests in arrival order against an output arena in
+    HBM (a torch buffer owned here), launches the admitted ones as one batch
+    per step on up to `max_inflight` streams, and reports finished merges to
+    poll().  A finished merge's outputs stay in the arena until release().
+    Python does argument marshalling only."""
+
+    def __init__(self, key_dtype="uint32", with_payload=True, arena_bytes=32 << 30,
+                 max_batch=64, max_inflight=2, max_requests=4096, device="cuda:0", arena=None):
+        import torch
+        from . import KEY_TYPES, load
+        self.torch = torch
+        self.device = torch.device(device)
+        self.key_dtype = getattr(torch, str(key_dtype).replace("torch.", ""))
+        self.with_payload = bool(with_payload)
+        self.arena = arena if arena is not None else torch.empty(
+            arena_bytes, dtype=torch.uint8, device=self.device)
+        if self.arena.dtype != torch.uint8 or self.arena.device != self.device \
+                or not self.arena.is_contiguous():
+            raise ValueError("the arena must be a contiguous uint8 tensor on the server's device")
+        self.lib = load()
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            rc = self.lib.cm_server_create(KEY_TYPES[str(self.key_dtype).replace("torch.", "")],
+                                           int(self.with_payload), self.arena.data_ptr(),
+                                           self.arena.numel(), max_batch, max_inflight,
+                                           max_requests, ctypes.byref(h))
+        self._check(rc, "cm_server_create")
+        self._h = h
+        self._ticket = ctypes.c_uint64()
+        self._cap = 256
+        self._done = (ServerDone * self._cap)()
+        self._count = ctypes.c_uint32()
+
+    def _check(self, rc, where):
+        if rc != 0:
+            from . import CMError
+            raise CMError(rc, where)
+
+    def submit_ptrs(self, A, A_val, m, B, B_val, n, stream=None, pending=False):
+        """Raw form (device addresses and sizes); returns the status and
+        sets self.last_ticket on success (CM_EBUSY = -9: no slot free)."""
+        rc = self.lib.cm_server_submit(self._h, A, A_val, m, B, B_val, n, stream,
+                                       1 if pending else 0, ctypes.byref(self._ticket))
+        self.last_ticket = self._ticket.value
+        return rc
+
+    def submit(self, A, B, A_val=None, B_val=None, stream=None):
+        """Queue a merge of device tensors; it waits for the work enqueued so
+        far on `stream` (default: the current stream), which produced them.
+        Returns the ticket."""
+        torch = self.torch
+        for t in (A, B) + ((A_val, B_val) if self.with_payload else ()):
+            if t is None or t.device != self.device or t.dim() != 1 or not t.is_contiguous():
+                raise ValueError("inputs must be contiguous 1-D tensors on the server's device")
+        if A.dtype != self.key_dtype or B.dtype != self.key_dtype:
+            raise TypeError(f"keys must be {self.key_dtype}")
+        if not self.with_payload and (A_val is not None or B_val is not None):
+            raise ValueError("this server has no payloads")
+        s = stream if stream is not None else torch.cuda.current_stream(self.device)
+        rc = self.submit_ptrs(A.data_ptr() if A.numel() else None,
+                              A_val.data_ptr() if self.with_payload and A.numel() else None,
+                              A.numel(), B.data_ptr() if B.numel() else None,
+                              B_val.data_ptr() if self.with_payload and B.numel() else None,
+                              B.numel(), s.cuda_stream, pending=True)
+        self._check(rc, "cm_server_submit")
+        return self.last_ticket
+
+    def poll(self, wait_us=0):
+        """Finished merges (cm_server_done entries), at most 256 per call."""
+        self._check(self.lib.cm_server_poll(self._h, self._done, self._cap,
+                                            ctypes.byref(self._count), int(wait_us)),
+                    "cm_server_poll")
+        return [self._done[k] for k in range(self._count.value)]
+
+    def outputs(self, done, num_outputs):
+        """Views of a finished merge's keys (and payloads) in the arena."""
+        ks = self.torch.empty(0, dtype=self.key_dtype).element_size()
+        keys = self.arena[done.keys_offset:done.keys_offset + num_outputs * ks].view(
+            self.key_dtype)
+        if not self.with_payload:
+            return keys
+        vals = self.arena[done.vals_offset:done.vals_offset + num_outputs * 4].view(
+            self.torch.uint32)
+        return keys, vals
+
+    def release(self, ticket):
+        self._check(self.lib.cm_server_release(self._h, ticket), "cm_server_release")
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(self.lib.cm_server_get_stats(self._h, ctypes.byref(st)),
+                    "cm_server_get_stats")
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._check(self.lib.cm_server_destroy(self._h), "cm_server_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

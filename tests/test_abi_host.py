@@ -48,7 +48,7 @@ def test_library_exports_every_declared_function():
 def test_status_strings_and_version():
     assert cm.load().cm_version() >= 1
     assert cm.status_string(OK) == "ok"
-    assert cm.status_string(ENOSPC) == "workspace too small"
+    assert cm.status_string(ENOSPC) == "workspace or arena too small"
 
 
 def test_host_co_rank_figure(figure):
@@ -280,3 +280,27 @@ def test_timing_argument_errors():
     assert lib.cm_timing_start(0) == EINVAL
     assert lib.cm_timing_stop(ctypes.byref(u), ctypes.byref(d), ctypes.byref(d), None, None,
                               None) == EINVAL
+
+
+def test_server_argument_errors():
+    lib = cm.load()
+    P = ctypes.c_void_p
+    h = ctypes.c_void_p()
+    assert lib.cm_server_create(0, 1, None, 1 << 20, 8, 2, 64, ctypes.byref(h)) == EINVAL
+    assert lib.cm_server_create(9, 1, P(0x1000), 1 << 20, 8, 2, 64, ctypes.byref(h)) == EDTYPE
+    assert lib.cm_server_create(0, 1, P(0x1000), 255, 8, 2, 64, ctypes.byref(h)) == EINVAL
+    assert lib.cm_server_create(0, 1, P(0x1000), 1 << 20, 0, 2, 64, ctypes.byref(h)) == EINVAL
+    assert lib.cm_server_create(0, 1, P(0x1000), 1 << 20, 8, 17, 64, ctypes.byref(h)) == EINVAL
+    assert lib.cm_server_create(0, 1, P(0x1000), 1 << 20, 8, 2, 65536, ctypes.byref(h)) == EINVAL
+    assert lib.cm_server_create(0, 1, P(0x1000), 1 << 20, 8, 2, 64, None) == EINVAL
+    assert h.value is None
+    t = ctypes.c_uint64()
+    n = ctypes.c_uint32()
+    assert lib.cm_server_submit(None, P(0x1000), P(0x2000), 4, P(0x3000), P(0x4000), 4, None, 0,
+                                ctypes.byref(t)) == EINVAL
+    assert lib.cm_server_poll(None, None, 0, ctypes.byref(n), 0) == EINVAL
+    assert lib.cm_server_release(None, 1) == EINVAL
+    assert lib.cm_server_get_stats(None, None) == EINVAL
+    assert lib.cm_server_destroy(None) == EINVAL
+    assert cm.status_string(-9) == "every request slot is taken"
+    assert cm.status_string(-10) == "canceled at shutdown"

@@ -202,10 +202,3 @@ def test_budget_accounting_errors():
     with pytest.raises(ValueError):
         serve.Budget(0)
 
-
-def test_interval_union():
-    import bench
-    assert bench.interval_union([], []) == 0.0
-    assert bench.interval_union([0.0], [2.0]) == 2.0
-    # overlapping, nested, touching and disjoint intervals, in any order
-    assert bench.interval_union([5.0, 0.0, 1.0, 2.0], [1.0, 2.0, 0.5, 1.0]) == 4.0
