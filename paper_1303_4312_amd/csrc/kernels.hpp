@@ -588,6 +588,19 @@ __device__ __forceinline__ uint32_t seg_of(const uint64_t* __restrict__ a_off,
   return lo;
 }
 
+// The same search over offset accessors (LDS table or global arrays).
+template <typename AO, typename BO>
+__device__ __forceinline__ uint32_t seg_of_at(AO ao, BO bo, uint32_t lo, uint32_t hi, uint64_t g) {
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo + 1) >> 1);
+    if (ao(mid) + bo(mid) <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
 // Block boundaries of the batch seen as one merge under (segment, key):
 // boundary i lies in segment s; its co-rank is a_off[s] plus the co-rank of
 // i - c_off[s] inside segment s (Algorithm 1 on that segment's arrays).
@@ -667,18 +680,16 @@ __global__ __launch_bounds__(256) void k_seg_fine_co_rank(const K* __restrict__ 
 // positions where segment s ends on each side (they may lie beyond the
 // window).  When both sides of the current segment are used up the run moves
 // on to the next non-empty segment.
-template <typename K, int E>
-__device__ __forceinline__ void merge_run_seg(const K* s_key, int a_len, int len, int a, int b, int avail,
-                                              const uint64_t* __restrict__ a_off,
-                                              const uint64_t* __restrict__ b_off, uint32_t S, uint32_t s,
-                                              uint64_t j0, uint64_t k0, K (&out_key)[E],
-                                              int (&out_src)[E]) {
+template <typename K, int E, typename AO, typename BO>
+__device__ __forceinline__ void merge_run_seg(const K* s_key, int a_len, int len, int a, int b, int avail, AO ao,
+                                              BO bo, uint32_t S, uint32_t s, uint64_t j0, uint64_t k0,
+                                              K (&out_key)[E], int (&out_src)[E]) {
   const int b_len = len - a_len;
   auto clamp_end = [](uint64_t end, uint64_t base) -> int {
     return (int)std::min(end - base, (uint64_t)INT_MAX);
   };
-  int a_end = clamp_end(a_off[s + 1], j0);
-  int b_end = clamp_end(b_off[s + 1], k0);
+  int a_end = clamp_end(ao(s + 1), j0);
+  int b_end = clamp_end(bo(s + 1), k0);
   K ka = a < a_len ? s_key[a] : K{};
   K kb = b < b_len ? s_key[a_len + b] : K{};
 #pragma unroll
@@ -686,8 +697,8 @@ __device__ __forceinline__ void merge_run_seg(const K* s_key, int a_len, int len
     if (e < avail) {
       while (a == a_end && b == b_end && s + 1 < S) {
         ++s;
-        a_end = clamp_end(a_off[s + 1], j0);
-        b_end = clamp_end(b_off[s + 1], k0);
+        a_end = clamp_end(ao(s + 1), j0);
+        b_end = clamp_end(bo(s + 1), k0);
       }
       const bool has_a = a < std::min(a_end, a_len);
       const bool has_b = b < std::min(b_end, b_len);
@@ -707,15 +718,22 @@ __device__ __forceinline__ void merge_run_seg(const K* s_key, int a_len, int len
   }
 }
 
-template <typename K, bool VAL, int NT, int E>
+// Offsets of the segments a block's outputs can lie in (s_first..s_last, so
+// entries s_first..s_last + 1) are staged in LDS when there are at most this
+// many segments; blocks over more (tiny) segments read them from HBM.
+constexpr uint32_t kSegTable = 256;
+
+// VST: C (and C_val) 16-byte aligned: the block leaves with 16-byte stores.
+template <typename K, bool VAL, int NT, int E, bool VST>
 __global__ __launch_bounds__(NT) void k_seg_merge_blocks(
     const K* __restrict__ A, const uint32_t* __restrict__ Av, const uint64_t* __restrict__ a_off,
     const K* __restrict__ B, const uint32_t* __restrict__ Bv, const uint64_t* __restrict__ b_off, uint32_t S,
     uint64_t N, K* __restrict__ C, uint32_t* __restrict__ Cv, const uint64_t* __restrict__ bj,
     const uint32_t* __restrict__ bs, uint64_t num_tiles, const uint32_t* __restrict__ flag, int search) {
   constexpr int T = NT * E;
-  __shared__ K s_key[T];
-  __shared__ uint32_t s_val[VAL ? T : 1];
+  __shared__ __attribute__((aligned(16))) K s_key[T];
+  __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T : 1];
+  __shared__ uint64_t s_aoff[kSegTable + 1], s_boff[kSegTable + 1];
   if (*flag) return;
   for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
     const uint64_t i0 = t * (uint64_t)T;
@@ -727,18 +745,35 @@ __global__ __launch_bounds__(NT) void k_seg_merge_blocks(
     const uint64_t j1 = j0 + (uint64_t)a_len;
     const uint32_t s_first = bs[t];
     const uint32_t s_last = bs[t + 1];
+    const uint32_t entries = s_last - s_first + 2;  // s_last + 1 <= S: inside a_off / b_off
+    const bool table = entries <= kSegTable + 1;     // block-uniform
+    if (table) {
+      for (uint32_t x = threadIdx.x; x < entries; x += NT) {
+        s_aoff[x] = a_off[s_first + x];
+        s_boff[x] = b_off[s_first + x];
+      }
+    }
     load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
     __syncthreads();
 
+    // offsets of segment s (s >= s_first): from the table when it holds s
+    auto ao = [&](uint32_t q) -> uint64_t {
+      const uint32_t x = q - s_first;
+      return table && x < entries ? s_aoff[x] : a_off[q];
+    };
+    auto bo = [&](uint32_t q) -> uint64_t {
+      const uint32_t x = q - s_first;
+      return table && x < entries ? s_boff[x] : b_off[q];
+    };
     const int d = std::min((int)threadIdx.x * E, len);
     const int avail = len - d;
     K ok[E];
     int os[E];
     if (avail > 0) {
       const uint64_t g = i0 + (uint64_t)d;
-      const uint32_t s = seg_of(a_off, b_off, s_first, s_last, g);
-      const uint64_t sa0 = a_off[s], sa1 = a_off[s + 1];
-      const uint64_t sb0 = b_off[s], sb1 = b_off[s + 1];
+      const uint32_t s = seg_of_at(ao, bo, s_first, s_last, g);
+      const uint64_t sa0 = ao(s), sa1 = ao(s + 1);
+      const uint64_t sb0 = bo(s), sb1 = bo(s + 1);
       // the part of segment s inside this block, in window coordinates; its
       // ends are exact co-rank cuts (block ends or segment ends)
       // (clamped into the windows so that unsorted input cannot lead outside)
@@ -754,8 +789,7 @@ __global__ __launch_bounds__(NT) void k_seg_merge_blocks(
       auto ra = [=](int x) { return sA[x]; };
       auto rb = [=](int x) { return sB[x]; };
       const int ja = co_rank<K, int>(search, dd, ra, wa1 - wa0, rb, wb1 - wb0);
-      merge_run_seg<K, E>(s_key, a_len, len, wa0 + ja, wb0 + (dd - ja), avail, a_off, b_off, S, s, j0, k0,
-                          ok, os);
+      merge_run_seg<K, E>(s_key, a_len, len, wa0 + ja, wb0 + (dd - ja), avail, ao, bo, S, s, j0, k0, ok, os);
     }
     uint32_t ov[E];
     if constexpr (VAL) {
@@ -772,7 +806,12 @@ __global__ __launch_bounds__(NT) void k_seg_merge_blocks(
       }
     }
     __syncthreads();
-    store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+    if constexpr (VST) {
+      store_span_vec<K, NT>(C, i0, len, s_key);
+      if constexpr (VAL) store_span_vec<uint32_t, NT>(Cv, i0, len, s_val);
+    } else {
+      store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+    }
     if (t + gridDim.x < num_tiles) __syncthreads();
   }
 }

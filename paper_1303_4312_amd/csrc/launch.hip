@@ -208,14 +208,25 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
     using K = decltype(key);
     return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
       constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      if (val)
-        hipLaunchKernelGGL((k_seg_merge_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
+      static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
+      // outputs 16-byte aligned: 16-byte stores (the inputs are staged element-wise)
+      const bool vst = val ? all_aligned16({C, Cv}) : all_aligned16({C});
+      auto go = [&](auto val_c, auto vst_c) {
+        constexpr bool V = decltype(val_c)::value, W = decltype(vst_c)::value;
+        hipLaunchKernelGGL((k_seg_merge_blocks<K, V, NT, E, W>), dim3((unsigned)tiles), dim3(NT), 0, st,
                            (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
                            ch.search);
+      };
+      using T_ = std::true_type;
+      using F_ = std::false_type;
+      if (val && vst)
+        go(T_{}, T_{});
+      else if (val)
+        go(T_{}, F_{});
+      else if (vst)
+        go(F_{}, T_{});
       else
-        hipLaunchKernelGGL((k_seg_merge_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
-                           ch.search);
+        go(F_{}, F_{});
       return launch_status();
     });
   });
