@@ -36,7 +36,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "merged keys/s & % of HBM peak; batched vs per-merge launches, bit-exact"
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_4312_amd", "csrc", f)
                   for f in ("kernels.hpp", "merge_device.hpp", "launch.hip")]
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_merge_blocks_zipf_u32_pairs_counters.md")
+COUNTERS_FILES = {
+    "zipf": os.path.join(ROOT, "profiles", "k_merge_blocks_zipf_u32_pairs_counters.md"),
+    "segmented": os.path.join(ROOT, "profiles", "k_seg_merge_blocks_segmented_u32_pairs_counters.md"),
+}
 
 
 def log(msg):
@@ -69,18 +72,23 @@ def workload_inputs(name):
     elif name in ("a_below_b", "interleaved", "all_equal"):
         d = w.structured(name)
         desc = f"single merge m=n=2^27, uint32 keys, structured case {name}, uint32 payloads"
+    elif name == "segmented":
+        d = w.segmented()
+        desc = ("segmented batch: 65536 merges, sides log-uniform in [1,2^16], uint32 keys "
+                "uniform in [0,2^20) sorted per segment, uint32 payloads")
     else:
         raise SystemExit(f"unknown workload {name}")
     return d, desc
 
 
-def read_traffic(alg_bytes, nt, e):
-    """Measured HBM bytes per launch of the block-merge kernel in tile
-    configuration nt x e, from the committed rocprofv3 counter summary of
-    this workload, if it was taken on this kernel source; else None."""
-    if not os.path.exists(COUNTERS_FILE):
+def read_traffic(workload, alg_bytes, nt, e):
+    """Measured HBM bytes per launch of the workload's block-merge kernel in
+    tile configuration nt x e, from the committed rocprofv3 counter summary
+    of this workload, if it was taken on this kernel source; else None."""
+    path = COUNTERS_FILES.get(workload)
+    if path is None or not os.path.exists(path):
         return None
-    text = open(COUNTERS_FILE).read()
+    text = open(path).read()
     m = re.search(r"```json\n(.*?)\n```", text, re.S)
     if not m:
         return None
@@ -102,7 +110,11 @@ def cpu_baseline_leg(d, C_gpu, Cv_gpu, seconds):
     reps, t_total, out = 0, 0.0, None
     while reps == 0 or t_total < seconds:
         t0 = time.perf_counter()
-        out = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        if "a_off" in d:
+            out = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
+                                                d["Bv"])
+        else:
+            out = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
         t_total += time.perf_counter() - t0
         reps += 1
     n = d["A"].size + d["B"].size
@@ -437,9 +449,32 @@ def main():
     key_bytes = A.element_size()
     C = torch.empty(N, dtype=A.dtype, device=dev)
     Cv = torch.empty(N, dtype=torch.uint32, device=dev)
-    ws = torch.empty(max(cm.merge_workspace_size(key_dtype, True, m, n), 1), dtype=torch.uint8,
-                     device=dev)
     stream = torch.cuda.current_stream(dev)
+    segmented = args.workload == "segmented"
+    if segmented:  # the step is one segmented-batch call
+        a_off = torch.from_numpy(d["a_off"]).to(dev)
+        b_off = torch.from_numpy(d["b_off"]).to(dev)
+        ws = torch.empty(max(cm.segmented_workspace_size(key_dtype, True, m, n,
+                                                         a_off.numel() - 1), 1),
+                         dtype=torch.uint8, device=dev)
+        op = cm.OP_SEGMENTED
+
+        def step():
+            cm.stable_merge_segmented(A, a_off, B, b_off, Av, Bv, C, Cv, workspace=ws,
+                                      stream=stream)
+
+        def tune():
+            return cm.autotune_segmented(A, a_off, B, b_off, Av, Bv, reps=3)
+    else:  # the step is one single-merge call
+        ws = torch.empty(max(cm.merge_workspace_size(key_dtype, True, m, n), 1),
+                         dtype=torch.uint8, device=dev)
+        op = cm.OP_MERGE
+
+        def step():
+            cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+
+        def tune():
+            return cm.autotune_merge(A, B, Av, Bv, reps=3)
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.uint32, device=dev)
@@ -456,12 +491,12 @@ def main():
     tuned = None
     if not args.no_tune:
         # off the timed path: pick the fastest configuration on this machine
-        tuned = cm.autotune_merge(A, B, Av, Bv, reps=3)
+        tuned = tune()
         log(f"autotuned choice (config, search, partition): {tuned}")
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
-        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+        step()
     torch.cuda.synchronize()
 
     log(f"timing {args.steps} steps")
@@ -469,7 +504,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+        step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     calls, co_rank_ms, merge_ms, _, call_each, merge_each = cm.timing_stop(per_call=True)
@@ -481,10 +516,12 @@ def main():
     per_elem = 2 * (key_bytes + 4)           # read + write one key and one payload
     alg_bytes = N * per_elem
     achieved = alg_bytes / (merge_ms * 1e-3) / 1e9
-    cfg, search, partition = cm.tuning_get(cm.OP_MERGE, key_dtype, True, N)
+    cfg, search, partition = cm.tuning_get(op, key_dtype, True, N)
     nt, e = cm.config_info(cfg)
-    streaming = partition == 3
-    traffic = None if streaming else read_traffic(alg_bytes, nt, e)
+    streaming = partition == 3 and not segmented
+    kernel = ("k_seg_merge_blocks" if segmented else
+              "k_merge_stream" if streaming else "k_merge_blocks")
+    traffic = None if streaming else read_traffic(args.workload, alg_bytes, nt, e)
     result = {
         "metric": METRIC,
         "value": value,
@@ -504,8 +541,9 @@ def main():
             "block": {"threads": nt, "items_per_thread": e},
             "search": ["algorithm1", "bisection"][search],
             "autotuned": tuned is not None,
-            "boundary_pass": ["one_level", "two_level_64", "two_level_16", "stream",
-                               "in_block"][partition],
+            "boundary_pass": (["one_level", "two_level"][partition != 0] if segmented else
+                              ["one_level", "two_level_64", "two_level_16", "stream",
+                               "in_block"][partition]),
         },
         "roofline": {
             "bound": "hbm",
@@ -514,7 +552,7 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_merge_stream" if streaming else "k_merge_blocks",
+            "kernel": kernel,
             "kernel_ms": merge_ms,
             "co_rank_pass_ms": co_rank_ms,
             "algorithmic_bytes_per_launch": alg_bytes,
@@ -542,6 +580,9 @@ def main():
 
     if not args.no_latency:
         result["latency"] = latency_leg()
+
+    if segmented:
+        result["config"]["segments"] = int(d["a_off"].size - 1)
 
     if not args.no_batched:
         del A, Av, B, Bv, C, Cv, ws
