@@ -216,6 +216,41 @@ def batched_leg(steps, warmup, tune):
     }
 
 
+def boundary_ab_leg(A, Av, B, Bv, C, Cv, ws, stream, key_dtype, op, reps=10):
+    """The boundary pass as an explicit A/B on the step's own arrays, same
+    tile as the timed step: synchronised one-level (0), two-level with a
+    64- or 16-lane coarse search (1, 2), and synchronisation-free (4: every
+    block co-ranks its own ends).  Median per-call times from the library's
+    events; the co-rank share is the boundary pass over the whole call."""
+    import torch
+    import paper_1303_4312_amd as cm
+    N = A.numel() + B.numel()
+    cls = N.bit_length()
+    saved = cm.tuning_get(op, key_dtype, True, N)
+    out = []
+    try:
+        for part in (0, 1, 2, 4):
+            cm.tuning_set(op, key_dtype, True, cls, saved[0], saved[1], part)
+            for _ in range(2):
+                cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+            torch.cuda.synchronize()
+            cm.timing_start(reps)
+            for _ in range(reps):
+                cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
+            torch.cuda.synchronize()
+            _, _, _, _, call_each, merge_each = cm.timing_stop(per_call=True)
+            call = statistics.median(call_each)
+            merge = statistics.median(merge_each)
+            out.append({"partition": part,
+                        "pass": ["one_level", "two_level_64", "two_level_16", "stream",
+                                 "in_block"][part],
+                        "call_ms": call, "merge_kernel_ms": merge,
+                        "co_rank_share": (call - merge) / call})
+    finally:
+        cm.tuning_set(op, key_dtype, True, cls, *saved)
+    return out
+
+
 def latency_leg(reps=200, warmup=20):
     """Small single merge, m = n = 2^20 uint32 keys uniform in [0, 2^16) with
     payloads: it fits in the Infinity Cache, so this is a warm-cache latency
@@ -422,6 +457,8 @@ def main():
                     help="skip the autotuner (use the library defaults)")
     ap.add_argument("--no-copy-ceiling", action="store_true",
                     help="skip measuring this box's plain-copy bandwidth")
+    ap.add_argument("--no-boundary-ab", action="store_true",
+                    help="skip the A/B of boundary passes on the step's arrays")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the small warm-cache latency leg")
     ap.add_argument("--no-serving", action="store_true",
@@ -566,6 +603,11 @@ def main():
                     "block-merge end, HIP events on the call's stream"},
         "step_hbm_frac": (alg_bytes / (elapsed / args.steps)) / 1e9 / HBM_PEAK_GBS,
     }
+
+    if not segmented and not args.no_boundary_ab:
+        result["boundary_ab"] = boundary_ab_leg(A, Av, B, Bv, C, Cv, ws, stream, key_dtype, op)
+        log("boundary A/B: " + ", ".join(f"{r['pass']} {r['call_ms']:.3f} ms"
+                                         for r in result["boundary_ab"]))
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -315,7 +315,8 @@ int cm_autotune_segmented(int key_type,
 /*
  * Tuning table.  Entries map (op, key_type, with_payload, size class) to
  * {config, search, partition}; op 0 = single merge, 1 = segmented batch,
- * 2 = batch of separate merges (size class of its total output count);
+ * 2 = batch of separate merges (size class of its total output count),
+ * 3 = stable sort (size class of n; the partition field is unused);
  * the size class of a merge of N outputs is the bit length of N (0..64).
  * A merge call uses the entry of its size class when there is one, else
  * the settings of cm_set_config / cm_set_search / cm_set_partition.
@@ -412,6 +413,37 @@ int cm_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
 int cm_timing_start(uint32_t capacity);
 int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean,
                    float *call_start_ms, float *call_ms, float *merge_ms);
+
+/*
+ * Stable merge sort built from the co-rank merge (Section 1: merging is the
+ * step of merge sort; Sections 2-3 give the perfectly balanced parallel
+ * merge each pass uses).  Sorts n keys (and their uint32 payloads) into
+ * keys_out (vals_out) in nondecreasing key order; equal keys keep their
+ * input order (stable).  Float keys compare as IEEE values (-0.0 == +0.0,
+ * NaN not allowed).
+ *   Runs of one block's size are first sorted inside LDS (per-thread sorting
+ *   networks, then co-rank merges in LDS); then ceil(log2(n / block)) passes
+ *   merge runs pairwise, each pass one boundary kernel and one block merge
+ *   over all pairs (Algorithm 2 per pair).  Passes alternate between the
+ *   output and the workspace.
+ * cm_sort_workspace_size(key_type, with_payload, n): bytes (a second key and
+ *   payload buffer of n entries plus one uint64 per block), 0 for n == 0.
+ * cm_stable_sort(key_type, keys, n, keys_out, workspace, bytes, stream)
+ * cm_stable_sort_pairs(key_type, keys, vals, n, keys_out, vals_out,
+ *   workspace, bytes, stream)
+ *   Device pointers; enqueued on `stream`.  keys_out may be keys itself and
+ *   vals_out vals itself (in place); any other overlap of outputs with
+ *   inputs, with each other or with the workspace is CM_EALIAS.  n == 0 is a
+ *   no-op.  Errors: CM_EDTYPE, CM_EINVAL (null pointer with n > 0),
+ *   CM_ENOSPC, CM_EALIAS, CM_EHIP.  The tile configuration and search come
+ *   from the tuning table (operation 3) or the process defaults.
+ */
+size_t cm_sort_workspace_size(int key_type, int with_payload, uint64_t n);
+int cm_stable_sort(int key_type, const void *keys, uint64_t n, void *keys_out, void *workspace,
+                   size_t workspace_bytes, hipStream_t stream);
+int cm_stable_sort_pairs(int key_type, const void *keys, const uint32_t *vals, uint64_t n,
+                         void *keys_out, uint32_t *vals_out, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream);
 
 /*
  * Serving runtime (not part of the method; it feeds the batch call above).

@@ -15,6 +15,11 @@ only compiles it, loads it and marshals numpy arrays:
 - :func:`co_rank_alg1` -- Algorithm 1 (Section 2) with its state trace.
 - :func:`stable_merge_segmented` -- the merge applied to each segment of a
   batch independently.
+- :func:`stable_sort` -- the stable sort merge sort computes (Section 1
+  names merging as the step of merge sort): the permutation that orders the
+  keys, equal keys in input order.  numpy's stable argsort is the step; no
+  merge code is involved, so the GPU merge sort is checked against the
+  definition rather than against another merge sort.
 
 Key types: numpy uint32, uint64, float32. Payloads: uint32 or None.
 """
@@ -162,3 +167,15 @@ def stable_merge_segmented(A, a_off, B, b_off, Av=None, Bv=None):
                                           _ptr(B), _ptr(Bv), _ptr(b_off), a_off.size - 1,
                                           _ptr(C), _ptr(Cv))
     return C if Cv is None else (C, Cv)
+
+
+def stable_sort(keys, vals=None):
+    """Keys sorted nondecreasingly, equal keys keeping their input order
+    (IEEE comparison for float32: -0.0 and +0.0 are equal keys); payloads
+    follow their keys.  Returns keys, or (keys, payloads)."""
+    k = _keys(keys)
+    order = np.argsort(k, kind="stable")
+    if vals is None:
+        return k[order]
+    v = _pay(vals, k.size)
+    return k[order], v[order]

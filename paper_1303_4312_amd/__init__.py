@@ -27,7 +27,8 @@ __all__ = [
     "copy", "timing_start", "timing_stop", "get_search", "set_partition", "get_partition",
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
     "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
-    "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "stable_merge_batch", "batch_descriptors",
+    "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
+    "stable_sort", "sort_workspace_size",
     "launch_batch", "set_coarse_stride", "set_block_order",
 ]
 
@@ -37,7 +38,7 @@ library_path = os.path.join(_HERE, "libcorank_merge.so")
 # C enum cm_key_type
 KEY_U32, KEY_U64, KEY_F32 = 0, 1, 2
 # operations of the tuning table
-OP_MERGE, OP_SEGMENTED, OP_BATCH = 0, 1, 2
+OP_MERGE, OP_SEGMENTED, OP_BATCH, OP_SORT = 0, 1, 2, 3
 KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
 
 EXPORTS = [
@@ -53,7 +54,8 @@ EXPORTS = [
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
     "cm_set_coarse_stride", "cm_set_block_order",
     "cm_server_create", "cm_server_submit", "cm_server_poll", "cm_server_release",
-    "cm_server_get_stats", "cm_server_destroy",
+    "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_stable_sort",
+    "cm_stable_sort_pairs",
 ]
 
 _lib = None
@@ -74,6 +76,12 @@ def load():
         raise RuntimeError(
             f"{library_path} is missing: build it with "
             "`python -m paper_1303_4312_amd.build` (no CPU fallback exists)")
+    # torch first: its HIP runtime (requested under the name libamdhip64.so)
+    # must be the one the library binds (libamdhip64.so.7, satisfied by the
+    # already-loaded runtime's soname).  Loaded the other way round, the
+    # process would hold two HIP runtimes and torch's streams and memory would
+    # be foreign to the library's launches.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(library_path)
     c_int, c_u64, c_size, vp = ctypes.c_int, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_void_p
     p64 = ctypes.POINTER(ctypes.c_uint64)
@@ -133,6 +141,9 @@ def load():
         "cm_server_release": (c_int, [vp, c_u64]),
         "cm_server_get_stats": (c_int, [vp, vp]),
         "cm_server_destroy": (c_int, [vp]),
+        "cm_sort_workspace_size": (c_size, [c_int, c_int, c_u64]),
+        "cm_stable_sort": (c_int, [c_int, vp, c_u64, vp, vp, c_size, vp]),
+        "cm_stable_sort_pairs": (c_int, [c_int, vp, vp, c_u64, vp, vp, vp, c_size, vp]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
@@ -397,6 +408,44 @@ def timing_stop(per_call=False):
     if not per_call:
         return calls.value, tb.value, tm.value
     return (calls.value, tb.value, tm.value) + tuple(list(a[:calls.value]) for a in arrays)
+
+
+def sort_workspace_size(key_dtype, with_payload: bool, n: int) -> int:
+    kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
+    return load().cm_sort_workspace_size(kt, int(bool(with_payload)), n)
+
+
+def stable_sort(keys, vals=None, out=None, out_vals=None, workspace=None, stream=None):
+    """Stable merge sort of a device key array (with uint32 payloads if vals
+    is given).  out / out_vals may be the inputs themselves (in place).
+    Returns the sorted keys, or (keys, payloads)."""
+    torch = _torch()
+    keys = _dev(keys, "keys")
+    kt = _key_type(keys)
+    n = keys.numel()
+    with_val = vals is not None
+    if with_val:
+        vals = _dev(vals, "vals", torch.uint32)
+        if vals.numel() != n:
+            raise ValueError("vals must be as long as keys")
+    if out is None:
+        out = torch.empty_like(keys)
+    if with_val and out_vals is None:
+        out_vals = torch.empty_like(vals)
+    out = _dev(out, "out", keys.dtype)
+    if out.numel() != n or (with_val and _dev(out_vals, "out_vals", torch.uint32).numel() != n):
+        raise ValueError("outputs must be as long as keys")
+    ws, wsb = _workspace(load().cm_sort_workspace_size(kt, int(with_val), n), keys.device,
+                         workspace)
+    s = _stream(stream, keys.device)
+    if with_val:
+        _check(load().cm_stable_sort_pairs(kt, _ptr(keys), _ptr(vals), n, _ptr(out),
+                                           _ptr(out_vals), _ptr(ws), wsb, s),
+               "cm_stable_sort_pairs")
+        return out, out_vals
+    _check(load().cm_stable_sort(kt, _ptr(keys), n, _ptr(out), _ptr(ws), wsb, s),
+           "cm_stable_sort")
+    return out
 
 
 def check_sorted(X, stream=None) -> bool:

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_NAME = "libcorank_merge.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-HIP_SOURCES = ["launch.hip"]
+HIP_SOURCES = ["launch.hip", "sort.hip"]
 CXX_SOURCES = ["api.cpp", "host_co_rank.cpp", "server.cpp"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed fp32 VALU ops.

@@ -239,6 +239,51 @@ Choice batch_choice(int kt, bool val, const cm_merge_desc* d, uint32_t count) {
   return ch;
 }
 
+// ---- stable merge sort
+
+// Workspace of a sort: a second key (and payload) buffer for the passes and
+// one block co-rank per block (sized for the smallest block).
+size_t sort_ws_bytes(int kt, bool val, uint64_t N) {
+  if (N == 0) return 0;
+  return round256(N * key_bytes(kt)) + (val ? round256(N * 4) : 0) +
+         round256(((N + kMinTile - 1) / kMinTile + 1) * sizeof(uint64_t));
+}
+
+int sort_impl(int kt, bool val, const void* X, const uint32_t* Xv, uint64_t N, void* Y, uint32_t* Yv, void* ws,
+              size_t ws_bytes, hipStream_t st) {
+  if (!key_type_ok(kt)) return CM_EDTYPE;
+  if (N && (!X || !Y)) return CM_EINVAL;
+  if (val && N && (!Xv || !Yv)) return CM_EINVAL;
+  if (N == 0) return CM_OK;
+  const size_t ks = key_bytes(kt);
+  const size_t need = sort_ws_bytes(kt, val, N);
+  if (!ws || ws_bytes < need) return CM_ENOSPC;
+  // outputs may be the inputs themselves (in place) but must not overlap them otherwise
+  const Span yk{Y == X ? nullptr : Y, N * ks};
+  const Span yv{val && Yv != Xv ? Yv : nullptr, val ? N * 4 : 0};
+  if (any_overlap({yk, yv, {ws, need}}, {{X, N * ks}, {Xv, val ? N * 4 : 0}}) ||
+      any_overlap({{Y, N * ks}, {Yv, val ? N * 4 : 0}, {ws, need}}, {}))
+    return CM_EALIAS;
+  const Choice ch = resolve(kOpSort, kt, val, N);
+  const uint64_t T = tile_size(ch.cfg);
+  const uint64_t tiles = (N + T - 1) / T;
+  if (tiles >= (1ull << 31)) return CM_EINVAL;
+  int passes = 0;
+  for (uint64_t L = T; L < N; L *= 2) ++passes;
+  char* w = (char*)ws;
+  void* bk[2] = {Y, w};
+  uint32_t* bv[2] = {Yv, val ? (uint32_t*)(w + round256(N * ks)) : nullptr};
+  uint64_t* bj = (uint64_t*)(w + round256(N * ks) + (val ? round256(N * 4) : 0));
+  // ping-pong between Y and the workspace so that the last pass writes Y
+  int cur = passes % 2;
+  int rc = launch_sort_blocks(kt, val, ch.cfg, X, val ? Xv : nullptr, N, bk[cur], bv[cur], tiles, st);
+  for (int sh = 1; rc == CM_OK && sh <= passes; ++sh) {  // runs of T << (sh - 1)
+    rc = launch_sort_pass(kt, val, ch, g_set.shape, bk[cur], bv[cur], N, sh, bk[cur ^ 1], bv[cur ^ 1], bj, tiles, st);
+    cur ^= 1;
+  }
+  return rc;
+}
+
 // Do any of the byte ranges in `outs` overlap each other or any range in
 // `ins`?  Sorting keeps this O((outs + ins) log outs) for large batches.
 bool spans_overlap(std::vector<Span>& outs, const std::vector<Span>& ins) {
@@ -616,7 +661,7 @@ int cm_tuning_clear(void) {
 
 int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int config_id, int search_mode,
                   int partition_mode) {
-  if (op != kOpMerge && op != kOpSegmented && op != kOpBatch) return CM_EINVAL;
+  if (op < kOpMerge || op > kOpSort) return CM_EINVAL;
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
   if (size_cls < 0 || size_cls > 64 || (search_mode != 0 && search_mode != 1) || partition_mode < 0 ||
@@ -667,7 +712,7 @@ int cm_tuning_load(const char* path) {
     int op, kt, val, sc, cfg, search, part;
     double ms;
     if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
-        (op != kOpMerge && op != kOpSegmented && op != kOpBatch) || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
+        op < kOpMerge || op > kOpSort || !key_type_ok(kt) || (val != 0 && val != 1) || sc < 0 ||
         sc > 64 || cfg < 0 || cfg >= kNumCfgs || (search != 0 && search != 1) || part < 0 || part > kMaxPartition) {
       rc = CM_EINVAL;
       break;
@@ -800,6 +845,21 @@ int cm_copy(const void* src, void* dst, uint64_t bytes, hipStream_t stream) {
   if (!src || !dst || (bytes % 16) || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) return CM_EINVAL;
   if (overlap(src, bytes, dst, bytes)) return CM_EALIAS;
   return launch_copy16(src, dst, bytes / 16, stream);
+}
+
+size_t cm_sort_workspace_size(int key_type, int with_payload, uint64_t n) {
+  if (!key_type_ok(key_type)) return 0;
+  return sort_ws_bytes(key_type, with_payload != 0, n);
+}
+
+int cm_stable_sort(int key_type, const void* keys, uint64_t n, void* keys_out, void* workspace,
+                   size_t workspace_bytes, hipStream_t stream) {
+  return sort_impl(key_type, false, keys, nullptr, n, keys_out, nullptr, workspace, workspace_bytes, stream);
+}
+
+int cm_stable_sort_pairs(int key_type, const void* keys, const uint32_t* vals, uint64_t n, void* keys_out,
+                         uint32_t* vals_out, void* workspace, size_t workspace_bytes, hipStream_t stream) {
+  return sort_impl(key_type, true, keys, vals, n, keys_out, vals_out, workspace, workspace_bytes, stream);
 }
 
 int cm_timing_start(uint32_t capacity) {

@@ -28,7 +28,7 @@ extern const uint64_t kMinTile;
 // workspace).
 constexpr uint32_t kMinCoarse = 16;
 
-enum Op : int { kOpMerge = 0, kOpSegmented = 1, kOpBatch = 2 };
+enum Op : int { kOpMerge = 0, kOpSegmented = 1, kOpBatch = 2, kOpSort = 3 };
 
 // How one call runs.
 struct Choice {
@@ -67,6 +67,14 @@ inline bool all_aligned16(std::initializer_list<const void*> ps) {
     if (((uintptr_t)p & 15) != 0) return false;
   return true;
 }
+
+// Merge sort (sort.hip): sort every run of T = tile_size(cfg) elements of X
+// into Y; then one pass merging runs of 2^(sh-1) blocks (T << (sh - 1)
+// elements) of X pairwise into Y (block co-ranks in bj, `tiles` entries).
+int launch_sort_blocks(int kt, bool val, int cfg, const void* X, const uint32_t* Xv, uint64_t N, void* Y,
+                       uint32_t* Yv, uint64_t tiles, hipStream_t st);
+int launch_sort_pass(int kt, bool val, const Choice& ch, const Shape& shape, const void* X, const uint32_t* Xv,
+                     uint64_t N, int sh, void* Y, uint32_t* Yv, uint64_t* bj, uint64_t tiles, hipStream_t st);
 
 // Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj
 // (bj == nullptr: each block searches its own two boundary co-ranks).

@@ -555,24 +555,6 @@ __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __re
 
 // ---- segmented batch -------------------------------------------------------
 
-// flag |= 1 if the offsets are inconsistent (not starting at 0, decreasing
-// somewhere, or not ending at the host totals).  Grid-stride over the
-// segments; the flag is cleared by k_fill_u32 before.  Every later kernel of
-// the call reads the flag and does nothing when it is set.
-__global__ __launch_bounds__(256) void k_seg_validate(const uint64_t* __restrict__ a_off,
-                                                      const uint64_t* __restrict__ b_off, uint64_t S,
-                                                      uint64_t total_a, uint64_t total_b,
-                                                      uint32_t* __restrict__ flag) {
-  int bad = 0;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride)
-    if (a_off[s] > a_off[s + 1] || b_off[s] > b_off[s + 1]) bad = 1;
-  if (blockIdx.x == 0 && threadIdx.x == 0 &&
-      (a_off[0] != 0 || b_off[0] != 0 || a_off[S] != total_a || b_off[S] != total_b))
-    bad = 1;
-  if (__any(bad) && (threadIdx.x % warpSize) == 0) atomicOr(flag, 1u);
-}
-
 // Largest s in [lo, hi] with a_off[s] + b_off[s] <= g (the segment holding
 // output position g; empty segments before it are skipped).
 __device__ __forceinline__ uint32_t seg_of(const uint64_t* __restrict__ a_off,
@@ -825,18 +807,6 @@ __global__ __launch_bounds__(256) void k_check_sorted(const K* __restrict__ X, u
   for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1; x < len; x += stride)
     if (X[x - 1] > X[x]) bad = 1;
   if (__any(bad) && (threadIdx.x % warpSize) == 0) atomicOr(flag, 1u);
-}
-
-__global__ void k_fill_u32(uint32_t* p, uint32_t v) { *p = v; }
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-// Plain streaming copy, 16 bytes per lane per step, grid-stride.
-__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
-                                                uint64_t count) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += stride)
-    __builtin_nontemporal_store(__builtin_nontemporal_load(src + x), dst + x);
 }
 
 }  // namespace cm

@@ -7,6 +7,7 @@
 #include <type_traits>
 
 #include "corank_merge.h"
+#include "dispatch.hpp"
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -19,32 +20,36 @@ const TileCfg kCfgs[] = {{256, 7}, {256, 11}, {256, 15}, {128, 7}, {512, 7}, {25
 const int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 const uint64_t kMinTile = 128 * 7;  // smallest nt * e in kCfgs
 
-static int launch_status() { return hipGetLastError() == hipSuccess ? CM_OK : CM_EHIP; }
+// ---- non-template kernels (launched from this file only)
 
-template <typename F>
-static int by_key(int kt, F&& f) {
-  switch (kt) {
-    case CM_KEY_U32: return f(uint32_t{});
-    case CM_KEY_U64: return f(uint64_t{});
-    default: return f(float{});
-  }
+// flag |= 1 if the offsets are inconsistent (not starting at 0, decreasing
+// somewhere, or not ending at the host totals).  Grid-stride over the
+// segments; the flag is cleared by k_fill_u32 before.  Every later kernel of
+// the call reads the flag and does nothing when it is set.
+__global__ __launch_bounds__(256) void k_seg_validate(const uint64_t* __restrict__ a_off,
+                                                      const uint64_t* __restrict__ b_off, uint64_t S,
+                                                      uint64_t total_a, uint64_t total_b,
+                                                      uint32_t* __restrict__ flag) {
+  int bad = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < S; s += stride)
+    if (a_off[s] > a_off[s + 1] || b_off[s] > b_off[s + 1]) bad = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0 &&
+      (a_off[0] != 0 || b_off[0] != 0 || a_off[S] != total_a || b_off[S] != total_b))
+    bad = 1;
+  if (__any(bad) && (threadIdx.x % warpSize) == 0) atomicOr(flag, 1u);
 }
 
-// Calls f(std::integral_constant<int, NT>, std::integral_constant<int, E>)
-// for configuration cfg; the cases must match kCfgs.
-template <typename F>
-static int by_cfg(int cfg, F&& f) {
-  switch (cfg) {
-    case 0: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 7>{});
-    case 1: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 11>{});
-    case 2: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 15>{});
-    case 3: return f(std::integral_constant<int, 128>{}, std::integral_constant<int, 7>{});
-    case 4: return f(std::integral_constant<int, 512>{}, std::integral_constant<int, 7>{});
-    case 5: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 5>{});
-    case 6: return f(std::integral_constant<int, 256>{}, std::integral_constant<int, 9>{});
-    case 7: return f(std::integral_constant<int, 512>{}, std::integral_constant<int, 11>{});
-    default: return CM_ECONFIG;
-  }
+__global__ void k_fill_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Plain streaming copy, 16 bytes per lane per step, grid-stride.
+__global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
+                                                uint64_t count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < count; x += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + x), dst + x);
 }
 
 int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,

@@ -304,3 +304,21 @@ def test_server_argument_errors():
     assert lib.cm_server_destroy(None) == EINVAL
     assert cm.status_string(-9) == "every request slot is taken"
     assert cm.status_string(-10) == "canceled at shutdown"
+
+
+def test_one_hip_runtime_whatever_the_import_order(tmp_path):
+    """Loading the library before torch must not leave two HIP runtimes in
+    the process (torch's streams and memory would be foreign to the
+    library's launches).  Checked in a fresh interpreter from its mappings."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1303_4312_amd as cm\n"
+        "cm.load()\n"
+        "import torch\n"
+        "paths = {l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}\n"
+        "print(len(paths))\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300, check=True).stdout.split()
+    assert out[-1] == "1", f"HIP runtimes mapped: {out[-1]}"
