@@ -251,6 +251,107 @@ def boundary_ab_leg(A, Av, B, Bv, C, Cv, ws, stream, key_dtype, op, reps=10):
     return out
 
 
+def partition_ablation_leg(A, Av, B, Bv, C, Cv, P=2048, reps=5):
+    """The paper's claim against the classic cross-rank partition, on the
+    step's own arrays: P workgroups each merge one output segment (the
+    streaming kernel), the segments cut by co-ranking (equal lengths) or by
+    P/2 equidistant samples of each array cross-ranked in the other.  Same
+    kernel, same P; reported: merge kernel and partition times (median of
+    the library's events) and the longest segment over the mean."""
+    import torch
+    import paper_1303_4312_amd as cm
+    N = A.numel() + B.numel()
+    out = {"P": P}
+    ref = None
+    for part, name in ((0, "co_rank"), (1, "cross_rank")):
+        cm.merge_partition_ablation(A, B, Av, Bv, P=P, partition=part, C=C, C_val=Cv)
+        torch.cuda.synchronize()
+        cm.timing_start(reps)
+        for _ in range(reps):
+            _, _, bounds = cm.merge_partition_ablation(A, B, Av, Bv, P=P, partition=part, C=C,
+                                                       C_val=Cv)
+        torch.cuda.synchronize()
+        _, _, _, _, call_each, merge_each = cm.timing_stop(per_call=True)
+        b = bounds.cpu().numpy().astype("float64")
+        seg = b[1:] - b[:-1]
+        if ref is None:
+            ref = (C.clone(), Cv.clone())
+            same = True
+        else:
+            same = bool(torch.equal(ref[0], C) and torch.equal(ref[1], Cv))
+        merge_ms = statistics.median(merge_each)
+        out[name] = {"merge_kernel_ms": merge_ms,
+                     "partition_ms": statistics.median(call_each) - merge_ms,
+                     "longest_segment_over_mean": float(seg.max() / (N / P)),
+                     "shortest_segment_over_mean": float(seg.min() / (N / P)),
+                     "identical_output": same}
+    out["cross_rank_over_co_rank"] = (out["cross_rank"]["merge_kernel_ms"] /
+                                      out["co_rank"]["merge_kernel_ms"])
+    return out
+
+
+def sort_leg(lg=28, reps=5, seed=2024):
+    """Stable merge sort (NEXT step on from the merge: merge sort's passes
+    are batched co-rank merges) of 2^lg uint32 keys uniform on [0, 2^32)
+    with uint32 payloads (the input position).  Beside it, the library
+    reference torch.sort(stable=True) plus the payload gather, on the same
+    arrays; the two results must be identical."""
+    import numpy as np
+    import torch
+    import paper_1303_4312_amd as cm
+    dev = torch.device("cuda:0")
+    n = 1 << lg
+    rng = np.random.default_rng(seed)
+    k = torch.from_numpy(rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)).to(dev)
+    v = torch.arange(n, dtype=torch.int32, device=dev)
+    out = torch.empty_like(k)
+    outv = torch.empty_like(v)
+    ws = torch.empty(cm.sort_workspace_size("uint32", True, n), dtype=torch.uint8, device=dev)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return statistics.median(ts)
+
+    ms = timed(lambda: cm.stable_sort(k, v.view(torch.uint32), out, outv.view(torch.uint32),
+                                      workspace=ws))
+    k64 = k.to(torch.int64)  # int64 keeps the uint32 order for torch.sort
+    res = {}
+
+    def ref():
+        s, idx = torch.sort(k64, stable=True)
+        res["k"], res["v"] = s, v[idx]
+
+    ms_ref = timed(ref)
+    same = bool(torch.equal(res["k"].to(torch.int32).view(torch.uint32), out) and
+                torch.equal(res["v"], outv))
+    cfg, search, _ = cm.tuning_get(cm.OP_SORT, "uint32", True, n)
+    nt, e = cm.config_info(cfg)
+    passes = 0  # runs of nt * e doubled until one covers n
+    while (nt * e) << passes < n:
+        passes += 1
+    return {
+        "workload": f"stable sort of 2^{lg} uint32 keys uniform on [0,2^32), uint32 payloads",
+        "keys": n,
+        "ms": ms,
+        "keys_per_s": n / (ms * 1e-3),
+        "block": {"threads": nt, "items_per_thread": e},
+        "merge_passes": passes,
+        "torch_sort_stable_ms": ms_ref,
+        "speedup_vs_torch_sort": ms_ref / ms,
+        "identical_to_torch_sort": same,
+    }
+
+
 def latency_leg(reps=200, warmup=20):
     """Small single merge, m = n = 2^20 uint32 keys uniform in [0, 2^16) with
     payloads: it fits in the Infinity Cache, so this is a warm-cache latency
@@ -461,6 +562,10 @@ def main():
                     help="skip the A/B of boundary passes on the step's arrays")
     ap.add_argument("--no-latency", action="store_true",
                     help="skip the small warm-cache latency leg")
+    ap.add_argument("--no-ablation", action="store_true",
+                    help="skip the co-rank vs cross-rank partition ablation")
+    ap.add_argument("--no-sort", action="store_true",
+                    help="skip the stable merge sort leg")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (Poisson arrivals, p50/p99)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -609,6 +714,13 @@ def main():
         log("boundary A/B: " + ", ".join(f"{r['pass']} {r['call_ms']:.3f} ms"
                                          for r in result["boundary_ab"]))
 
+    if not segmented and not args.no_ablation:
+        result["partition_ablation"] = partition_ablation_leg(A, Av, B, Bv, C, Cv)
+        pa = result["partition_ablation"]
+        log(f"partition ablation (P={pa['P']}): co-rank {pa['co_rank']['merge_kernel_ms']:.3f} ms, "
+            f"cross-rank {pa['cross_rank']['merge_kernel_ms']:.3f} ms, longest segment "
+            f"{pa['cross_rank']['longest_segment_over_mean']:.2f} x mean")
+
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")
         C_h = C.cpu().numpy()
@@ -625,6 +737,12 @@ def main():
 
     if segmented:
         result["config"]["segments"] = int(d["a_off"].size - 1)
+
+    if not args.no_sort:
+        torch.cuda.empty_cache()
+        result["sort"] = sort_leg()
+        log(f"sort: {result['sort']['ms']:.2f} ms ({result['sort']['keys_per_s'] / 1e9:.1f} G keys/s), "
+            f"torch.sort stable {result['sort']['torch_sort_stable_ms']:.2f} ms")
 
     if not args.no_batched:
         del A, Av, B, Bv, C, Cv, ws

@@ -415,6 +415,34 @@ int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_me
                    float *call_start_ms, float *call_ms, float *merge_ms);
 
 /*
+ * Partition ablation (the prior art the paper improves on, Section 1).  The
+ * merge with P processing elements, each a workgroup merging one contiguous
+ * output segment through LDS ring buffers (the streaming kernel of
+ * boundary mode 3), with the segments cut in one of two ways:
+ *   partition 0: P segments of equal length, cut by co-ranking their ends
+ *     (Lemma 1 / Algorithm 2 of the paper);
+ *   partition 1: the classic cross-rank partition: P / 2 equidistant
+ *     samples of A and P / 2 of B, each ranked in the other array by
+ *     binary search; the P sample cuts in output order bound the segments,
+ *     which hold at most ceil(2m / P) elements of A and ceil(2n / P) of B
+ *     and may differ in length by a factor of two.
+ * Both produce the merge of cm_stable_merge_pairs (payload pointers all NULL
+ * for keys only); only the balance of the segments differs.
+ * cm_partition_ablation_workspace_size(P): workspace bytes.
+ * cm_merge_partition_ablation(key_type, A, A_val, m, B, B_val, n, C, C_val,
+ *   P, partition, bounds, workspace, bytes, stream): P even in [2, 2^20];
+ *   bounds: device array of P + 1 uint64 that receives the segment starts
+ *   (bounds[P] = m + n).  Timing events (cm_timing_start) separate the
+ *   partition kernels from the merge kernel.  Errors as for
+ *   cm_stable_merge_pairs; CM_EINVAL for a bad P or partition.
+ */
+size_t cm_partition_ablation_workspace_size(uint32_t P);
+int cm_merge_partition_ablation(int key_type, const void *A, const uint32_t *A_val, uint64_t m,
+                                const void *B, const uint32_t *B_val, uint64_t n, void *C,
+                                uint32_t *C_val, uint32_t P, int partition, uint64_t *bounds,
+                                void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Stable merge sort built from the co-rank merge (Section 1: merging is the
  * step of merge sort; Sections 2-3 give the perfectly balanced parallel
  * merge each pass uses).  Sorts n keys (and their uint32 payloads) into

@@ -28,7 +28,7 @@ __all__ = [
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
     "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
-    "stable_sort", "sort_workspace_size",
+    "stable_sort", "sort_workspace_size", "merge_partition_ablation",
     "launch_batch", "set_coarse_stride", "set_block_order",
 ]
 
@@ -55,7 +55,7 @@ EXPORTS = [
     "cm_set_coarse_stride", "cm_set_block_order",
     "cm_server_create", "cm_server_submit", "cm_server_poll", "cm_server_release",
     "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_stable_sort",
-    "cm_stable_sort_pairs",
+    "cm_stable_sort_pairs", "cm_partition_ablation_workspace_size", "cm_merge_partition_ablation",
 ]
 
 _lib = None
@@ -144,6 +144,9 @@ def load():
         "cm_sort_workspace_size": (c_size, [c_int, c_int, c_u64]),
         "cm_stable_sort": (c_int, [c_int, vp, c_u64, vp, vp, c_size, vp]),
         "cm_stable_sort_pairs": (c_int, [c_int, vp, vp, c_u64, vp, vp, vp, c_size, vp]),
+        "cm_partition_ablation_workspace_size": (c_size, [ctypes.c_uint32]),
+        "cm_merge_partition_ablation": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp,
+                                                ctypes.c_uint32, c_int, vp, vp, c_size, vp]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_float),
                                    ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)]),
@@ -446,6 +449,23 @@ def stable_sort(keys, vals=None, out=None, out_vals=None, workspace=None, stream
     _check(load().cm_stable_sort(kt, _ptr(keys), n, _ptr(out), _ptr(ws), wsb, s),
            "cm_stable_sort")
     return out
+
+
+def merge_partition_ablation(A, B, A_val=None, B_val=None, P=2048, partition=0, C=None,
+                             C_val=None, stream=None):
+    """The merge with P workgroups each merging one output segment; segments
+    cut by co-ranking (partition 0) or by the classic cross-rank partition
+    (1).  Returns (C[, C_val], bounds) with bounds the P + 1 segment starts
+    (a device uint64 tensor)."""
+    torch = _torch()
+    kt, with_val, m, n, A, A_val, B, B_val, C, C_val = _pair_args(A, B, A_val, B_val, C, C_val)
+    bounds = torch.empty(P + 1, dtype=torch.uint64, device=A.device)
+    ws, wsb = _workspace(load().cm_partition_ablation_workspace_size(P), A.device, None)
+    _check(load().cm_merge_partition_ablation(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n,
+                                              _ptr(C), _ptr(C_val), P, partition, _ptr(bounds),
+                                              _ptr(ws), wsb, _stream(stream, A.device)),
+           "cm_merge_partition_ablation")
+    return ((C, C_val) if with_val else (C,)) + (bounds,)
 
 
 def check_sorted(X, stream=None) -> bool:

@@ -172,7 +172,7 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
     int rc = launch_stream_co_ranks(kt, A, m, B, n, P, bj, st);
     if (rc != CM_OK) return rc;
     timing_mark(1, st);
-    rc = launch_merge_stream(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, bj, P, st);
+    rc = launch_merge_stream(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, nullptr, bj, P, st);
     timing_mark(2, st);
     return rc;
   }
@@ -845,6 +845,43 @@ int cm_copy(const void* src, void* dst, uint64_t bytes, hipStream_t stream) {
   if (!src || !dst || (bytes % 16) || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) return CM_EINVAL;
   if (overlap(src, bytes, dst, bytes)) return CM_EALIAS;
   return launch_copy16(src, dst, bytes / 16, stream);
+}
+
+size_t cm_partition_ablation_workspace_size(uint32_t P) {
+  if (P < 2) return 0;
+  return round256(((size_t)P + 1) * sizeof(uint64_t)) + round256(2 * (size_t)P * sizeof(uint64_t));
+}
+
+int cm_merge_partition_ablation(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                                const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, uint32_t P,
+                                int partition, uint64_t* bounds, void* workspace, size_t workspace_bytes,
+                                hipStream_t stream) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  const bool val = A_val || B_val || C_val;
+  if (m + n < m || P < 2 || (P & 1) || P > (1u << 20) || (partition != 0 && partition != 1) || !bounds)
+    return CM_EINVAL;
+  const uint64_t N = m + n;
+  const size_t ks = key_bytes(key_type);
+  if ((m && !A) || (n && !B) || (N && !C)) return CM_EINVAL;
+  if (val && ((m && !A_val) || (n && !B_val) || (N && !C_val))) return CM_EINVAL;
+  const size_t need = cm_partition_ablation_workspace_size(P);
+  if (!workspace || workspace_bytes < need) return CM_ENOSPC;
+  if (any_overlap({{C, N * ks}, {C_val, val ? N * 4 : 0}, {bounds, ((uint64_t)P + 1) * 8}, {workspace, need}},
+                  {{A, m * ks}, {B, n * ks}, {A_val, val ? m * 4 : 0}, {B_val, val ? n * 4 : 0}}))
+    return CM_EALIAS;
+  const Choice ch = resolve(kOpMerge, key_type, val, N);
+  uint64_t* J = (uint64_t*)workspace;
+  uint64_t* cuts = (uint64_t*)((char*)workspace + round256(((size_t)P + 1) * sizeof(uint64_t)));
+  timing_mark(0, stream);
+  int rc = partition == 0 ? launch_stream_co_ranks(key_type, A, m, B, n, P, J, stream)
+                          : launch_cross_rank_cuts(key_type, A, m, B, n, P / 2, cuts, bounds, J, stream);
+  if (rc == CM_OK && partition == 0) rc = launch_equal_starts(N, P, bounds, stream);
+  if (rc != CM_OK) return rc;
+  timing_mark(1, stream);
+  rc = launch_merge_stream(key_type, val, ch, A, val ? A_val : nullptr, m, B, val ? B_val : nullptr, n, C,
+                           val ? C_val : nullptr, bounds, J, P, stream);
+  timing_mark(2, stream);
+  return rc;
 }
 
 size_t cm_sort_workspace_size(int key_type, int with_payload, uint64_t n) {

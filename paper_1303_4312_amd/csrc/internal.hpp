@@ -90,8 +90,14 @@ uint32_t stream_blocks(int kt, bool val, const Choice& ch, uint64_t N);
 int launch_stream_co_ranks(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t P, uint64_t* J,
                            hipStream_t st);
 int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
-                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* J,
-                        uint32_t P, hipStream_t st);
+                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* I,
+                        const uint64_t* J, uint32_t P, hipStream_t st);
+// The classic cross-rank partition into P = 2h segments: the 2h sample cuts
+// (cuts: 4h uint64 of scratch) in output order into I, J (2h + 1 entries);
+// and the starts of the equal split into P segments (I, P + 1 entries).
+int launch_cross_rank_cuts(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t h, uint64_t* cuts,
+                           uint64_t* I, uint64_t* J, hipStream_t st);
+int launch_equal_starts(uint64_t N, uint32_t P, uint64_t* I, hipStream_t st);
 
 // Segmented batch: offset check, boundary co-ranks (and segments), block merge.
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,

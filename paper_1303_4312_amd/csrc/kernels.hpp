@@ -302,6 +302,62 @@ __global__ __launch_bounds__(256) void k_stream_co_rank(const K* __restrict__ A,
   if ((threadIdx.x & 63) == 0) J[w] = j;
 }
 
+// ---- the classic cross-rank partition (the prior art of Section 1) -----------
+//
+// h equidistant samples of A and h of B; each sample is ranked in the other
+// array by binary search: A[j] has k = #{B < A[j]} elements of B before it
+// (equal keys: A first), B[k] has j = #{A <= B[k]} elements of A before it.
+// Each sample gives an exact cut (j, k) of the output at i = j + k; sample 0
+// of each side is the cut (0, 0), and samples past the end give (m, n).
+// Segments between consecutive cuts hold at most ceil(m / h) elements of A
+// and ceil(n / h) of B, so their lengths can differ by a factor of two.
+template <typename K>
+__global__ __launch_bounds__(256) void k_cross_rank_cuts(const K* __restrict__ A, uint64_t m,
+                                                         const K* __restrict__ B, uint64_t n, uint32_t h,
+                                                         uint64_t* __restrict__ ia, uint64_t* __restrict__ ja,
+                                                         uint64_t* __restrict__ ib, uint64_t* __restrict__ jb) {
+  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= 2ull * h) return;
+  const bool from_a = x < h;
+  const uint64_t r = from_a ? x : x - h;
+  const uint64_t len = from_a ? m : n;
+  const uint64_t step = (len + h - 1) / h;
+  const uint64_t pos = r * step;
+  uint64_t j, k;
+  if (r == 0) {
+    j = 0;
+    k = 0;
+  } else if (pos >= len) {
+    j = m;
+    k = n;
+  } else if (from_a) {
+    const K key = A[pos];
+    uint64_t lo = 0, hi = n;  // first B index with B[y] >= key
+    while (lo < hi) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (B[mid] < key) lo = mid + 1; else hi = mid;
+    }
+    j = pos;
+    k = lo;
+  } else {
+    const K key = B[pos];
+    uint64_t lo = 0, hi = m;  // first A index with A[y] > key
+    while (lo < hi) {
+      const uint64_t mid = lo + (hi - lo) / 2;
+      if (A[mid] <= key) lo = mid + 1; else hi = mid;
+    }
+    j = lo;
+    k = pos;
+  }
+  if (from_a) {
+    ia[r] = j + k;
+    ja[r] = j;
+  } else {
+    ib[r] = j + k;
+    jb[r] = j;
+  }
+}
+
 // Ring of T slots: slot of position x (x < T) after head h (h < T).
 template <int T>
 __device__ __forceinline__ int ring_slot(int h, int x) {
@@ -327,7 +383,8 @@ __global__ __launch_bounds__(NT) void k_merge_stream(const K* __restrict__ A, co
                                                      uint64_t m, const K* __restrict__ B,
                                                      const uint32_t* __restrict__ Bv, uint64_t n,
                                                      K* __restrict__ C, uint32_t* __restrict__ Cv,
-                                                     const uint64_t* __restrict__ J, uint32_t P, int search) {
+                                                     const uint64_t* __restrict__ I, const uint64_t* __restrict__ J,
+                                                     uint32_t P, int search) {
   constexpr int T = NT * E;
   __shared__ K ra_key[T];
   __shared__ K rb_key[T];
@@ -337,8 +394,9 @@ __global__ __launch_bounds__(NT) void k_merge_stream(const K* __restrict__ A, co
   const uint64_t N = m + n;
   const uint64_t w = blockIdx.x;
   if (w >= P) return;
-  uint64_t o = stream_block_start(w, N, P);
-  const uint64_t o_end = stream_block_start(w + 1, N, P);
+  // segment w: equal shares, or the starts I gives (any monotone cuts with J)
+  uint64_t o = I ? I[w] : stream_block_start(w, N, P);
+  const uint64_t o_end = std::max(I ? I[w + 1] : stream_block_start(w + 1, N, P), o);
   uint64_t ja = J[w];
   const uint64_t ja_end = std::max(J[w + 1], ja);  // the max only matters for unsorted input
   uint64_t kb = o - ja;

@@ -52,6 +52,39 @@ __global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u
     __builtin_nontemporal_store(__builtin_nontemporal_load(src + x), dst + x);
 }
 
+// Puts the 2h cuts in output order (A's cut first on equal ranks, which are
+// the same cut) and closes with (m + n, m): I / J get 2h + 1 entries.
+__global__ __launch_bounds__(256) void k_cross_rank_place(const uint64_t* __restrict__ ia,
+                                                          const uint64_t* __restrict__ ja,
+                                                          const uint64_t* __restrict__ ib,
+                                                          const uint64_t* __restrict__ jb, uint32_t h,
+                                                          uint64_t N, uint64_t m, uint64_t* __restrict__ I,
+                                                          uint64_t* __restrict__ J) {
+  const uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x == 0) {
+    I[2ull * h] = N;
+    J[2ull * h] = m;
+  }
+  if (x >= 2ull * h) return;
+  const bool from_a = x < h;
+  const uint64_t r = from_a ? x : x - h;
+  const uint64_t key = from_a ? ia[r] : ib[r];
+  const uint64_t* other = from_a ? ib : ia;
+  uint64_t lo = 0, hi = h;  // cuts of the other side before this one
+  while (lo < hi) {
+    const uint64_t mid = lo + (hi - lo) / 2;
+    if (from_a ? other[mid] < key : other[mid] <= key) lo = mid + 1; else hi = mid;
+  }
+  I[r + lo] = key;
+  J[r + lo] = from_a ? ja[r] : jb[r];
+}
+
+// Segment starts of the equal split (co-rank partition with P segments).
+__global__ __launch_bounds__(256) void k_equal_starts(uint64_t N, uint32_t P, uint64_t* __restrict__ I) {
+  const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w <= P) I[w] = stream_block_start(w, N, P);
+}
+
 int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,
                           uint64_t n, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
@@ -155,21 +188,45 @@ int launch_stream_co_ranks(int kt, const void* A, uint64_t m, const void* B, uin
 }
 
 int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
-                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* J,
-                        uint32_t P, hipStream_t st) {
+                        const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* I,
+                        const uint64_t* J, uint32_t P, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
     using K = decltype(key);
     return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
       constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
       if (val)
         hipLaunchKernelGGL((k_merge_stream<K, true, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
-                           (const K*)B, Bv, n, (K*)C, Cv, J, P, ch.search);
+                           (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
       else
         hipLaunchKernelGGL((k_merge_stream<K, false, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
-                           (const K*)B, Bv, n, (K*)C, Cv, J, P, ch.search);
+                           (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
       return launch_status();
     });
   });
+}
+
+int launch_cross_rank_cuts(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t h, uint64_t* cuts,
+                           uint64_t* I, uint64_t* J, hipStream_t st) {
+  uint64_t* ia = cuts;
+  uint64_t* ja = cuts + h;
+  uint64_t* ib = cuts + 2ull * h;
+  uint64_t* jb = cuts + 3ull * h;
+  const unsigned blocks = (unsigned)((2ull * h + 255) / 256);
+  const int rc = by_key(kt, [&](auto key) -> int {
+    using K = decltype(key);
+    hipLaunchKernelGGL((k_cross_rank_cuts<K>), dim3(blocks), dim3(256), 0, st, (const K*)A, m, (const K*)B, n, h, ia,
+                       ja, ib, jb);
+    return launch_status();
+  });
+  if (rc != CM_OK) return rc;
+  hipLaunchKernelGGL(k_cross_rank_place, dim3(blocks), dim3(256), 0, st, (const uint64_t*)ia, (const uint64_t*)ja,
+                     (const uint64_t*)ib, (const uint64_t*)jb, h, m + n, m, I, J);
+  return launch_status();
+}
+
+int launch_equal_starts(uint64_t N, uint32_t P, uint64_t* I, hipStream_t st) {
+  hipLaunchKernelGGL(k_equal_starts, dim3((unsigned)(((uint64_t)P + 1 + 255) / 256)), dim3(256), 0, st, N, P, I);
+  return launch_status();
 }
 
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,

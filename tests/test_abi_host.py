@@ -322,3 +322,23 @@ def test_one_hip_runtime_whatever_the_import_order(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                          timeout=300, check=True).stdout.split()
     assert out[-1] == "1", f"HIP runtimes mapped: {out[-1]}"
+
+
+def test_partition_ablation_argument_errors():
+    lib = cm.load()
+    P = ctypes.c_void_p
+    ws = lib.cm_partition_ablation_workspace_size(64)
+    assert ws >= 65 * 8 and ws % 256 == 0
+    assert lib.cm_partition_ablation_workspace_size(1) == 0
+    args = dict(A=P(0x1000), Av=None, m=100, B=P(0x2000), Bv=None, n=100, C=P(0x10000), Cv=None)
+
+    def call(P_, part, bounds=P(0x20000), wsb=ws, kt=0):
+        return lib.cm_merge_partition_ablation(kt, args["A"], None, 100, args["B"], None, 100,
+                                               args["C"], None, P_, part, bounds, P(0x30000), wsb,
+                                               None)
+    assert call(63, 0) == EINVAL      # odd P
+    assert call(0, 0) == EINVAL
+    assert call(64, 2) == EINVAL      # unknown partition
+    assert call(64, 0, bounds=None) == EINVAL
+    assert call(64, 0, wsb=ws - 1) == ENOSPC
+    assert call(64, 0, kt=9) == EDTYPE
