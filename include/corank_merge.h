@@ -63,8 +63,20 @@ enum cm_status {
     CM_ECANCELED = -10 /* server: request dropped at shutdown without running */
 };
 
-/* Key types. */
-enum cm_key_type { CM_KEY_U32 = 0, CM_KEY_U64 = 1, CM_KEY_F32 = 2 };
+/*
+ * Key types.  The first three merge and sort in nondecreasing key order; the
+ * _DESC types hold the same bits and use the reversed order (nonincreasing;
+ * ties still go A first in a merge and keep input order in a sort).  Float
+ * keys compare as IEEE values either way (-0.0 == +0.0; no NaN).
+ */
+enum cm_key_type {
+    CM_KEY_U32 = 0,
+    CM_KEY_U64 = 1,
+    CM_KEY_F32 = 2,
+    CM_KEY_U32_DESC = 3,
+    CM_KEY_U64_DESC = 4,
+    CM_KEY_F32_DESC = 5
+};
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *cm_status_string(int status);

@@ -21,6 +21,10 @@ only compiles it, loads it and marshals numpy arrays:
   merge code is involved, so the GPU merge sort is checked against the
   definition rather than against another merge sort.
 
+Every function takes ``descending=True`` for keys ordered nonincreasingly:
+the same method under the reversed total order (Section 2 merges under any
+total order), equal keys still A first.
+
 Key types: numpy uint32, uint64, float32. Payloads: uint32 or None.
 """
 from __future__ import annotations
@@ -36,6 +40,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 _KT = {np.dtype(np.uint32): 0, np.dtype(np.uint64): 1, np.dtype(np.float32): 2}
+_DESC = 3  # key types 3..5: the same keys under the reversed order
 
 _lib = None
 
@@ -96,8 +101,13 @@ def _pay(v, length):
     return v
 
 
-def stable_merge(A, B, Av=None, Bv=None):
-    """Stable merge of sorted A and B; returns C, or (C, Cv) with payloads."""
+def _kt(dtype, descending):
+    return _KT[dtype] + (_DESC if descending else 0)
+
+
+def stable_merge(A, B, Av=None, Bv=None, descending=False):
+    """Stable merge of sorted A and B (both nonincreasing, merged under the
+    reversed order, if descending); returns C, or (C, Cv) with payloads."""
     A = _keys(A)
     B = _keys(B, A.dtype)
     if (Av is None) != (Bv is None):
@@ -105,22 +115,23 @@ def stable_merge(A, B, Av=None, Bv=None):
     Av, Bv = _pay(Av, A.size), _pay(Bv, B.size)
     C = np.empty(A.size + B.size, dtype=A.dtype)
     Cv = None if Av is None else np.empty(A.size + B.size, dtype=np.uint32)
-    _load().oracle_stable_merge(_KT[A.dtype], _ptr(A), _ptr(Av), A.size,
+    _load().oracle_stable_merge(_kt(A.dtype, descending), _ptr(A), _ptr(Av), A.size,
                                 _ptr(B), _ptr(Bv), B.size, _ptr(C), _ptr(Cv))
     return C if Cv is None else (C, Cv)
 
 
-def co_rank_brute(i, A, B):
+def co_rank_brute(i, A, B, descending=False):
     """(j, k) for output rank i, by merging i outputs and counting A's."""
     A = _keys(A)
     B = _keys(B, A.dtype)
     if not 0 <= i <= A.size + B.size:
         raise ValueError("oracle: rank out of range")
-    j = int(_load().oracle_co_rank_brute(_KT[A.dtype], i, _ptr(A), A.size, _ptr(B), B.size))
+    j = int(_load().oracle_co_rank_brute(_kt(A.dtype, descending), i, _ptr(A), A.size, _ptr(B),
+                                         B.size))
     return j, i - j
 
 
-def co_rank_alg1(i, A, B, trace_cap=0):
+def co_rank_alg1(i, A, B, trace_cap=0, descending=False):
     """Algorithm 1. Returns (j, k, iters) or, with trace_cap > 0,
     (j, k, iters, states) where states is a list of (j, k, j_low, k_low)
     tuples (k_low is None before it is first assigned)."""
@@ -133,7 +144,7 @@ def co_rank_alg1(i, A, B, trace_cap=0):
     ns = ctypes.c_uint64()
     it = ctypes.c_uint64()
     tr = np.zeros(4 * max(trace_cap, 1), dtype=np.uint64)
-    rc = _load().oracle_co_rank_alg1(_KT[A.dtype], i, _ptr(A), A.size, _ptr(B), B.size,
+    rc = _load().oracle_co_rank_alg1(_kt(A.dtype, descending), i, _ptr(A), A.size, _ptr(B), B.size,
                                      ctypes.byref(j), ctypes.byref(k),
                                      _ptr(tr) if trace_cap else None, trace_cap,
                                      ctypes.byref(ns), ctypes.byref(it))
@@ -148,7 +159,7 @@ def co_rank_alg1(i, A, B, trace_cap=0):
     return j.value, k.value, it.value, states
 
 
-def stable_merge_segmented(A, a_off, B, b_off, Av=None, Bv=None):
+def stable_merge_segmented(A, a_off, B, b_off, Av=None, Bv=None, descending=False):
     """Merge segment s of A with segment s of B into C at a_off[s]+b_off[s]."""
     A = _keys(A)
     B = _keys(B, A.dtype)
@@ -163,18 +174,26 @@ def stable_merge_segmented(A, a_off, B, b_off, Av=None, Bv=None):
     Av, Bv = _pay(Av, A.size), _pay(Bv, B.size)
     C = np.empty(A.size + B.size, dtype=A.dtype)
     Cv = None if Av is None else np.empty(A.size + B.size, dtype=np.uint32)
-    _load().oracle_stable_merge_segmented(_KT[A.dtype], _ptr(A), _ptr(Av), _ptr(a_off),
+    _load().oracle_stable_merge_segmented(_kt(A.dtype, descending), _ptr(A), _ptr(Av),
+                                          _ptr(a_off),
                                           _ptr(B), _ptr(Bv), _ptr(b_off), a_off.size - 1,
                                           _ptr(C), _ptr(Cv))
     return C if Cv is None else (C, Cv)
 
 
-def stable_sort(keys, vals=None):
-    """Keys sorted nondecreasingly, equal keys keeping their input order
-    (IEEE comparison for float32: -0.0 and +0.0 are equal keys); payloads
-    follow their keys.  Returns keys, or (keys, payloads)."""
+def stable_sort(keys, vals=None, descending=False):
+    """Keys sorted nondecreasingly (nonincreasingly if descending), equal
+    keys keeping their input order (IEEE comparison for float32: -0.0 and
+    +0.0 are equal keys); payloads follow their keys.  Returns keys, or
+    (keys, payloads).  The nonincreasing order is the nondecreasing order of
+    an order-reversing image of the keys (bitwise complement for unsigned
+    keys, negation for floats, which keeps -0.0 and +0.0 equal)."""
     k = _keys(keys)
-    order = np.argsort(k, kind="stable")
+    if descending:
+        image = -k if k.dtype == np.float32 else ~k
+        order = np.argsort(image, kind="stable")
+    else:
+        order = np.argsort(k, kind="stable")
     if vals is None:
         return k[order]
     v = _pay(vals, k.size)

@@ -36,37 +36,51 @@
 #define ORACLE_U32 0
 #define ORACLE_U64 1
 #define ORACLE_F32 2
+/* Types 3, 4, 5: the same keys under the reversed order (nonincreasing).
+ * The method is stated for any total order on keys (Section 2), so these
+ * merge with x <= y read as x >= y and keep the tie rule (A first). */
+#define ORACLE_DESC 3
 
-/* x <= y for element a of A and element b of B under the key order. */
-static int key_le(int kt, const void *A, uint64_t a, const void *B, uint64_t b)
+static int base_type(int kt) { return kt >= ORACLE_DESC ? kt - ORACLE_DESC : kt; }
+
+/* x <= y for element a of A and element b of B in plain numeric order. */
+static int num_le(int t, const void *A, uint64_t a, const void *B, uint64_t b)
 {
-    if (kt == ORACLE_U32)
+    if (t == ORACLE_U32)
         return ((const uint32_t *)A)[a] <= ((const uint32_t *)B)[b];
-    if (kt == ORACLE_U64)
+    if (t == ORACLE_U64)
         return ((const uint64_t *)A)[a] <= ((const uint64_t *)B)[b];
     return ((const float *)A)[a] <= ((const float *)B)[b];
 }
 
-/* A[a] > B[b] and B[b] >= A[a], spelled out as in Algorithm 1's two tests. */
+static int num_lt(int t, const void *A, uint64_t a, const void *B, uint64_t b)
+{
+    if (t == ORACLE_U32)
+        return ((const uint32_t *)A)[a] < ((const uint32_t *)B)[b];
+    if (t == ORACLE_U64)
+        return ((const uint64_t *)A)[a] < ((const uint64_t *)B)[b];
+    return ((const float *)A)[a] < ((const float *)B)[b];
+}
+
+/* A[a] <= B[b] under the key order. */
+static int key_le(int kt, const void *A, uint64_t a, const void *B, uint64_t b)
+{
+    return kt >= ORACLE_DESC ? num_le(base_type(kt), B, b, A, a) : num_le(kt, A, a, B, b);
+}
+
+/* A[a] > B[b] and B[b] >= A[a] under the key order, spelled out as in
+ * Algorithm 1's two tests. */
 static int key_gt(int kt, const void *A, uint64_t a, const void *B, uint64_t b)
 {
-    if (kt == ORACLE_U32)
-        return ((const uint32_t *)A)[a] > ((const uint32_t *)B)[b];
-    if (kt == ORACLE_U64)
-        return ((const uint64_t *)A)[a] > ((const uint64_t *)B)[b];
-    return ((const float *)A)[a] > ((const float *)B)[b];
+    return kt >= ORACLE_DESC ? num_lt(base_type(kt), A, a, B, b) : num_lt(kt, B, b, A, a);
 }
 
 static int key_ge(int kt, const void *A, uint64_t a, const void *B, uint64_t b)
 {
-    if (kt == ORACLE_U32)
-        return ((const uint32_t *)A)[a] >= ((const uint32_t *)B)[b];
-    if (kt == ORACLE_U64)
-        return ((const uint64_t *)A)[a] >= ((const uint64_t *)B)[b];
-    return ((const float *)A)[a] >= ((const float *)B)[b];
+    return kt >= ORACLE_DESC ? num_le(base_type(kt), A, a, B, b) : num_le(kt, B, b, A, a);
 }
 
-static size_t key_size(int kt) { return kt == ORACLE_U64 ? 8 : 4; }
+static size_t key_size(int kt) { return base_type(kt) == ORACLE_U64 ? 8 : 4; }
 
 int oracle_key_size(int kt) { return (int)key_size(kt); }
 

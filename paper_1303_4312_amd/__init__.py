@@ -20,7 +20,7 @@ import ctypes
 import os
 
 __all__ = [
-    "CMError", "library_path", "co_rank_host", "co_rank", "stable_merge",
+    "CMError", "library_path", "co_rank_host", "co_rank", "stable_merge", "KEY_DESC_OFFSET",
     "stable_merge_pairs", "stable_merge_segmented", "merge_workspace_size",
     "segmented_workspace_size", "check_sorted", "config_count", "config_info",
     "set_config", "get_config", "set_search", "KEY_TYPES", "stable_merge_segmented_each",
@@ -37,6 +37,7 @@ library_path = os.path.join(_HERE, "libcorank_merge.so")
 
 # C enum cm_key_type
 KEY_U32, KEY_U64, KEY_F32 = 0, 1, 2
+KEY_DESC_OFFSET = 3  # CM_KEY_*_DESC = CM_KEY_* + 3: the same keys, nonincreasing order
 # operations of the tuning table
 OP_MERGE, OP_SEGMENTED, OP_BATCH, OP_SORT = 0, 1, 2, 3
 KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
@@ -173,12 +174,13 @@ def _torch():
     return torch
 
 
-def _key_type(t) -> int:
+def _key_type(t, descending: bool = False) -> int:
+    """C key type of tensor t: the ascending type, or its _DESC twin."""
     torch = _torch()
     kt = {torch.uint32: KEY_U32, torch.uint64: KEY_U64, torch.float32: KEY_F32}.get(t.dtype)
     if kt is None:
         raise TypeError(f"unsupported key dtype {t.dtype} (uint32, uint64, float32)")
-    return kt
+    return kt + (KEY_DESC_OFFSET if descending else 0)
 
 
 def _dev(t, name, dtype=None):
@@ -225,8 +227,9 @@ def _workspace(nbytes, device, workspace):
     return workspace, workspace.numel() * workspace.element_size()
 
 
-def co_rank_host(i: int, A, B):
-    """Co-ranks (j, k) of rank i for host arrays (numpy or CPU tensors)."""
+def co_rank_host(i: int, A, B, descending=False):
+    """Co-ranks (j, k) of rank i for host arrays (numpy or CPU tensors),
+    sorted nonincreasingly if descending."""
     import numpy as np
     A = np.ascontiguousarray(A)
     B = np.ascontiguousarray(B, dtype=A.dtype)
@@ -234,6 +237,7 @@ def co_rank_host(i: int, A, B):
           np.dtype(np.float32): KEY_F32}.get(A.dtype)
     if kt is None:
         raise TypeError(f"unsupported key dtype {A.dtype}")
+    kt += KEY_DESC_OFFSET if descending else 0
     j, k = ctypes.c_uint64(), ctypes.c_uint64()
     _check(load().cm_co_rank_host(kt, i, A.ctypes.data_as(ctypes.c_void_p), A.size,
                                   B.ctypes.data_as(ctypes.c_void_p), B.size,
@@ -241,10 +245,11 @@ def co_rank_host(i: int, A, B):
     return j.value, k.value
 
 
-def co_rank(ranks, A, B, j_out=None, stream=None):
+def co_rank(ranks, A, B, j_out=None, stream=None, descending=False):
     """A co-ranks of device rank tensor `ranks` (uint64) over device arrays A
-    and B; returns j (uint64 tensor; k = ranks - j).  A plain int rank
-    returns the pair (j, k) and synchronises."""
+    and B (sorted nonincreasingly if descending); returns j (uint64 tensor;
+    k = ranks - j).  A plain int rank returns the pair (j, k) and
+    synchronises."""
     torch = _torch()
     A = _dev(A, "A")
     B = _dev(B, "B", A.dtype)
@@ -254,7 +259,8 @@ def co_rank(ranks, A, B, j_out=None, stream=None):
     ranks = _dev(ranks, "ranks", torch.uint64)
     if j_out is None:
         j_out = torch.empty_like(ranks)
-    _check(load().cm_co_rank(_key_type(A), _ptr(ranks), ranks.numel(), _ptr(A), A.numel(),
+    _check(load().cm_co_rank(_key_type(A, descending), _ptr(ranks), ranks.numel(), _ptr(A),
+                             A.numel(),
                              _ptr(B), B.numel(), _ptr(j_out), _stream(stream, A.device)),
            "cm_co_rank")
     if scalar:
@@ -265,8 +271,9 @@ def co_rank(ranks, A, B, j_out=None, stream=None):
     return j_out
 
 
-def stable_merge(A, B, C=None, workspace=None, stream=None):
-    """Stable merge of sorted device key arrays A and B; returns C."""
+def stable_merge(A, B, C=None, workspace=None, stream=None, descending=False):
+    """Stable merge of sorted device key arrays A and B (both nonincreasing
+    if descending); returns C."""
     torch = _torch()
     A = _dev(A, "A")
     B = _dev(B, "B", A.dtype)
@@ -276,14 +283,15 @@ def stable_merge(A, B, C=None, workspace=None, stream=None):
     C = _dev(C, "C", A.dtype)
     if C.numel() != m + n:
         raise ValueError("C must hold m + n keys")
-    kt = _key_type(A)
+    kt = _key_type(A, descending)
     ws, wsb = _workspace(load().cm_merge_workspace_size(kt, 0, m, n), A.device, workspace)
     _check(load().cm_stable_merge(kt, _ptr(A), m, _ptr(B), n, _ptr(C), _ptr(ws), wsb,
                                   _stream(stream, A.device)), "cm_stable_merge")
     return C
 
 
-def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, stream=None):
+def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, stream=None,
+                       descending=False):
     """Stable merge of (key, uint32 payload) pairs; returns (C, C_val)."""
     torch = _torch()
     A = _dev(A, "A")
@@ -301,7 +309,7 @@ def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, s
     C_val = _dev(C_val, "C_val", torch.uint32)
     if C.numel() != m + n or C_val.numel() != m + n:
         raise ValueError("C and C_val must hold m + n elements")
-    kt = _key_type(A)
+    kt = _key_type(A, descending)
     ws, wsb = _workspace(load().cm_merge_workspace_size(kt, 1, m, n), A.device, workspace)
     _check(load().cm_stable_merge_pairs(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n,
                                         _ptr(C), _ptr(C_val), _ptr(ws), wsb,
@@ -310,7 +318,7 @@ def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, s
 
 
 def stable_merge_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=None,
-                           workspace=None, stream=None):
+                           workspace=None, stream=None, descending=False):
     """Merge segment s of A (A[a_off[s]:a_off[s+1]]) with segment s of B into
     C at a_off[s] + b_off[s].  a_off, b_off: uint64 device tensors of
     num_seg + 1 entries.  Returns C or (C, C_val)."""
@@ -334,7 +342,7 @@ def stable_merge_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C
         if C_val is None:
             C_val = torch.empty(ta + tb, dtype=torch.uint32, device=A.device)
         C_val = _dev(C_val, "C_val", torch.uint32)
-    kt = _key_type(A)
+    kt = _key_type(A, descending)
     S = a_off.numel() - 1
     ws, wsb = _workspace(load().cm_segmented_workspace_size(kt, int(with_val), ta, tb, S),
                          A.device, workspace)
@@ -418,13 +426,14 @@ def sort_workspace_size(key_dtype, with_payload: bool, n: int) -> int:
     return load().cm_sort_workspace_size(kt, int(bool(with_payload)), n)
 
 
-def stable_sort(keys, vals=None, out=None, out_vals=None, workspace=None, stream=None):
+def stable_sort(keys, vals=None, out=None, out_vals=None, workspace=None, stream=None,
+                descending=False):
     """Stable merge sort of a device key array (with uint32 payloads if vals
     is given).  out / out_vals may be the inputs themselves (in place).
     Returns the sorted keys, or (keys, payloads)."""
     torch = _torch()
     keys = _dev(keys, "keys")
-    kt = _key_type(keys)
+    kt = _key_type(keys, descending)
     n = keys.numel()
     with_val = vals is not None
     if with_val:
@@ -468,12 +477,13 @@ def merge_partition_ablation(A, B, A_val=None, B_val=None, P=2048, partition=0, 
     return ((C, C_val) if with_val else (C,)) + (bounds,)
 
 
-def check_sorted(X, stream=None) -> bool:
-    """True if the device key array X is nondecreasing (synchronises)."""
+def check_sorted(X, stream=None, descending=False) -> bool:
+    """True if the device key array X is nondecreasing (nonincreasing if
+    descending); synchronises."""
     torch = _torch()
     X = _dev(X, "X")
     flag = torch.empty(1, dtype=torch.uint32, device=X.device)
-    _check(load().cm_check_sorted(_key_type(X), _ptr(X), X.numel(), _ptr(flag),
+    _check(load().cm_check_sorted(_key_type(X, descending), _ptr(X), X.numel(), _ptr(flag),
                                   _stream(stream, X.device)), "cm_check_sorted")
     return int(flag.cpu()[0]) == 0
 

@@ -6,6 +6,7 @@ binding loads; nothing is installed elsewhere.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import subprocess
 import sys
@@ -36,7 +37,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     out_dir = os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)
-    objs = []
+    cmds, objs = [], []
     for src in HIP_SOURCES + CXX_SOURCES:
         obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
@@ -44,10 +45,17 @@ def build(verbose: bool = False) -> str:
         if src.endswith(".cpp"):
             cmd = [hipcc(), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE,
                    "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    # the translation units are independent: compile them side by side
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with concurrent.futures.ThreadPoolExecutor(jobs) as pool:
+        for cmd, res in zip(cmds, pool.map(lambda c: subprocess.run(c), cmds)):
+            if res.returncode != 0:
+                raise subprocess.CalledProcessError(res.returncode, cmd)
     tmp = LIB_PATH + ".tmp"
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:

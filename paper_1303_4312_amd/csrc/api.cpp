@@ -24,7 +24,7 @@ namespace {
 // process-wide settings
 
 struct Settings {
-  int cfg[3][2] = {{0, 0}, {0, 0}, {0, 0}};  // [key type][payload] default configuration
+  int cfg[CM_KEY_F32_DESC + 1][2] = {};       // [key type][payload] default configuration (0)
   int search = 1;                             // bisection
   int partition = -1;                         // automatic (see resolve)
   Shape shape;                                // coarse stride, block order
@@ -76,8 +76,8 @@ void timing_mark(int slot, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // checks
 
-bool key_type_ok(int kt) { return kt == CM_KEY_U32 || kt == CM_KEY_U64 || kt == CM_KEY_F32; }
-size_t key_bytes(int kt) { return kt == CM_KEY_U64 ? 8 : 4; }
+bool key_type_ok(int kt) { return kt >= CM_KEY_U32 && kt <= CM_KEY_F32_DESC; }
+size_t key_bytes(int kt) { return kt == CM_KEY_U64 || kt == CM_KEY_U64_DESC ? 8 : 4; }
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 bool overlap(const void* p, uint64_t pbytes, const void* q, uint64_t qbytes) {

@@ -8,6 +8,7 @@
 #include <type_traits>
 
 #include "corank_merge.h"
+#include "order.hpp"
 
 namespace cm {
 
@@ -18,7 +19,11 @@ int by_key(int kt, F&& f) {
   switch (kt) {
     case CM_KEY_U32: return f(uint32_t{});
     case CM_KEY_U64: return f(uint64_t{});
-    default: return f(float{});
+    case CM_KEY_F32: return f(float{});
+    case CM_KEY_U32_DESC: return f(Desc<uint32_t>{});
+    case CM_KEY_U64_DESC: return f(Desc<uint64_t>{});
+    case CM_KEY_F32_DESC: return f(Desc<float>{});
+    default: return CM_EDTYPE;
   }
 }
 

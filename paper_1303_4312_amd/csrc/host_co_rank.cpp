@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "corank_merge.h"
+#include "order.hpp"
 
 namespace {
 
@@ -35,7 +36,7 @@ uint64_t co_rank_alg1(uint64_t i, const K* A, uint64_t m, const K* B, uint64_t n
 
 extern "C" int cm_co_rank_host(int key_type, uint64_t i, const void* A, uint64_t m, const void* B, uint64_t n,
                                uint64_t* j, uint64_t* k) {
-  if (key_type != CM_KEY_U32 && key_type != CM_KEY_U64 && key_type != CM_KEY_F32) return CM_EDTYPE;
+  if (key_type < CM_KEY_U32 || key_type > CM_KEY_F32_DESC) return CM_EDTYPE;
   if (!j || !k || (m && !A) || (n && !B) || m + n < m) return CM_EINVAL;
   if (i > m + n) return CM_ERANGE;
   uint64_t jj;
@@ -46,8 +47,19 @@ extern "C" int cm_co_rank_host(int key_type, uint64_t i, const void* A, uint64_t
     case CM_KEY_U64:
       jj = co_rank_alg1(i, static_cast<const uint64_t*>(A), m, static_cast<const uint64_t*>(B), n);
       break;
-    default:
+    case CM_KEY_F32:
       jj = co_rank_alg1(i, static_cast<const float*>(A), m, static_cast<const float*>(B), n);
+      break;
+    case CM_KEY_U32_DESC:
+      jj = co_rank_alg1(i, static_cast<const cm::Desc<uint32_t>*>(A), m, static_cast<const cm::Desc<uint32_t>*>(B),
+                        n);
+      break;
+    case CM_KEY_U64_DESC:
+      jj = co_rank_alg1(i, static_cast<const cm::Desc<uint64_t>*>(A), m, static_cast<const cm::Desc<uint64_t>*>(B),
+                        n);
+      break;
+    default:
+      jj = co_rank_alg1(i, static_cast<const cm::Desc<float>*>(A), m, static_cast<const cm::Desc<float>*>(B), n);
       break;
   }
   *j = jj;

@@ -508,10 +508,10 @@ __global__ __launch_bounds__(NT) void k_merge_stream(const K* __restrict__ A, co
       if (x < len) {
         const int sl = x < a_take ? ring_slot<T>(ha, x) : ring_slot<T>(hb, x - a_take);
         const K key = x < a_take ? ra_key[sl] : rb_key[sl];
-        __builtin_nontemporal_store(key, C + o + x);
+        store_nt(key, C + o + x);
         if constexpr (VAL) {
           const uint32_t v = x < a_take ? ra_val[sl] : rb_val[sl];
-          __builtin_nontemporal_store(v, Cv + o + x);
+          store_nt(v, Cv + o + x);
         }
       }
     }

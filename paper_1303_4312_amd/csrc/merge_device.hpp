@@ -12,7 +12,18 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "order.hpp"
+
 namespace cm {
+
+// Non-temporal store of one key or payload (a Desc key stores its bits).
+template <typename X>
+__device__ __forceinline__ void store_nt(X v, X* p) {
+  if constexpr (is_desc<X>::value)
+    __builtin_nontemporal_store(v.v, &p->v);
+  else
+    __builtin_nontemporal_store(v, p);
+}
 
 enum SearchMode : int { kSearchAlg1 = 0, kSearchBisect = 1 };
 
@@ -212,8 +223,8 @@ __device__ __forceinline__ void store_block(K* __restrict__ C, uint32_t* __restr
   for (int r = 0; r < E; ++r) {
     const int x = (int)threadIdx.x + r * NT;
     if (x < len) {
-      __builtin_nontemporal_store(s_key[x], C + i0 + x);
-      if constexpr (VAL) __builtin_nontemporal_store(s_val[x], Cv + i0 + x);
+      store_nt(s_key[x], C + i0 + x);
+      if constexpr (VAL) store_nt(s_val[x], Cv + i0 + x);
     }
   }
 }
@@ -299,7 +310,7 @@ __device__ __forceinline__ void store_span_vec(X* __restrict__ G, uint64_t i0, i
   for (int q = (int)threadIdx.x; q < nv; q += NT)
     __builtin_nontemporal_store(*(const vec16*)(src + q * V), (vec16*)(G + i0 + (uint64_t)q * V));
   const int x = nv * V + (int)threadIdx.x;
-  if (x < len) __builtin_nontemporal_store(src[x], G + i0 + x);
+  if (x < len) store_nt(src[x], G + i0 + x);
 }
 
 }  // namespace cm

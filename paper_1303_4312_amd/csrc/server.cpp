@@ -292,14 +292,14 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
                      uint32_t max_inflight, uint32_t max_requests, cm_server** server) {
   if (!server) return CM_EINVAL;
   *server = nullptr;
-  if (key_type != CM_KEY_U32 && key_type != CM_KEY_U64 && key_type != CM_KEY_F32) return CM_EDTYPE;
+  if (key_type < CM_KEY_U32 || key_type > CM_KEY_F32_DESC) return CM_EDTYPE;
   if (!arena || arena_bytes < 256 || max_batch < 1 || max_batch > 65536 || max_inflight < 1 || max_inflight > 16 ||
       max_requests < 1 || max_requests > 65535)
     return CM_EINVAL;
   cm_server* s = new cm_server();
   s->kt = key_type;
   s->val = with_payload != 0;
-  s->ks = key_type == CM_KEY_U64 ? 8 : 4;
+  s->ks = key_type == CM_KEY_U64 || key_type == CM_KEY_U64_DESC ? 8 : 4;
   s->arena = (char*)arena;
   s->max_batch = max_batch;
   s->max_inflight = max_inflight;

@@ -28,16 +28,6 @@
 
 namespace cm {
 
-// Largest key: pads a short last run (pads sort after every real key, and
-// after equal real keys because they come later).
-template <typename K>
-__device__ __forceinline__ K key_max() {
-  if constexpr (std::is_same<K, float>::value)
-    return __builtin_huge_valf();
-  else
-    return ~K(0);
-}
-
 template <typename K, bool VAL, int NT, int E>
 __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, const uint32_t* __restrict__ Xv,
                                                     uint64_t N, K* __restrict__ Y, uint32_t* __restrict__ Yv,
@@ -52,7 +42,9 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
     for (int x = (int)threadIdx.x; x < T; x += NT) {
-      s_k[0][x] = x < len ? X[i0 + x] : key_max<K>();
+      // pads: the last key of the order, after every real key (and after
+      // equal real keys, being later)
+      s_k[0][x] = x < len ? X[i0 + x] : key_last<K>();
       if constexpr (VAL)
         if (x < len) s_v[x] = Xv[i0 + x];
     }
@@ -113,8 +105,8 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
     }
 
     for (int x = (int)threadIdx.x; x < len; x += NT) {
-      __builtin_nontemporal_store(s_k[src][x], Y + i0 + x);
-      if constexpr (VAL) __builtin_nontemporal_store(s_v[s_i[src][x]], Yv + i0 + x);
+      store_nt(s_k[src][x], Y + i0 + x);
+      if constexpr (VAL) store_nt(s_v[s_i[src][x]], Yv + i0 + x);
     }
     if (t + gridDim.x < num_tiles) __syncthreads();
   }

@@ -380,9 +380,10 @@ class NativeServer:
     Python does argument marshalling only."""
 
     def __init__(self, key_dtype="uint32", with_payload=True, arena_bytes=32 << 30,
-                 max_batch=64, max_inflight=2, max_requests=4096, device="cuda:0", arena=None):
+                 max_batch=64, max_inflight=2, max_requests=4096, device="cuda:0", arena=None,
+                 descending=False):
         import torch
-        from . import KEY_TYPES, load
+        from . import KEY_DESC_OFFSET, KEY_TYPES, load
         self.torch = torch
         self.device = torch.device(device)
         self.key_dtype = getattr(torch, str(key_dtype).replace("torch.", ""))
@@ -395,7 +396,8 @@ class NativeServer:
         self.lib = load()
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            rc = self.lib.cm_server_create(KEY_TYPES[str(self.key_dtype).replace("torch.", "")],
+            kt = KEY_TYPES[str(self.key_dtype).replace("torch.", "")]
+            rc = self.lib.cm_server_create(kt + (KEY_DESC_OFFSET if descending else 0),
                                            int(self.with_payload), self.arena.data_ptr(),
                                            self.arena.numel(), max_batch, max_inflight,
                                            max_requests, ctypes.byref(h))

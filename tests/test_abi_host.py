@@ -342,3 +342,32 @@ def test_partition_ablation_argument_errors():
     assert call(64, 0, bounds=None) == EINVAL
     assert call(64, 0, wsb=ws - 1) == ENOSPC
     assert call(64, 0, kt=9) == EDTYPE
+
+
+@pytest.mark.parametrize("dtype", [np.uint32, np.uint64, np.float32])
+def test_host_co_rank_descending(dtype):
+    rng = np.random.default_rng(8)
+    for m, n in ((0, 0), (3, 0), (0, 4), (57, 91), (1000, 10)):
+        A = np.sort(rng.integers(0, 12, m).astype(dtype))[::-1].copy()
+        B = np.sort(rng.integers(0, 12, n).astype(dtype))[::-1].copy()
+        for i in range(0, m + n + 1, max(1, (m + n) // 13)):
+            assert cm.co_rank_host(i, A, B, descending=True) == \
+                oracle.co_rank_brute(i, A, B, descending=True)
+
+
+def test_descending_key_types_accepted():
+    lib = cm.load()
+    for kt in range(6):
+        assert lib.cm_merge_workspace_size(kt, 1, 1000, 1000) > 0
+        assert lib.cm_sort_workspace_size(kt, 1, 1000) > 0
+    assert lib.cm_merge_workspace_size(6, 1, 1000, 1000) == 0
+    # every key type has its own default tile configuration
+    try:
+        for kt in range(6):
+            assert lib.cm_set_config(kt, 1, kt + 1) == 0
+        for kt in range(6):
+            assert lib.cm_get_config(kt, 1) == kt + 1
+        assert lib.cm_set_config(6, 1, 0) == EDTYPE
+    finally:
+        for kt in range(6):
+            lib.cm_set_config(kt, 1, 0)
