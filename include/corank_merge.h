@@ -427,6 +427,27 @@ int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_me
                    float *call_start_ms, float *call_ms, float *merge_ms);
 
 /*
+ * Payloads of any width.  The merge moves one uint32 per key; wider payloads
+ * (uint64, structs) travel as origin codes instead: merge the keys with
+ * A_codes / B_codes as payloads, then move W-byte records by the merged
+ * codes.  Element x of A has code x, element y of B code 2^31 + y (m, n <
+ * 2^31), so the codes in C_val name each output's source.
+ * cm_origin_codes(m, n, A_codes, B_codes, stream): fills A_codes[x] = x and
+ *   B_codes[y] = 2^31 + y (device arrays of m and n uint32).
+ * cm_gather_records(codes, N, A_rec, m, B_rec, n, width, out, stream):
+ *   out[i] = the width-byte record A_rec[codes[i]] or B_rec[codes[i] - 2^31]
+ *   for i < N (device arrays; records contiguous).  Moves 16-, 8- or 4-byte
+ *   words when width and every base allow.  A code past its array leaves
+ *   out[i] untouched.  CM_EINVAL (width 0, null pointer with a nonzero
+ *   size, m or n >= 2^31), CM_EALIAS (out overlaps an input), CM_EHIP.
+ */
+int cm_origin_codes(uint64_t m, uint64_t n, uint32_t *A_codes, uint32_t *B_codes,
+                    hipStream_t stream);
+int cm_gather_records(const uint32_t *codes, uint64_t N, const void *A_rec, uint64_t m,
+                      const void *B_rec, uint64_t n, uint64_t width, void *out,
+                      hipStream_t stream);
+
+/*
  * Partition ablation (the prior art the paper improves on, Section 1).  The
  * merge with P processing elements, each a workgroup merging one contiguous
  * output segment through LDS ring buffers (the streaming kernel of

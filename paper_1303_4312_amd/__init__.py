@@ -28,7 +28,8 @@ __all__ = [
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
     "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
-    "stable_sort", "sort_workspace_size", "merge_partition_ablation",
+    "stable_sort", "sort_workspace_size", "merge_partition_ablation", "origin_codes",
+    "gather_records", "merge_records",
     "launch_batch", "set_coarse_stride", "set_block_order",
 ]
 
@@ -57,6 +58,7 @@ EXPORTS = [
     "cm_server_create", "cm_server_submit", "cm_server_poll", "cm_server_release",
     "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_stable_sort",
     "cm_stable_sort_pairs", "cm_partition_ablation_workspace_size", "cm_merge_partition_ablation",
+    "cm_origin_codes", "cm_gather_records",
 ]
 
 _lib = None
@@ -146,6 +148,8 @@ def load():
         "cm_stable_sort": (c_int, [c_int, vp, c_u64, vp, vp, c_size, vp]),
         "cm_stable_sort_pairs": (c_int, [c_int, vp, vp, c_u64, vp, vp, vp, c_size, vp]),
         "cm_partition_ablation_workspace_size": (c_size, [ctypes.c_uint32]),
+        "cm_origin_codes": (c_int, [c_u64, c_u64, vp, vp, vp]),
+        "cm_gather_records": (c_int, [vp, c_u64, vp, c_u64, vp, c_u64, c_u64, vp, vp]),
         "cm_merge_partition_ablation": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp,
                                                 ctypes.c_uint32, c_int, vp, vp, c_size, vp]),
         "cm_timing_stop": (c_int, [ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_double),
@@ -475,6 +479,54 @@ def merge_partition_ablation(A, B, A_val=None, B_val=None, P=2048, partition=0, 
                                               _ptr(ws), wsb, _stream(stream, A.device)),
            "cm_merge_partition_ablation")
     return ((C, C_val) if with_val else (C,)) + (bounds,)
+
+
+def origin_codes(m: int, n: int, device="cuda:0", stream=None):
+    """(A_codes, B_codes): A_codes[x] = x, B_codes[y] = 2^31 + y (uint32)."""
+    torch = _torch()
+    a = torch.empty(m, dtype=torch.uint32, device=device)
+    b = torch.empty(n, dtype=torch.uint32, device=device)
+    _check(load().cm_origin_codes(m, n, _ptr(a), _ptr(b), _stream(stream, a.device)),
+           "cm_origin_codes")
+    return a, b
+
+
+def _record_width(t):
+    width = t.element_size()
+    for d in t.shape[1:]:
+        width *= d
+    return width
+
+
+def gather_records(codes, A_rec, B_rec, out=None, stream=None):
+    """out[i] = A_rec[codes[i]] or B_rec[codes[i] - 2^31]: records are the
+    rows of A_rec / B_rec (same dtype and row shape, contiguous)."""
+    torch = _torch()
+    codes = _dev(codes, "codes", torch.uint32)
+    if A_rec.dtype != B_rec.dtype or A_rec.shape[1:] != B_rec.shape[1:]:
+        raise ValueError("A_rec and B_rec need the same dtype and row shape")
+    for t, name in ((A_rec, "A_rec"), (B_rec, "B_rec")):
+        if t.device.type != "cuda" or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous GPU tensor")
+    N = codes.numel()
+    if out is None:
+        out = torch.empty((N,) + tuple(A_rec.shape[1:]), dtype=A_rec.dtype, device=codes.device)
+    width = _record_width(A_rec)
+    _check(load().cm_gather_records(_ptr(codes), N, _ptr(A_rec), A_rec.shape[0], _ptr(B_rec),
+                                    B_rec.shape[0], width, _ptr(out),
+                                    _stream(stream, codes.device)), "cm_gather_records")
+    return out
+
+
+def merge_records(A, B, A_rec, B_rec, descending=False, stream=None):
+    """Stable merge of key arrays A and B whose payloads are records of any
+    width (rows of A_rec / B_rec): the keys are merged with origin codes as
+    payloads, then the records are gathered by code.  Returns (C, C_rec)."""
+    if A_rec.shape[0] != A.numel() or B_rec.shape[0] != B.numel():
+        raise ValueError("one record per key")
+    a_codes, b_codes = origin_codes(A.numel(), B.numel(), A.device, stream)
+    C, codes = stable_merge_pairs(A, a_codes, B, b_codes, stream=stream, descending=descending)
+    return C, gather_records(codes, A_rec, B_rec, stream=stream)
 
 
 def check_sorted(X, stream=None, descending=False) -> bool:

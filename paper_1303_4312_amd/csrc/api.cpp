@@ -847,6 +847,23 @@ int cm_copy(const void* src, void* dst, uint64_t bytes, hipStream_t stream) {
   return launch_copy16(src, dst, bytes / 16, stream);
 }
 
+int cm_origin_codes(uint64_t m, uint64_t n, uint32_t* A_codes, uint32_t* B_codes, hipStream_t stream) {
+  if ((m && !A_codes) || (n && !B_codes) || m >= (1ull << 31) || n >= (1ull << 31)) return CM_EINVAL;
+  if (any_overlap({{A_codes, m * 4}, {B_codes, n * 4}}, {})) return CM_EALIAS;
+  if (m + n == 0) return CM_OK;
+  return launch_origin_codes(m, n, A_codes, B_codes, stream);
+}
+
+int cm_gather_records(const uint32_t* codes, uint64_t N, const void* A_rec, uint64_t m, const void* B_rec,
+                      uint64_t n, uint64_t width, void* out, hipStream_t stream) {
+  if (width == 0 || (N && (!codes || !out)) || (m && !A_rec) || (n && !B_rec) || m >= (1ull << 31) ||
+      n >= (1ull << 31) || (N && width > UINT64_MAX / N))
+    return CM_EINVAL;
+  if (any_overlap({{out, N * width}}, {{codes, N * 4}, {A_rec, m * width}, {B_rec, n * width}})) return CM_EALIAS;
+  if (N == 0) return CM_OK;
+  return launch_gather_records(codes, N, A_rec, m, B_rec, n, width, out, stream);
+}
+
 size_t cm_partition_ablation_workspace_size(uint32_t P) {
   if (P < 2) return 0;
   return round256(((size_t)P + 1) * sizeof(uint64_t)) + round256(2 * (size_t)P * sizeof(uint64_t));

@@ -98,6 +98,11 @@ int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const
 int launch_cross_rank_cuts(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t h, uint64_t* cuts,
                            uint64_t* I, uint64_t* J, hipStream_t st);
 int launch_equal_starts(uint64_t N, uint32_t P, uint64_t* I, hipStream_t st);
+// Payloads of any width: origin codes of A and B, and the gather of W-byte
+// records by code.
+int launch_origin_codes(uint64_t m, uint64_t n, uint32_t* A_codes, uint32_t* B_codes, hipStream_t st);
+int launch_gather_records(const uint32_t* codes, uint64_t N, const void* A_rec, uint64_t m, const void* B_rec,
+                          uint64_t n, uint64_t width, void* out, hipStream_t st);
 
 // Segmented batch: offset check, boundary co-ranks (and segments), block merge.
 int launch_seg_validate(const uint64_t* a_off, const uint64_t* b_off, uint64_t S, uint64_t total_a,

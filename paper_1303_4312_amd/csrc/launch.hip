@@ -85,6 +85,72 @@ __global__ __launch_bounds__(256) void k_equal_starts(uint64_t N, uint32_t P, ui
   if (w <= P) I[w] = stream_block_start(w, N, P);
 }
 
+// ---- payloads of any width (records moved by origin code) -----------------
+
+// A_codes[x] = x, B_codes[y] = 2^31 + y (the origin of each element).
+__global__ __launch_bounds__(256) void k_origin_codes(uint64_t m, uint64_t n, uint32_t* __restrict__ A_codes,
+                                                      uint32_t* __restrict__ B_codes) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t x = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; x < m + n; x += stride) {
+    if (x < m)
+      A_codes[x] = (uint32_t)x;
+    else
+      B_codes[x - m] = 0x80000000u | (uint32_t)(x - m);
+  }
+}
+
+// out[i] = record codes[i] of A (code < 2^31) or of B (code - 2^31), each
+// record W bytes, moved in words of U bytes (U divides W and every base is
+// U-aligned).  Codes outside A and B leave the record untouched.
+template <typename U>
+__global__ __launch_bounds__(256) void k_gather_records(const uint32_t* __restrict__ codes, uint64_t N,
+                                                        const U* __restrict__ A_rec, uint64_t m,
+                                                        const U* __restrict__ B_rec, uint64_t n, uint64_t words,
+                                                        U* __restrict__ out) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < N * words; t += stride) {
+    const uint64_t i = t / words, w = t - i * words;
+    const uint32_t c = codes[i];
+    const U* src = nullptr;
+    if (c < 0x80000000u) {
+      if (c < m) src = A_rec + (uint64_t)c * words;
+    } else if ((uint64_t)(c & 0x7fffffffu) < n) {
+      src = B_rec + (uint64_t)(c & 0x7fffffffu) * words;
+    }
+    if (src) out[i * words + w] = src[w];
+  }
+}
+
+int launch_origin_codes(uint64_t m, uint64_t n, uint32_t* A_codes, uint32_t* B_codes, hipStream_t st) {
+  const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((m + n + 255) / 256, 8192));
+  hipLaunchKernelGGL(k_origin_codes, dim3((unsigned)blocks), dim3(256), 0, st, m, n, A_codes, B_codes);
+  return launch_status();
+}
+
+int launch_gather_records(const uint32_t* codes, uint64_t N, const void* A_rec, uint64_t m, const void* B_rec,
+                          uint64_t n, uint64_t width, void* out, hipStream_t st) {
+  auto aligned = [&](uintptr_t u) {
+    return width % u == 0 && ((uintptr_t)A_rec % u) == 0 && ((uintptr_t)B_rec % u) == 0 &&
+           ((uintptr_t)out % u) == 0;
+  };
+  auto go = [&](auto word) {
+    using U = decltype(word);
+    const uint64_t words = width / sizeof(U);
+    const uint64_t blocks = std::max<uint64_t>(1, std::min<uint64_t>((N * words + 255) / 256, 16384));
+    hipLaunchKernelGGL((k_gather_records<U>), dim3((unsigned)blocks), dim3(256), 0, st, codes, N, (const U*)A_rec,
+                       m, (const U*)B_rec, n, words, (U*)out);
+  };
+  if (aligned(16))
+    go(u32x4{});
+  else if (aligned(8))
+    go(uint64_t{});
+  else if (aligned(4))
+    go(uint32_t{});
+  else
+    go(uint8_t{});
+  return launch_status();
+}
+
 int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,
                           uint64_t n, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {

@@ -371,3 +371,19 @@ def test_descending_key_types_accepted():
     finally:
         for kt in range(6):
             lib.cm_set_config(kt, 1, 0)
+
+
+def test_records_argument_errors():
+    lib = cm.load()
+    P = ctypes.c_void_p
+    assert lib.cm_origin_codes(5, 0, None, None, None) == EINVAL
+    assert lib.cm_origin_codes(1 << 31, 0, P(0x1000), None, None) == EINVAL
+    assert lib.cm_origin_codes(0, 0, None, None, None) == OK
+    assert lib.cm_origin_codes(100, 100, P(0x1000), P(0x1100), None) == EALIAS
+    assert lib.cm_gather_records(P(0x1000), 10, P(0x2000), 5, P(0x3000), 5, 0, P(0x4000),
+                                 None) == EINVAL
+    assert lib.cm_gather_records(P(0x1000), 10, None, 5, P(0x3000), 5, 8, P(0x4000),
+                                 None) == EINVAL
+    assert lib.cm_gather_records(P(0x1000), 10, P(0x2000), 5, P(0x3000), 5, 8, P(0x2000),
+                                 None) == EALIAS
+    assert lib.cm_gather_records(None, 0, None, 0, None, 0, 8, None, None) == OK
