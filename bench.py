@@ -34,8 +34,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "merged keys/s & % of HBM peak; batched vs per-merge launches, bit-exact"
+# sources of the merge kernels whose HBM counters are stored under profiles/
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_4312_amd", "csrc", f)
-                  for f in ("kernels.hpp", "merge_device.hpp", "launch.hip")]
+                  for f in ("kernels.hpp", "merge_device.hpp", "order.hpp", "dispatch.hpp",
+                            "launch_impl.hpp", "launch.hip")]
 COUNTERS_FILES = {
     "zipf": os.path.join(ROOT, "profiles", "k_merge_blocks_zipf_u32_pairs_counters.md"),
     "segmented": os.path.join(ROOT, "profiles", "k_seg_merge_blocks_segmented_u32_pairs_counters.md"),
@@ -288,6 +290,53 @@ def partition_ablation_leg(A, Av, B, Bv, C, Cv, P=2048, reps=5):
     out["cross_rank_over_co_rank"] = (out["cross_rank"]["merge_kernel_ms"] /
                                       out["co_rank"]["merge_kernel_ms"])
     return out
+
+
+def generic_order_leg(A, Av, B, Bv, reps=10):
+    """The merge under the reversed key order (the step's arrays reversed,
+    CM_KEY_*_DESC) against the same merge ascending, and the merge of the
+    same keys carrying 8-byte records (origin codes merged, records gathered
+    by code).  Median whole-call times from the library's events; the record
+    merge is timed end to end with torch events (two calls)."""
+    import torch
+    import paper_1303_4312_amd as cm
+    N = A.numel() + B.numel()
+    Ad, Bd, Avd, Bvd = A.flip(0), B.flip(0), Av.flip(0), Bv.flip(0)
+    C = torch.empty(N, dtype=A.dtype, device=A.device)
+    Cv = torch.empty(N, dtype=torch.uint32, device=A.device)
+
+    def calls(fn):
+        fn()
+        torch.cuda.synchronize()
+        cm.timing_start(reps)
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        _, _, _, _, call_each, merge_each = cm.timing_stop(per_call=True)
+        return statistics.median(call_each), statistics.median(merge_each)
+
+    asc = calls(lambda: cm.stable_merge_pairs(A, Av, B, Bv, C, Cv))
+    desc = calls(lambda: cm.stable_merge_pairs(Ad, Avd, Bd, Bvd, C, Cv, descending=True))
+    Arec = torch.arange(A.numel(), dtype=torch.int64, device=A.device)
+    Brec = -torch.arange(B.numel(), dtype=torch.int64, device=A.device) - 1
+    cm.merge_records(A, B, Arec, Brec)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        cm.merge_records(A, B, Arec, Brec)
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    rec_ms = statistics.median(ts)
+    return {
+        "ascending_call_ms": asc[0], "ascending_merge_kernel_ms": asc[1],
+        "descending_call_ms": desc[0], "descending_merge_kernel_ms": desc[1],
+        "records_8byte_ms": rec_ms,
+        "records_8byte_keys_per_s": N / (rec_ms * 1e-3),
+        "records_note": "codes filled, keys merged with codes, 8-byte records gathered by code",
+    }
 
 
 def sort_leg(lg=28, reps=5, seed=2024):
@@ -564,13 +613,22 @@ def main():
                     help="skip the small warm-cache latency leg")
     ap.add_argument("--no-ablation", action="store_true",
                     help="skip the co-rank vs cross-rank partition ablation")
+    ap.add_argument("--no-generic", action="store_true",
+                    help="skip the descending-order and wide-record legs")
     ap.add_argument("--no-sort", action="store_true",
                     help="skip the stable merge sort leg")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving leg (Poisson arrivals, p50/p99)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one cm_copy of 1 GiB (for counter calibration)")
+    ap.add_argument("--only-step", action="store_true",
+                    help="run the timed step only (no other leg): the form profiled under "
+                         "rocprofv3")
     args = ap.parse_args()
+    if args.only_step:
+        for leg in ("cpu_baseline", "batched", "latency", "serving", "boundary_ab", "ablation",
+                    "generic", "sort"):
+            setattr(args, "no_" + leg, True)
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
@@ -720,6 +778,13 @@ def main():
         log(f"partition ablation (P={pa['P']}): co-rank {pa['co_rank']['merge_kernel_ms']:.3f} ms, "
             f"cross-rank {pa['cross_rank']['merge_kernel_ms']:.3f} ms, longest segment "
             f"{pa['cross_rank']['longest_segment_over_mean']:.2f} x mean")
+
+    if not segmented and not args.no_generic:
+        result["generic_order"] = generic_order_leg(A, Av, B, Bv)
+        go = result["generic_order"]
+        log(f"descending merge {go['descending_call_ms']:.3f} ms vs ascending "
+            f"{go['ascending_call_ms']:.3f} ms; with 8-byte records {go['records_8byte_ms']:.3f} ms")
+        torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on the host")

@@ -18,7 +18,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB_NAME = "libcorank_merge.so"
 LIB_PATH = os.path.join(HERE, LIB_NAME)
 
-HIP_SOURCES = ["launch.hip", "sort.hip"]
+HIP_SOURCES = ["launch.hip", "launch_keys_u32.hip", "launch_keys_u64.hip", "launch_keys_f32.hip",
+               "sort.hip"]
 CXX_SOURCES = ["api.cpp", "host_co_rank.cpp", "server.cpp"]
 
 # -packed-fp32-ops: keep the compiler from emitting packed fp32 VALU ops.

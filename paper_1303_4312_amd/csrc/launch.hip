@@ -10,8 +10,18 @@
 #include "dispatch.hpp"
 #include "internal.hpp"
 #include "kernels.hpp"
+#include "launch_decl.hpp"
 
 namespace cm {
+
+// The key-dependent launchers are instantiated in launch_keys_*.hip (one file
+// per key width, compiled side by side); only the dispatch lives here.
+extern template struct Launch<uint32_t>;
+extern template struct Launch<Desc<uint32_t>>;
+extern template struct Launch<uint64_t>;
+extern template struct Launch<Desc<uint64_t>>;
+extern template struct Launch<float>;
+extern template struct Launch<Desc<float>>;
 
 // Every configuration is instantiated for every key type and payload mode.
 // E is odd so that the strided LDS accesses of the transposes (stride E
@@ -153,122 +163,34 @@ int launch_gather_records(const uint32_t* codes, uint64_t N, const void* A_rec, 
 
 int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B,
                           uint64_t n, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    const uint64_t blocks = (nb + 255) / 256;
-    if (ch.partition == 0) {
-      hipLaunchKernelGGL((k_block_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
-                         (const K*)B, n, tile, nb, bj, ch.search);
-      return launch_status();
-    }
-    const uint32_t G = sh.coarse_stride;
-    const uint64_t nc = num_coarse(nb, G);
-    if (ch.partition == 1)
-      hipLaunchKernelGGL((k_coarse_co_rank<K, 64>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st,
-                         (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
-    else
-      hipLaunchKernelGGL((k_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st,
-                         (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
-    if (launch_status() != CM_OK) return CM_EHIP;
-    hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
-                       (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
-    return launch_status();
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::block_co_ranks(ch, sh, A, m, B, n, tile, nb, bj, coarse, st); });
 }
 
 int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
                         uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
-      const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
-      const dim3 g((unsigned)tiles), b(NT);
-      // bj == nullptr: every block co-ranks its own ends (no boundary pass)
-      auto go = [&](auto val_c, auto vec_c) {
-        constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
-        if (bj)
-          hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv, n,
-                             (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
-        else
-          hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
-                             Bv, n, (K*)C, Cv, tiles, ch.search, sh.xcd_order);
-      };
-      using T_ = std::true_type;
-      using F_ = std::false_type;
-      if (val && vec)
-        go(T_{}, T_{});
-      else if (val)
-        go(T_{}, F_{});
-      else if (vec)
-        go(F_{}, T_{});
-      else
-        go(F_{}, F_{});
-      return launch_status();
-    });
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::merge_blocks(val, ch, sh, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st); });
 }
 
 // Resident workgroups per CU of `kernel` at nt threads, times the CU count;
 // cached per kernel (the library drives one device type).
-static uint32_t resident_blocks(const void* kernel, int nt, int* cache) {
-  if (*cache > 0) return (uint32_t)*cache;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || cus <= 0 ||
-      per_cu <= 0) {
-    (void)hipGetLastError();
-    return 256;  // a safe count for any device: correctness never depends on it
-  }
-  *cache = cus * per_cu;
-  return (uint32_t)*cache;
-}
 
 uint32_t stream_blocks(int kt, bool val, const Choice& ch, uint64_t N) {
   const uint64_t T = tile_size(ch.cfg);
   const uint64_t tiles = (N + T - 1) / T;
-  const uint32_t res = (uint32_t)by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      static int cache_v = 0, cache_k = 0;
-      return val ? (int)resident_blocks((const void*)k_merge_stream<K, true, NT, E>, NT, &cache_v)
-                 : (int)resident_blocks((const void*)k_merge_stream<K, false, NT, E>, NT, &cache_k);
-    });
-  });
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, tiles));
+  const int res = by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::stream_resident(val, ch.cfg); });
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res > 0 ? (uint64_t)res : 256, tiles));
 }
 
 int launch_stream_co_ranks(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t P, uint64_t* J,
                            hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    const uint64_t waves = (uint64_t)P + 1;
-    hipLaunchKernelGGL((k_stream_co_rank<K>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, (const K*)A, m,
-                       (const K*)B, n, P, J);
-    return launch_status();
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::stream_co_ranks(A, m, B, n, P, J, st); });
 }
 
 int launch_merge_stream(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m,
                         const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* I,
                         const uint64_t* J, uint32_t P, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      if (val)
-        hipLaunchKernelGGL((k_merge_stream<K, true, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
-                           (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
-      else
-        hipLaunchKernelGGL((k_merge_stream<K, false, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
-                           (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
-      return launch_status();
-    });
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::merge_stream(val, ch, A, Av, m, B, Bv, n, C, Cv, I, J, P, st); });
 }
 
 int launch_cross_rank_cuts(int kt, const void* A, uint64_t m, const void* B, uint64_t n, uint32_t h, uint64_t* cuts,
@@ -279,10 +201,7 @@ int launch_cross_rank_cuts(int kt, const void* A, uint64_t m, const void* B, uin
   uint64_t* jb = cuts + 3ull * h;
   const unsigned blocks = (unsigned)((2ull * h + 255) / 256);
   const int rc = by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    hipLaunchKernelGGL((k_cross_rank_cuts<K>), dim3(blocks), dim3(256), 0, st, (const K*)A, m, (const K*)B, n, h, ia,
-                       ja, ib, jb);
-    return launch_status();
+    return Launch<decltype(key)>::cross_rank_cuts(A, m, B, n, h, ia, ja, ib, jb, blocks, st);
   });
   if (rc != CM_OK) return rc;
   hipLaunchKernelGGL(k_cross_rank_place, dim3(blocks), dim3(256), 0, st, (const uint64_t*)ia, (const uint64_t*)ja,
@@ -309,55 +228,14 @@ int launch_seg_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const v
                               const void* B, const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile,
                               uint64_t nb, uint64_t* bj, uint32_t* bs, uint64_t* jc, uint32_t* sc,
                               const uint32_t* flag, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    if (ch.partition == 0 || !jc || !sc) {
-      hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
-                         (const K*)A, a_off, (const K*)B, b_off, S, N, tile, nb, bj, bs, flag, ch.search);
-      return launch_status();
-    }
-    const uint32_t G = sh.coarse_stride;
-    const uint64_t nc = num_coarse(nb, G);
-    hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const K*)A,
-                       a_off, (const K*)B, b_off, S, N, tile * G, nc, jc, sc, flag, ch.search);
-    if (launch_status() != CM_OK) return CM_EHIP;
-    hipLaunchKernelGGL((k_seg_fine_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, (const K*)A,
-                       a_off, (const K*)B, b_off, N, tile, nb, G, (const uint64_t*)jc, (const uint32_t*)sc, bj, bs,
-                       flag);
-    return launch_status();
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::seg_block_co_ranks(ch, sh, A, a_off, B, b_off, S, N, tile, nb, bj, bs, jc, sc, flag, st); });
 }
 
 int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, const uint32_t* Av,
                             const uint64_t* a_off, const void* B, const uint32_t* Bv, const uint64_t* b_off,
                             uint32_t S, uint64_t N, void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs,
                             uint64_t tiles, const uint32_t* flag, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
-      // outputs 16-byte aligned: 16-byte stores (the inputs are staged element-wise)
-      const bool vst = val ? all_aligned16({C, Cv}) : all_aligned16({C});
-      auto go = [&](auto val_c, auto vst_c) {
-        constexpr bool V = decltype(val_c)::value, W = decltype(vst_c)::value;
-        hipLaunchKernelGGL((k_seg_merge_blocks<K, V, NT, E, W>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
-                           ch.search);
-      };
-      using T_ = std::true_type;
-      using F_ = std::false_type;
-      if (val && vst)
-        go(T_{}, T_{});
-      else if (val)
-        go(T_{}, F_{});
-      else if (vst)
-        go(F_{}, T_{});
-      else
-        go(F_{}, F_{});
-      return launch_status();
-    });
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::seg_merge_blocks(val, ch, A, Av, a_off, B, Bv, b_off, S, N, C, Cv, bj, bs, tiles, flag, st); });
 }
 
 static_assert(sizeof(MergeDesc) == sizeof(cm_merge_desc), "descriptor layouts differ");
@@ -365,57 +243,25 @@ static_assert(offsetof(MergeDesc, first_block) == offsetof(cm_merge_desc, first_
 
 int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
                           uint64_t* bj, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    hipLaunchKernelGGL((k_batch_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
-                       (const MergeDesc*)d, count, tile, nb, bj, ch.search);
-    return launch_status();
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::batch_co_ranks(ch, d, count, tile, nb, bj, st); });
 }
 
 int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
                               const uint64_t* bj, uint64_t tiles, bool vec, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      const dim3 g((unsigned)tiles), b(NT);
-      const MergeDesc* q = (const MergeDesc*)d;
-      if (val && vec)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search);
-      else if (val)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                           ch.search);
-      else if (vec)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, true>), g, b, 0, st, q, count, bj, tiles,
-                           ch.search);
-      else
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                           ch.search);
-      return launch_status();
-    });
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::batch_merge_blocks(val, ch, d, count, bj, tiles, vec, st); });
 }
 
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,
                         const void* B, uint64_t n, uint64_t* j_out, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    hipLaunchKernelGGL((k_co_rank_many<K>), dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, ranks, q,
-                       (const K*)A, m, (const K*)B, n, j_out, search);
-    return launch_status();
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::co_rank_many(search, ranks, q, A, m, B, n, j_out, st); });
 }
 
 int launch_check_sorted(int kt, const void* X, uint64_t len, uint32_t* flag, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(1), 0, st, flag, 0u);
-  if (launch_status() != CM_OK || len < 2) return launch_status();
+  const int rc = launch_status();
+  if (rc != CM_OK || len < 2) return rc;
   const uint64_t blocks = std::min<uint64_t>((len + 255) / 256, 4096);
-  return by_key(kt, [&](auto key) -> int {
-    using K = decltype(key);
-    hipLaunchKernelGGL((k_check_sorted<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)X, len, flag);
-    return launch_status();
-  });
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::check_sorted(X, len, flag, blocks, st); });
 }
 
 int launch_copy16(const void* src, void* dst, uint64_t count16, hipStream_t st) {
