@@ -276,6 +276,9 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     always uses one level.  All give the same results.
  *   cm_set_coarse_stride: blocks between coarse boundaries of the two-level
  *     pass (default 64; at least 16).
+ *   cm_set_fine_lanes: lanes that search each boundary of the two-level
+ *     pass's fine step inside its coarse window: 1 = bisection, 2 or 4 = a
+ *     ternary or 5-ary search (fewer dependent rounds, more lanes).
  *   cm_set_block_order: 1 (default) hands each of the chip's 8 XCDs a
  *     contiguous run of blocks (workgroups reach the XCDs round-robin), so
  *     neighbouring blocks, which share the cache lines at their window
@@ -294,6 +297,7 @@ int cm_set_partition(int partition_mode);
 int cm_get_partition(void);
 int cm_set_coarse_stride(uint32_t blocks);
 int cm_set_block_order(int xcd_contiguous);
+int cm_set_fine_lanes(int lanes);
 
 /*
  * Autotuner (self-written; not part of the method).  Times every tile

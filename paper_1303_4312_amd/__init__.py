@@ -30,7 +30,7 @@ __all__ = [
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
     "stable_sort", "sort_workspace_size", "merge_partition_ablation", "origin_codes",
     "gather_records", "merge_records",
-    "launch_batch", "set_coarse_stride", "set_block_order",
+    "launch_batch", "set_coarse_stride", "set_block_order", "set_fine_lanes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +54,7 @@ EXPORTS = [
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
-    "cm_set_coarse_stride", "cm_set_block_order",
+    "cm_set_coarse_stride", "cm_set_block_order", "cm_set_fine_lanes",
     "cm_server_create", "cm_server_submit", "cm_server_poll", "cm_server_release",
     "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_stable_sort",
     "cm_stable_sort_pairs", "cm_partition_ablation_workspace_size", "cm_merge_partition_ablation",
@@ -110,6 +110,7 @@ def load():
         "cm_set_partition": (c_int, [c_int]),
         "cm_set_coarse_stride": (c_int, [ctypes.c_uint32]),
         "cm_set_block_order": (c_int, [c_int]),
+        "cm_set_fine_lanes": (c_int, [c_int]),
         "cm_get_partition": (c_int, []),
         "cm_stable_merge_segmented_each": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
                                                    c_u64, vp, vp, vp, c_size, vp]),
@@ -585,6 +586,11 @@ def get_partition() -> int:
 def set_coarse_stride(blocks: int):
     """Blocks between coarse boundaries of the two-level pass (>= 16)."""
     _check(load().cm_set_coarse_stride(blocks), "cm_set_coarse_stride")
+
+
+def set_fine_lanes(lanes: int):
+    """Lanes per boundary in the fine step of the two-level pass (1, 2, 4)."""
+    _check(load().cm_set_fine_lanes(lanes), "cm_set_fine_lanes")
 
 
 def set_block_order(xcd_contiguous: int):

@@ -555,6 +555,12 @@ int cm_set_coarse_stride(uint32_t blocks) {
   return CM_OK;
 }
 
+int cm_set_fine_lanes(int lanes) {
+  if (lanes != 1 && lanes != 2 && lanes != 4) return CM_EINVAL;
+  g_set.shape.fine_lanes = lanes;
+  return CM_OK;
+}
+
 int cm_set_block_order(int xcd_contiguous) {
   if (xcd_contiguous != 0 && xcd_contiguous != 1) return CM_EINVAL;
   g_set.shape.xcd_order = xcd_contiguous;

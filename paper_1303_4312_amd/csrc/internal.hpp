@@ -49,6 +49,7 @@ constexpr uint64_t kInBlockBelow = 1ull << 22;
 struct Shape {
   uint32_t coarse_stride = 64;  // blocks between coarse boundaries
   int xcd_order = 1;            // XCD-contiguous block order in the block merge
+  int fine_lanes = 1;           // lanes per boundary in the fine pass (1: bisection; 2, 4)
 };
 
 inline uint64_t tile_size(int cfg) { return (uint64_t)kCfgs[cfg].nt * (uint64_t)kCfgs[cfg].e; }

@@ -101,6 +101,41 @@ __global__ __launch_bounds__(256) void k_fine_co_rank(const K* __restrict__ A, u
 }
 
 // Arbitrary ranks: j_out[r] = A co-rank of ranks[r], UINT64_MAX if out of range.
+// The fine pass with L lanes per boundary (L = 2 or 4): each group searches
+// its window L-ary (co_rank_group), ceil(log_{L+1} w) rounds instead of
+// ceil(log2 w).  Whole waves run together: groups past the end and coarse
+// boundaries take an empty interval.
+template <typename K, int L>
+__global__ __launch_bounds__(256) void k_fine_co_rank_group(const K* __restrict__ A, uint64_t m,
+                                                            const K* __restrict__ B, uint64_t n, uint64_t tile,
+                                                            uint64_t num_bounds, uint32_t G,
+                                                            const uint64_t* __restrict__ jc,
+                                                            uint64_t* __restrict__ j_out) {
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if ((gid & ~63ull) / L >= num_bounds) return;  // whole waves with no boundary leave
+  const uint64_t t = gid / L;
+  const bool mine = t < num_bounds;
+  const uint64_t N = m + n;
+  const uint64_t c = mine ? t / G : 0;
+  const bool coarse = mine && t % G == 0;
+  uint64_t lo = 0, hi = 0, i = 0;
+  if (mine && !coarse) {
+    i = std::min(t * tile, N);
+    const uint64_t i0 = std::min(c * G * tile, N), i1 = std::min((c + 1) * G * tile, N);
+    const uint64_t j0 = jc[c], j1 = jc[c + 1];
+    const uint64_t k0 = i0 - j0, k1 = i1 - j1;
+    lo = std::max(i > n ? i - n : 0, j0);
+    if (i > k1) lo = std::max(lo, i - k1);
+    hi = std::min(std::min(i, m), j1);
+    hi = std::min(hi, i - std::min(k0, i));
+    if (hi < lo) hi = lo;  // only for unsorted input (monotonicity broken)
+  }
+  auto ra = [=](uint64_t x) { return A[x]; };
+  auto rb = [=](uint64_t x) { return B[x]; };
+  const uint64_t j = co_rank_group<K, L>(i, ra, rb, lo, hi);
+  if (mine && (gid & (L - 1)) == 0) j_out[t] = coarse ? jc[c] : j;
+}
+
 template <typename K>
 __global__ __launch_bounds__(256) void k_co_rank_many(const uint64_t* __restrict__ ranks, uint64_t q,
                                                       const K* __restrict__ A, uint64_t m,

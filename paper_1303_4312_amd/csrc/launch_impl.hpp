@@ -50,8 +50,18 @@ int Launch<K>::block_co_ranks(const Choice& ch, const Shape& sh, const void* A, 
       hipLaunchKernelGGL((k_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st,
                          (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
     if (launch_status() != CM_OK) return CM_EHIP;
-    hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
-                       (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+    if (sh.fine_lanes == 2 || sh.fine_lanes == 4) {
+      const uint64_t lanes = nb * (uint64_t)sh.fine_lanes;
+      if (sh.fine_lanes == 2)
+        hipLaunchKernelGGL((k_fine_co_rank_group<K, 2>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st,
+                           (const K*)A, m, (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+      else
+        hipLaunchKernelGGL((k_fine_co_rank_group<K, 4>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st,
+                           (const K*)A, m, (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+    } else {
+      hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
+                         (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+    }
     return launch_status();
 }
 

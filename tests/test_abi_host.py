@@ -136,6 +136,7 @@ def test_config_table(restore_settings):
         cm.set_partition(mode)
         assert cm.get_partition() == mode
     assert cm.load().cm_set_partition(5) == EINVAL
+    assert cm.load().cm_set_fine_lanes(3) == EINVAL and cm.load().cm_set_fine_lanes(8) == EINVAL
     assert cm.load().cm_set_partition(-2) == EINVAL
     assert cm.load().cm_tuning_set(0, 0, 1, 20, 0, 1, 5) == EINVAL
 

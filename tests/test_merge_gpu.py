@@ -76,14 +76,17 @@ def test_all_configs_pairs_and_keys(dtype, search, partition):
             check_keys(A, B)
 
 
-@pytest.mark.parametrize("partition,stride,xcd", [(0, 64, 1), (1, 64, 1), (2, 64, 0), (1, 16, 0),
-                                                  (2, 16, 1), (3, 64, 1), (4, 64, 1), (4, 64, 0)])
-def test_two_level_partition_edges(partition, stride, xcd):
+@pytest.mark.parametrize("partition,stride,xcd,lanes", [
+    (0, 64, 1, 1), (1, 64, 1, 1), (2, 64, 0, 1), (1, 16, 0, 1), (2, 16, 1, 1), (3, 64, 1, 1),
+    (4, 64, 1, 1), (4, 64, 0, 1), (2, 64, 1, 2), (2, 16, 0, 4), (1, 64, 1, 4), (2, 64, 1, 4)])
+def test_two_level_partition_edges(partition, stride, xcd, lanes):
     """Block counts around multiples of the coarse stride, with the co-rank
-    windows of the fine pass both wide and degenerate; both block orders."""
+    windows of the fine pass both wide and degenerate; both block orders;
+    1, 2 or 4 lanes per fine boundary."""
     cm.set_partition(partition)
     cm.set_coarse_stride(stride)
     cm.set_block_order(xcd)
+    cm.set_fine_lanes(lanes)
     nt, e = cm.config_info(cm.get_config("uint32", True))
     T = nt * e
     rng = np.random.default_rng(21)
