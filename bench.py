@@ -401,6 +401,103 @@ def sort_leg(lg=28, reps=5, seed=2024):
     }
 
 
+def host_ingress_leg(pool_size=16, count=400, slots=8, seed=5000):
+    """Serving with requests in host memory (beside the device-resident leg):
+    each request's inputs wait in pinned host memory, are copied to one of
+    `slots` device staging areas on a copy stream, merged by the library's
+    serving runtime (which waits for that copy: inputs_pending), and its
+    outputs are copied back to pinned host memory on a second copy stream.
+    A request is done once its outputs are on the host; then its ticket and
+    staging slot are freed.  Closed loop (a new request enters as soon as a
+    slot is free): requests/s, keys/s and PCIe bytes per second (both ways
+    together); latency from entering a slot to outputs on the host."""
+    import torch
+    import paper_1303_4312_amd as cm
+    from paper_1303_4312_amd import serve, workloads as w
+    dev = torch.device("cuda:0")
+    pool = []
+    for r in range(pool_size):
+        d = w.request(seed + r)
+        pool.append(tuple(torch.from_numpy(d[k]).pin_memory() for k in ("A", "B", "Av", "Bv")))
+    cap = max(p[0].numel() + p[1].numel() for p in pool)
+    # per slot: device keys + payloads (A then B), host keys + payloads for the outputs
+    stage = [(torch.empty(cap, dtype=torch.uint32, device=dev),
+              torch.empty(cap, dtype=torch.uint32, device=dev)) for _ in range(slots)]
+    back = [(torch.empty(cap, dtype=torch.uint32).pin_memory(),
+             torch.empty(cap, dtype=torch.uint32).pin_memory()) for _ in range(slots)]
+    h2d, d2h = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+    srv = serve.NativeServer("uint32", True, arena_bytes=16 * cap * slots, max_batch=64,
+                             max_inflight=2, max_requests=slots, device=dev)
+    free = list(range(slots))
+    merging = {}   # ticket -> (slot, outputs, entered)
+    copying = []   # (event, ticket, slot, outputs, entered)
+    lat, done, sub, outputs, moved = [], 0, 0, 0, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while done < count:
+        while sub < count and free:
+            slot = free.pop()
+            A, B, Av, Bv = pool[sub % pool_size]
+            m, n = A.numel(), B.numel()
+            sk, sv = stage[slot]
+            entered = time.perf_counter()
+            with torch.cuda.stream(h2d):
+                sk[:m].copy_(A, non_blocking=True)
+                sk[m:m + n].copy_(B, non_blocking=True)
+                sv[:m].copy_(Av, non_blocking=True)
+                sv[m:m + n].copy_(Bv, non_blocking=True)
+            rc = srv.submit_ptrs(sk.data_ptr(), sv.data_ptr(), m, sk.data_ptr() + 4 * m,
+                                 sv.data_ptr() + 4 * m, n, h2d.cuda_stream, pending=True)
+            if rc != 0:
+                raise cm.CMError(rc, "cm_server_submit")
+            merging[srv.last_ticket] = (slot, m + n, entered)
+            moved += 8 * (m + n)
+            sub += 1
+        for d in srv.poll(wait_us=100 if not copying else 0):
+            if d.status != 0:
+                raise cm.CMError(d.status, "serving request")
+            slot, n_out, entered = merging.pop(d.ticket)
+            C, Cv = srv.outputs(d, n_out)
+            hk, hv = back[slot]
+            with torch.cuda.stream(d2h):
+                hk[:n_out].copy_(C, non_blocking=True)
+                hv[:n_out].copy_(Cv, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record(d2h)
+            copying.append((ev, d.ticket, slot, n_out, entered))
+        still = []
+        for item in copying:
+            ev, ticket, slot, n_out, entered = item
+            if not ev.query():
+                still.append(item)
+                continue
+            lat.append(time.perf_counter() - entered)
+            srv.release(ticket)
+            free.append(slot)
+            outputs += n_out
+            moved += 8 * n_out
+            done += 1
+        copying = still
+    wall = time.perf_counter() - t0
+    srv.close()
+    lat.sort()
+
+    def pick(q):
+        return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+    return {
+        "workload": ("the serving requests (sides log-uniform in [2^10, 2^24], uint32 key + "
+                     "payload) held in pinned host memory; inputs copied in and outputs "
+                     "copied out on two copy streams"),
+        "requests": count,
+        "staging_slots": slots,
+        "requests_per_s": count / wall,
+        "keys_per_s": outputs / wall,
+        "pcie_bytes_per_s": moved / wall,
+        "p50_ms": pick(0.5) * 1e3,
+        "p99_ms": pick(0.99) * 1e3,
+    }
+
+
 def latency_leg(reps=200, warmup=20):
     """Small single merge, m = n = 2^20 uint32 keys uniform in [0, 2^16) with
     payloads: it fits in the Infinity Cache, so this is a warm-cache latency
@@ -818,6 +915,11 @@ def main():
     if not args.no_serving:
         torch.cuda.empty_cache()
         result["serving"] = serving_leg()
+        torch.cuda.empty_cache()
+        result["serving_host_ingress"] = host_ingress_leg()
+        hi = result["serving_host_ingress"]
+        log(f"serving (host ingress): {hi['requests_per_s']:.0f} req/s, "
+            f"{hi['pcie_bytes_per_s'] / 1e9:.1f} GB/s over PCIe, p50 {hi['p50_ms']:.2f} ms")
 
     print(json.dumps(result), flush=True)
 
