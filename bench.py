@@ -401,6 +401,35 @@ def sort_leg(lg=28, reps=5, seed=2024):
     }
 
 
+def pcie_ceiling(nbytes=256 << 20, reps=10):
+    """Plain pinned-host <-> device copy rates on this machine (GB/s): host to
+    device alone, device to host alone, and both at once on two streams."""
+    import torch
+    dev = torch.device("cuda:0")
+    h_in = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    h_out = torch.empty(nbytes, dtype=torch.uint8).pin_memory()
+    d_in = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    d_out = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    s1, s2 = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
+
+    def run(up, down):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            if up:
+                with torch.cuda.stream(s1):
+                    d_in.copy_(h_in, non_blocking=True)
+            if down:
+                with torch.cuda.stream(s2):
+                    h_out.copy_(d_out, non_blocking=True)
+        torch.cuda.synchronize()
+        return (int(up) + int(down)) * reps * nbytes / (time.perf_counter() - t) / 1e9
+
+    run(True, True)
+    return {"h2d_gbs": run(True, False), "d2h_gbs": run(False, True),
+            "both_ways_gbs": run(True, True), "bytes_per_copy": nbytes}
+
+
 def host_ingress_leg(pool_size=16, count=400, slots=8, seed=5000):
     """Serving with requests in host memory (beside the device-resident leg):
     each request's inputs wait in pinned host memory, are copied to one of
@@ -410,15 +439,23 @@ def host_ingress_leg(pool_size=16, count=400, slots=8, seed=5000):
     A request is done once its outputs are on the host; then its ticket and
     staging slot are freed.  Closed loop (a new request enters as soon as a
     slot is free): requests/s, keys/s and PCIe bytes per second (both ways
-    together); latency from entering a slot to outputs on the host."""
+    together) against the box's plain pinned-copy rates; latency from entering
+    a slot to outputs on the host.  A first pass over the pool (also the
+    warm-up) checks every request's host outputs against the same merge run
+    alone on the device, byte for byte."""
+    import numpy as np
     import torch
     import paper_1303_4312_amd as cm
     from paper_1303_4312_amd import serve, workloads as w
     dev = torch.device("cuda:0")
-    pool = []
+    pool, alone = [], []
     for r in range(pool_size):
         d = w.request(seed + r)
         pool.append(tuple(torch.from_numpy(d[k]).pin_memory() for k in ("A", "B", "Av", "Bv")))
+        A, B, Av, Bv = (t.to(dev) for t in pool[-1])
+        C, Cv = cm.stable_merge_pairs(A, Av, B, Bv)
+        alone.append((C.cpu().numpy(), Cv.cpu().numpy()))
+        del A, B, Av, Bv, C, Cv
     cap = max(p[0].numel() + p[1].numel() for p in pool)
     # per slot: device keys + payloads (A then B), host keys + payloads for the outputs
     stage = [(torch.empty(cap, dtype=torch.uint32, device=dev),
@@ -428,74 +465,90 @@ def host_ingress_leg(pool_size=16, count=400, slots=8, seed=5000):
     h2d, d2h = torch.cuda.Stream(dev), torch.cuda.Stream(dev)
     srv = serve.NativeServer("uint32", True, arena_bytes=16 * cap * slots, max_batch=64,
                              max_inflight=2, max_requests=slots, device=dev)
-    free = list(range(slots))
-    merging = {}   # ticket -> (slot, outputs, entered)
-    copying = []   # (event, ticket, slot, outputs, entered)
-    lat, done, sub, outputs, moved = [], 0, 0, 0, 0
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    while done < count:
-        while sub < count and free:
-            slot = free.pop()
-            A, B, Av, Bv = pool[sub % pool_size]
-            m, n = A.numel(), B.numel()
-            sk, sv = stage[slot]
-            entered = time.perf_counter()
-            with torch.cuda.stream(h2d):
-                sk[:m].copy_(A, non_blocking=True)
-                sk[m:m + n].copy_(B, non_blocking=True)
-                sv[:m].copy_(Av, non_blocking=True)
-                sv[m:m + n].copy_(Bv, non_blocking=True)
-            rc = srv.submit_ptrs(sk.data_ptr(), sv.data_ptr(), m, sk.data_ptr() + 4 * m,
-                                 sv.data_ptr() + 4 * m, n, h2d.cuda_stream, pending=True)
-            if rc != 0:
-                raise cm.CMError(rc, "cm_server_submit")
-            merging[srv.last_ticket] = (slot, m + n, entered)
-            moved += 8 * (m + n)
-            sub += 1
-        for d in srv.poll(wait_us=100 if not copying else 0):
-            if d.status != 0:
-                raise cm.CMError(d.status, "serving request")
-            slot, n_out, entered = merging.pop(d.ticket)
-            C, Cv = srv.outputs(d, n_out)
-            hk, hv = back[slot]
-            with torch.cuda.stream(d2h):
-                hk[:n_out].copy_(C, non_blocking=True)
-                hv[:n_out].copy_(Cv, non_blocking=True)
-                ev = torch.cuda.Event()
-                ev.record(d2h)
-            copying.append((ev, d.ticket, slot, n_out, entered))
-        still = []
-        for item in copying:
-            ev, ticket, slot, n_out, entered = item
-            if not ev.query():
-                still.append(item)
-                continue
-            lat.append(time.perf_counter() - entered)
-            srv.release(ticket)
-            free.append(slot)
-            outputs += n_out
-            moved += 8 * n_out
-            done += 1
-        copying = still
-    wall = time.perf_counter() - t0
-    srv.close()
-    lat.sort()
 
-    def pick(q):
-        return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
-    return {
+    def run(count, check):
+        free = list(range(slots))
+        merging = {}   # ticket -> (request, slot, outputs, entered)
+        copying = []   # (event, ticket, request, slot, outputs, entered)
+        lat, done, sub, outputs, moved = [], 0, 0, 0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while done < count:
+            while sub < count and free:
+                slot = free.pop()
+                A, B, Av, Bv = pool[sub % pool_size]
+                m, n = A.numel(), B.numel()
+                sk, sv = stage[slot]
+                entered = time.perf_counter()
+                with torch.cuda.stream(h2d):
+                    sk[:m].copy_(A, non_blocking=True)
+                    sk[m:m + n].copy_(B, non_blocking=True)
+                    sv[:m].copy_(Av, non_blocking=True)
+                    sv[m:m + n].copy_(Bv, non_blocking=True)
+                rc = srv.submit_ptrs(sk.data_ptr(), sv.data_ptr(), m, sk.data_ptr() + 4 * m,
+                                     sv.data_ptr() + 4 * m, n, h2d.cuda_stream, pending=True)
+                if rc != 0:
+                    raise cm.CMError(rc, "cm_server_submit")
+                merging[srv.last_ticket] = (sub, slot, m + n, entered)
+                moved += 8 * (m + n)
+                sub += 1
+            for d in srv.poll(wait_us=100 if not copying else 0):
+                if d.status != 0:
+                    raise cm.CMError(d.status, "serving request")
+                req, slot, n_out, entered = merging.pop(d.ticket)
+                C, Cv = srv.outputs(d, n_out)
+                hk, hv = back[slot]
+                with torch.cuda.stream(d2h):
+                    hk[:n_out].copy_(C, non_blocking=True)
+                    hv[:n_out].copy_(Cv, non_blocking=True)
+                    ev = torch.cuda.Event()
+                    ev.record(d2h)
+                copying.append((ev, d.ticket, req, slot, n_out, entered))
+            still = []
+            for item in copying:
+                ev, ticket, req, slot, n_out, entered = item
+                if not ev.query():
+                    still.append(item)
+                    continue
+                lat.append(time.perf_counter() - entered)
+                if check:
+                    Ce, Cve = alone[req % pool_size]
+                    hk, hv = back[slot]
+                    if not (np.array_equal(hk[:n_out].numpy(), Ce)
+                            and np.array_equal(hv[:n_out].numpy(), Cve)):
+                        raise AssertionError(f"host-ingress request {req}: outputs differ "
+                                             "from the merge run alone")
+                srv.release(ticket)
+                free.append(slot)
+                outputs += n_out
+                moved += 8 * n_out
+                done += 1
+            copying = still
+        wall = time.perf_counter() - t0
+        lat.sort()
+
+        def pick(q):
+            return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+        return {"requests_per_s": count / wall, "keys_per_s": outputs / wall,
+                "pcie_bytes_per_s": moved / wall, "p50_ms": pick(0.5) * 1e3,
+                "p99_ms": pick(0.99) * 1e3}
+
+    run(pool_size, check=True)
+    res = run(count, check=False)
+    srv.close()
+    del stage, back
+    ceiling = pcie_ceiling()
+    res.update({
         "workload": ("the serving requests (sides log-uniform in [2^10, 2^24], uint32 key + "
                      "payload) held in pinned host memory; inputs copied in and outputs "
                      "copied out on two copy streams"),
         "requests": count,
         "staging_slots": slots,
-        "requests_per_s": count / wall,
-        "keys_per_s": outputs / wall,
-        "pcie_bytes_per_s": moved / wall,
-        "p50_ms": pick(0.5) * 1e3,
-        "p99_ms": pick(0.99) * 1e3,
-    }
+        "alone_vs_mix_checked": pool_size,
+        "pcie_ceiling": ceiling,
+        "frac_of_pcie_both_ways": res["pcie_bytes_per_s"] / 1e9 / ceiling["both_ways_gbs"],
+    })
+    return res
 
 
 def latency_leg(reps=200, warmup=20):
@@ -580,8 +633,9 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
     inputs plus outputs) and batches them on the fly.  First a closed loop
     (every request at once) gives the saturation rate; then Poisson arrivals
     at fractions of it.  Latency is arrival to completion as seen by the
-    scheduler.  The pure-Python scheduler's saturation rate on the same pool
-    is reported beside it."""
+    scheduler.  The warm-up run checks every finished request's outputs
+    against the same merge run alone, bit for bit.  The pure-Python
+    scheduler's saturation rate on the same pool is reported beside it."""
     import numpy as np
     import torch
     import paper_1303_4312_amd as cm
@@ -596,10 +650,12 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
     sizes = [p[0].numel() + p[1].numel() for p in pool]
     ptrs = [(A.data_ptr(), Av.data_ptr(), A.numel(), B.data_ptr(), Bv.data_ptr(), B.numel())
             for A, B, Av, Bv in pool]
+    alone = [tuple(t.view(torch.int32) for t in cm.stable_merge_pairs(A, Av, B, Bv))
+             for A, B, Av, Bv in pool]  # each request merged alone
     arena = torch.empty(16 << 30, dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
-    def run_native(arrivals):
+    def run_native(arrivals, check=False):
         total = len(arrivals)
         srv = serve.NativeServer("uint32", True, arena=arena, max_batch=64, max_inflight=2,
                                  max_requests=4096, device=dev)
@@ -615,15 +671,22 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
                     break
                 if rc != 0:
                     raise cm.CMError(rc, "cm_server_submit")
-                late[srv.last_ticket] = (now - (t0 + arrivals[sub]), sizes[sub % pool_size])
+                late[srv.last_ticket] = (now - (t0 + arrivals[sub]), sub % pool_size)
                 sub += 1
             wait = 200 if sub >= total else max(0, min(200, int((t0 + arrivals[sub] - now) * 1e6)))
             for d in poll(wait_us=wait):
                 if d.status != 0:
                     raise cm.CMError(d.status, "serving request")
-                lateness, n_out = late.pop(d.ticket)
+                lateness, req = late.pop(d.ticket)
                 lat.append(lateness + d.latency_ns * 1e-9)
+                n_out = sizes[req]
                 outputs += n_out
+                if check:
+                    C, Cv = srv.outputs(d, n_out)
+                    if not (torch.equal(C.view(torch.int32), alone[req][0])
+                            and torch.equal(Cv.view(torch.int32), alone[req][1])):
+                        raise AssertionError(f"serving request {req}: outputs differ from "
+                                             "the merge run alone")
                 release(d.ticket)
                 t_done = time.perf_counter()
         st = srv.stats()
@@ -638,7 +701,7 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
                 "mean_batch": st["submitted"] / max(st["batches"], 1),
                 "gpu_busy_fraction": st["busy_ms"] / (wall * 1e3)}
 
-    run_native([0.0] * per_point)  # warm-up
+    run_native([0.0] * per_point, check=True)  # warm-up; every output checked
     sat = run_native([0.0] * per_point)
     sat_rate = sat["requests_per_s"]
     log(f"serving (native): saturation {sat_rate:.0f} req/s, {sat['keys_per_s'] / 1e9:.1f} "
@@ -653,7 +716,7 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
         points.append(st)
         log(f"serving (native): rate {lam:.0f}/s p50 {st['p50_ms']:.3f} ms "
             f"p99 {st['p99_ms']:.3f} ms busy {st['gpu_busy_fraction']:.2f}")
-    del arena
+    del arena, alone
     torch.cuda.empty_cache()
 
     # the pure-Python scheduler (serve.Server) on the same pool, closed loop
@@ -680,6 +743,7 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
                    "2 batches in flight",
         "pool": pool_size,
         "requests_per_point": per_point,
+        "alone_vs_mix_checked": per_point,
         "mean_outputs_per_request": float(np.mean(sizes)),
         "saturation": sat,
         "points": points,
@@ -919,7 +983,9 @@ def main():
         result["serving_host_ingress"] = host_ingress_leg()
         hi = result["serving_host_ingress"]
         log(f"serving (host ingress): {hi['requests_per_s']:.0f} req/s, "
-            f"{hi['pcie_bytes_per_s'] / 1e9:.1f} GB/s over PCIe, p50 {hi['p50_ms']:.2f} ms")
+            f"{hi['pcie_bytes_per_s'] / 1e9:.1f} GB/s over PCIe "
+            f"({hi['frac_of_pcie_both_ways']:.2f} of plain pinned copies both ways, "
+            f"{hi['pcie_ceiling']['both_ways_gbs']:.1f} GB/s), p50 {hi['p50_ms']:.2f} ms")
 
     print(json.dumps(result), flush=True)
 

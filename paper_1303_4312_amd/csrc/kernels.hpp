@@ -25,6 +25,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "merge_device.hpp"
 
@@ -201,14 +202,30 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
   const uint64_t k0 = i0 - j0;
   int pak = 0, pbk = a_len, pav = 0, pbv = a_len;  // window offsets in LDS
   if constexpr (VEC) {
-    // the two windows span at most T / V + 4 vectors
+    // the two windows span at most T / V + 4 vectors; keys and payloads are
+    // all requested before the first LDS write waits for them
     constexpr int T = NT * E;
     constexpr int RK = (T / kPerVec<K> + 4 + NT - 1) / NT;
-    stage_pair_vec<K, NT, RK>(A, m, j0, a_len, B, n, k0, b_len, s_key, pak, pbk);
-    if constexpr (VAL) {
-      constexpr int RV = (T / 4 + 4 + NT - 1) / NT;
-      stage_pair_vec<uint32_t, NT, RV>(Av, m, j0, a_len, Bv, n, k0, b_len, s_val, pav, pbv);
-    }
+    constexpr int RV = VAL ? (T / 4 + 4 + NT - 1) / NT : 1;
+    const PairSpan sk = pair_span<K>(j0, a_len, k0, b_len);
+    const PairSpan sv = pair_span<uint32_t>(j0, a_len, k0, b_len);
+    auto stage = [&](auto full) {
+      constexpr bool FULL = decltype(full)::value;
+      vec16 rk[RK], rv[RV];
+      load_pair_vec<K, NT, RK, FULL>(A, m, j0, B, n, k0, sk, rk);
+      if constexpr (VAL) load_pair_vec<uint32_t, NT, RV, FULL>(Av, m, j0, Bv, n, k0, sv, rv);
+      write_pair_vec<K, NT, RK>(s_key, sk, rk);
+      if constexpr (VAL) write_pair_vec<uint32_t, NT, RV>(s_val, sv, rv);
+    };
+    // payload vectors are partial wherever key vectors are (4-byte payloads)
+    if (pair_has_partial<K>(m, j0, n, k0, sk) || (VAL && pair_has_partial<uint32_t>(m, j0, n, k0, sv)))
+      stage(std::false_type{});
+    else
+      stage(std::true_type{});
+    pak = sk.pa;
+    pbk = sk.pb;
+    pav = sv.pa;
+    pbv = sv.pb;
   } else {
     load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
   }
@@ -822,13 +839,31 @@ __global__ __launch_bounds__(NT) void k_seg_merge_blocks(
     const uint32_t s_last = bs[t + 1];
     const uint32_t entries = s_last - s_first + 2;  // s_last + 1 <= S: inside a_off / b_off
     const bool table = entries <= kSegTable + 1;     // block-uniform
+    // the table's loads and the windows' loads are all issued before the
+    // first LDS write waits for any of them (entries s_first .. s_last + 1
+    // exist; a slot past them re-reads entry s_first)
+    constexpr int RT = (kSegTable + 1 + NT - 1) / NT;
+    uint64_t ta[RT], tb[RT];
+#pragma unroll
+    for (int r = 0; r < RT; ++r) {
+      const uint32_t x0 = threadIdx.x + (uint32_t)(r * NT);
+      const uint32_t x = x0 < entries ? x0 : 0;
+      ta[r] = a_off[s_first + x];
+      tb[r] = b_off[s_first + x];
+    }
+    WindowRegs<K, VAL, NT, E> w;
+    load_window_regs<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, w);
     if (table) {
-      for (uint32_t x = threadIdx.x; x < entries; x += NT) {
-        s_aoff[x] = a_off[s_first + x];
-        s_boff[x] = b_off[s_first + x];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        const uint32_t x = threadIdx.x + (uint32_t)(r * NT);
+        if (x < entries) {
+          s_aoff[x] = ta[r];
+          s_boff[x] = tb[r];
+        }
       }
     }
-    load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
+    write_window_regs<K, VAL, NT, E>(len, w, s_key, s_val);
     __syncthreads();
 
     // offsets of segment s (s >= s_first): from the table when it holds s

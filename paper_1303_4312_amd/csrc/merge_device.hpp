@@ -184,34 +184,59 @@ __device__ __forceinline__ int window_a_len(uint64_t j0, uint64_t j1, int len) {
 
 // Streams the two windows of a block into LDS: s_key[0, a_len) holds
 // A[ja, ja + a_len) and s_key[a_len, len) holds B[kb, kb + len - a_len);
-// payloads likewise.  Every thread issues all of its E loads before its
-// first LDS write so that E (or 2E with payloads) loads are in flight.
-// Consecutive lanes read consecutive addresses (one break at a_len).
+// payloads likewise.  Split in a load phase (registers) and an LDS-write
+// phase so that a caller can put other loads in flight beside these; every
+// thread issues all of its E (2E with payloads) loads before its first LDS
+// write.  The loads are unconditional (a slot past the block re-reads its
+// first element, len >= 1), so no copy between branches waits on a load in
+// flight.  Consecutive lanes read consecutive addresses (one break at a_len).
+template <typename K, bool VAL, int NT, int E>
+struct WindowRegs {
+  K k[E];
+  uint32_t v[VAL ? E : 1];
+};
+
+template <typename K, bool VAL, int NT, int E>
+__device__ __forceinline__ void load_window_regs(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+                                                 uint64_t ja, const K* __restrict__ B,
+                                                 const uint32_t* __restrict__ Bv, uint64_t kb, int a_len,
+                                                 int len, WindowRegs<K, VAL, NT, E>& w) {
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int x0 = (int)threadIdx.x + r * NT;
+    const int x = x0 < len ? x0 : 0;
+    const bool from_a = x < a_len;
+    const uint64_t g = from_a ? ja + (uint64_t)x : kb + (uint64_t)(x - a_len);
+    const K* pk = from_a ? A : B;
+    w.k[r] = pk[g];
+    if constexpr (VAL) {
+      const uint32_t* pv = from_a ? Av : Bv;
+      w.v[r] = pv[g];
+    }
+  }
+}
+
+template <typename K, bool VAL, int NT, int E>
+__device__ __forceinline__ void write_window_regs(int len, const WindowRegs<K, VAL, NT, E>& w, K* s_key,
+                                                  uint32_t* s_val) {
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int x = (int)threadIdx.x + r * NT;
+    if (x < len) {
+      s_key[x] = w.k[r];
+      if constexpr (VAL) s_val[x] = w.v[r];
+    }
+  }
+}
+
 template <typename K, bool VAL, int NT, int E>
 __device__ __forceinline__ void load_windows(const K* __restrict__ A, const uint32_t* __restrict__ Av,
                                              uint64_t ja, const K* __restrict__ B,
                                              const uint32_t* __restrict__ Bv, uint64_t kb, int a_len,
                                              int len, K* s_key, uint32_t* s_val) {
-  K kr[E];
-  uint32_t vr[E];
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int x = (int)threadIdx.x + r * NT;
-    if (x < len) {
-      const bool from_a = x < a_len;
-      const uint64_t g = from_a ? ja + (uint64_t)x : kb + (uint64_t)(x - a_len);
-      kr[r] = from_a ? A[g] : B[g];
-      if constexpr (VAL) vr[r] = from_a ? Av[g] : Bv[g];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < E; ++r) {
-    const int x = (int)threadIdx.x + r * NT;
-    if (x < len) {
-      s_key[x] = kr[r];
-      if constexpr (VAL) s_val[x] = vr[r];
-    }
-  }
+  WindowRegs<K, VAL, NT, E> w;
+  load_window_regs<K, VAL, NT, E>(A, Av, ja, B, Bv, kb, a_len, len, w);
+  write_window_regs<K, VAL, NT, E>(len, w, s_key, s_val);
 }
 
 // Writes the block's LDS contents (already in output order) to C[i0, i0 + len)
@@ -265,38 +290,74 @@ __device__ __forceinline__ vec16 load_span_vec(const X* __restrict__ Xp, uint64_
   return u.v;
 }
 
-// Stages the windows X_A[ga, ga + na) and X_B[gb, gb + nb) of one array pair
-// in LDS with 16-byte loads and LDS writes.  Element ga + x of the A window
-// lands at dst[pa + x] with pa = ga % V, element gb + y of the B window at
-// dst[pb + y] with pb = roundup(pa + na, V) + gb % V, so every aligned
-// global vector maps onto an aligned LDS vector.  dst must hold
-// na + nb + 3 V elements.  R = vectors per thread (compile-time bound).
-template <typename X, int NT, int R>
-__device__ __forceinline__ void stage_pair_vec(const X* __restrict__ XA, uint64_t totA, uint64_t ga, int na,
-                                               const X* __restrict__ XB, uint64_t totB, uint64_t gb, int nb,
-                                               X* dst, int& pa, int& pb) {
+// The windows X_A[ga, ga + na) and X_B[gb, gb + nb) of one array pair, as
+// staged in LDS by 16-byte vectors: element ga + x of the A window lands at
+// dst[pa + x] with pa = ga % V, element gb + y of the B window at dst[pb + y]
+// with pb = rb + gb % V and rb = roundup(pa + na, V), so every aligned global
+// vector maps onto an aligned LDS vector.  dst must hold na + nb + 3 V
+// elements.
+struct PairSpan {
+  int pa, pb, rb, nva, nvb;
+};
+
+template <typename X>
+__device__ __forceinline__ PairSpan pair_span(uint64_t ga, int na, uint64_t gb, int nb) {
   constexpr int V = kPerVec<X>;
-  pa = (int)(ga % V);
-  const int rb = (pa + na + V - 1) / V * V;  // first LDS vector slot of the B window
-  pb = rb + (int)(gb % V);
-  const int nva = span_vectors<X>(ga, na);
-  const int nvb = span_vectors<X>(gb, nb);
-  vec16 reg[R];
+  PairSpan p;
+  p.pa = (int)(ga % V);
+  p.rb = (p.pa + na + V - 1) / V * V;
+  p.pb = p.rb + (int)(gb % V);
+  p.nva = span_vectors<X>(ga, na);
+  p.nvb = span_vectors<X>(gb, nb);
+  return p;
+}
+
+// True when a vector of the pair's span runs past the end of its array (the
+// array's length is not a multiple of V and the window reaches its end): only
+// then must a vector be read element by element.  Uniform over the block.
+template <typename X>
+__device__ __forceinline__ bool pair_has_partial(uint64_t totA, uint64_t ga, uint64_t totB, uint64_t gb,
+                                                 const PairSpan& p) {
+  constexpr int V = kPerVec<X>;
+  return (p.nva && (ga / V + (uint64_t)p.nva) * V > totA) || (p.nvb && (gb / V + (uint64_t)p.nvb) * V > totB);
+}
+
+// Issues this thread's loads of the pair's vectors (R per thread at most)
+// into registers; write_pair_vec puts them in LDS.  Split in two so that a
+// caller staging keys and payloads issues every load before the first wait.
+// FULL (no vector of the span is partial): one 16-byte load per slot with no
+// branch; a slot past the span re-reads the span's first vector, so every
+// lane issues the same loads and the waits before the LDS writes count them
+// exactly.  Otherwise each vector is read through load_span_vec.
+template <typename X, int NT, int R, bool FULL>
+__device__ __forceinline__ void load_pair_vec(const X* __restrict__ XA, uint64_t totA, uint64_t ga,
+                                              const X* __restrict__ XB, uint64_t totB, uint64_t gb,
+                                              const PairSpan& p, vec16 (&reg)[R]) {
+  constexpr int V = kPerVec<X>;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int q = (int)threadIdx.x + r * NT;
-    if (q < nva)
-      reg[r] = load_span_vec(XA, totA, ga, q);
-    else if (q < nva + nvb)
-      reg[r] = load_span_vec(XB, totB, gb, q - nva);
+    if constexpr (FULL) {
+      const bool in_a = q < p.nva || (q >= p.nva + p.nvb && p.nva > 0);
+      const int v = q < p.nva ? q : (q < p.nva + p.nvb ? q - p.nva : 0);
+      const X* src = in_a ? XA + (ga / V + (uint64_t)v) * V : XB + (gb / V + (uint64_t)v) * V;
+      reg[r] = __builtin_nontemporal_load((const vec16*)src);
+    } else {
+      if (q < p.nva)
+        reg[r] = load_span_vec(XA, totA, ga, q);
+      else if (q < p.nva + p.nvb)
+        reg[r] = load_span_vec(XB, totB, gb, q - p.nva);
+    }
   }
+}
+
+template <typename X, int NT, int R>
+__device__ __forceinline__ void write_pair_vec(X* dst, const PairSpan& p, const vec16 (&reg)[R]) {
+  constexpr int V = kPerVec<X>;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int q = (int)threadIdx.x + r * NT;
-    if (q < nva)
-      *(vec16*)(dst + q * V) = reg[r];
-    else if (q < nva + nvb)
-      *(vec16*)(dst + rb + (q - nva) * V) = reg[r];
+    if (q < p.nva + p.nvb) *(vec16*)(dst + (q < p.nva ? q * V : p.rb + (q - p.nva) * V)) = reg[r];
   }
 }
 
