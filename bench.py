@@ -624,6 +624,31 @@ def copy_ceiling(dev, reps=20):
     return 2 * (1 << 30) / (ms * 1e-3) / 1e9
 
 
+def tile_copy_ceiling(cfg, A, Av, B, Bv, reps=20):
+    """GB/s of cm_copy_tiles in tile configuration cfg on the step's arrays:
+    the block merge's own data movement (same windows-in-LDS tile structure,
+    same bytes) without the merge.  None where it does not apply (keys not
+    4 bytes wide, or a side's length not a multiple of 4)."""
+    import torch
+    import paper_1303_4312_amd as cm
+    if A.element_size() != 4 or A.numel() % 4 or B.numel() % 4:
+        return None
+    a, b = A.view(torch.uint32), B.view(torch.uint32)
+    C, Cv = cm.copy_tiles(cfg, a, Av, b, Bv)
+    cm.copy_tiles(cfg, a, Av, b, Bv, C, Cv)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        cm.copy_tiles(cfg, a, Av, b, Bv, C, Cv)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del C, Cv
+    torch.cuda.empty_cache()
+    return 2 * (A.numel() + B.numel()) * 8 / (ms * 1e-3) / 1e9
+
+
 def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.1),
                 seed=5000):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
@@ -883,6 +908,9 @@ def main():
     kernel = ("k_seg_merge_blocks" if segmented else
               "k_merge_stream" if streaming else "k_merge_blocks")
     traffic = None if streaming else read_traffic(args.workload, alg_bytes, nt, e)
+    tile_gbs = None if args.no_copy_ceiling else tile_copy_ceiling(cfg, A, Av, B, Bv)
+    if tile_gbs:
+        log(f"tile-structure copy ceiling ({nt}x{e}): {tile_gbs:.0f} GB/s")
     result = {
         "metric": METRIC,
         "value": value,
@@ -919,6 +947,8 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "box_copy_gbs": copy_gbs,
             "frac_of_box_copy": (achieved / copy_gbs) if copy_gbs else None,
+            "tile_copy_gbs": tile_gbs,
+            "frac_of_tile_copy": (achieved / tile_gbs) if tile_gbs else None,
             "kernel_ms_median": statistics.median(merge_each),
             "kernel_ms_min": min(merge_each),
         },

@@ -426,6 +426,27 @@ int cm_stable_merge_segmented_each(int key_type,
  *   overlap).  Every output may be NULL.  CM_EINVAL if timing is off.
  */
 int cm_copy(const void *src, void *dst, uint64_t bytes, hipStream_t stream);
+
+/*
+ * cm_copy_tiles(config, A, A_val, m, B, B_val, n, C, C_val, stream): the
+ *   data movement of a block merge of uint32 keys with uint32 payloads under
+ *   tile configuration `config` (T = threads x items outputs per workgroup,
+ *   as cm_config_info reports), without the merge (a measurement aid: the
+ *   speed of the merge's own traffic pattern).  Workgroup t stages two
+ *   windows of the inputs in LDS with 16-byte loads, waits at a barrier and
+ *   stores T outputs with 16-byte stores: counting in 16-byte units (4
+ *   elements), tile t covers units [q0, q1) = [t T/4, min((t+1) T/4, N/4))
+ *   of C and copies A units [j(q0), j(q1)) followed by B units [q0 - j(q0),
+ *   q1 - j(q1)), where j(q) = floor(q (m/4) / (N/4)) is A's share; the same
+ *   for the payloads into C_val.  Every tile thus reads exactly what it
+ *   writes, split between A and B in proportion m : n (Proposition 2's equal
+ *   blocks with linear windows instead of co-ranks).  Device arrays; every
+ *   base 16-byte aligned, m and n multiples of 4, m + n < 2^34, config in
+ *   [0, cm_config_count()) (else CM_EINVAL); C and C_val must not overlap an
+ *   input (CM_EALIAS).  m + n = 0 is a no-op.
+ */
+int cm_copy_tiles(int config, const void *A, const uint32_t *A_val, uint64_t m, const void *B,
+                  const uint32_t *B_val, uint64_t n, void *C, uint32_t *C_val, hipStream_t stream);
 int cm_timing_start(uint32_t capacity);
 int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_mean,
                    float *call_start_ms, float *call_ms, float *merge_ms);

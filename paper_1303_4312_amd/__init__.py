@@ -49,7 +49,7 @@ EXPORTS = [
     "cm_segmented_workspace_size", "cm_stable_merge_segmented", "cm_check_sorted",
     "cm_config_count", "cm_config_info", "cm_set_config", "cm_get_config",
     "cm_set_search", "cm_get_search", "cm_set_partition", "cm_get_partition",
-    "cm_stable_merge_segmented_each", "cm_copy", "cm_timing_start", "cm_timing_stop",
+    "cm_stable_merge_segmented_each", "cm_copy", "cm_copy_tiles", "cm_timing_start", "cm_timing_stop",
     "cm_autotune_merge", "cm_autotune_segmented", "cm_tuning_set", "cm_tuning_get",
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
@@ -115,6 +115,7 @@ def load():
         "cm_stable_merge_segmented_each": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
                                                    c_u64, vp, vp, vp, c_size, vp]),
         "cm_copy": (c_int, [vp, vp, c_u64, vp]),
+        "cm_copy_tiles": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp]),
         "cm_autotune_merge": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp, c_size,
                                       c_int, vp, ctypes.POINTER(c_int)]),
         "cm_autotune_segmented": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64, c_u64, vp,
@@ -401,6 +402,27 @@ def copy(src, dst, stream=None):
     if dst.numel() * dst.element_size() != nbytes:
         raise ValueError("src and dst differ in size")
     _check(load().cm_copy(_ptr(src), _ptr(dst), nbytes, _stream(stream, src.device)), "cm_copy")
+
+
+def copy_tiles(config, A, A_val, B, B_val, C=None, C_val=None, stream=None):
+    """The block merge's data movement in tile configuration `config`
+    without the merge (measurement helper): uint32 keys and payloads, tile t
+    copies A's and B's shares of its outputs, A's first (cm_copy_tiles).
+    Returns (C, C_val)."""
+    torch = _torch()
+    for t, name in ((A, "A"), (A_val, "A_val"), (B, "B"), (B_val, "B_val")):
+        _dev(t, name)
+        if t.dtype != torch.uint32:
+            raise TypeError(f"{name} must be uint32")
+    N = A.numel() + B.numel()
+    if C is None:
+        C = torch.empty(N, dtype=torch.uint32, device=A.device)
+    if C_val is None:
+        C_val = torch.empty(N, dtype=torch.uint32, device=A.device)
+    _check(load().cm_copy_tiles(int(config), _ptr(A), _ptr(A_val), A.numel(), _ptr(B), _ptr(B_val),
+                                B.numel(), _ptr(C), _ptr(C_val), _stream(stream, A.device)),
+           "cm_copy_tiles")
+    return C, C_val
 
 
 _timing_capacity = [0]

@@ -853,6 +853,20 @@ int cm_copy(const void* src, void* dst, uint64_t bytes, hipStream_t stream) {
   return launch_copy16(src, dst, bytes / 16, stream);
 }
 
+int cm_copy_tiles(int config, const void* A, const uint32_t* A_val, uint64_t m, const void* B, const uint32_t* B_val,
+                  uint64_t n, void* C, uint32_t* C_val, hipStream_t stream) {
+  if (config < 0 || config >= kNumCfgs) return CM_EINVAL;
+  if ((m % 4) || (n % 4) || m + n >= (1ull << 34)) return CM_EINVAL;
+  const uint64_t N = m + n;
+  if ((m && (!A || !A_val)) || (n && (!B || !B_val)) || (N && (!C || !C_val))) return CM_EINVAL;
+  for (const void* p : {A, (const void*)A_val, B, (const void*)B_val, (const void*)C, (const void*)C_val})
+    if ((uintptr_t)p % 16) return CM_EINVAL;
+  if (any_overlap({{C, N * 4}, {C_val, N * 4}}, {{A, m * 4}, {A_val, m * 4}, {B, n * 4}, {B_val, n * 4}}))
+    return CM_EALIAS;
+  if (N == 0) return CM_OK;
+  return launch_copy_tiles(config, g_set.shape.xcd_order, A, A_val, m, B, B_val, n, C, C_val, stream);
+}
+
 int cm_origin_codes(uint64_t m, uint64_t n, uint32_t* A_codes, uint32_t* B_codes, hipStream_t stream) {
   if ((m && !A_codes) || (n && !B_codes) || m >= (1ull << 31) || n >= (1ull << 31)) return CM_EINVAL;
   if (any_overlap({{A_codes, m * 4}, {B_codes, n * 4}}, {})) return CM_EALIAS;

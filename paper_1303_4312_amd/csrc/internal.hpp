@@ -135,5 +135,7 @@ int launch_check_sorted(int kt, const void* X, uint64_t len, uint32_t* flag, hip
 
 // Streaming copy of count16 16-byte vectors.
 int launch_copy16(const void* src, void* dst, uint64_t count16, hipStream_t st);
+int launch_copy_tiles(int cfg, int xcd, const void* A, const uint32_t* Av, uint64_t m, const void* B,
+                      const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, hipStream_t st);
 
 }  // namespace cm

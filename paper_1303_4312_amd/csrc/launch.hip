@@ -62,6 +62,54 @@ __global__ __launch_bounds__(256) void k_copy16(const u32x4* __restrict__ src, u
     __builtin_nontemporal_store(__builtin_nontemporal_load(src + x), dst + x);
 }
 
+// The data movement of a block merge (uint32 keys + uint32 payloads) in its
+// tile structure, without the merge: workgroup b takes tile t (XCD order as
+// the merge), stages the windows A[ja, jb) and B[q0 - ja, q1 - jb) (units of
+// 16 bytes; ja = floor(q0 * mq / Nq), the A share of the tile's first
+// output, exact) in LDS with 16-byte loads issued before the first LDS
+// write, waits at a barrier, and stores the tile with 16-byte stores, A's
+// window first.
+template <int NT, int E>
+__global__ __launch_bounds__(NT) void k_copy_tiles(const u32x4* __restrict__ A, const u32x4* __restrict__ Av,
+                                                   uint64_t mq, const u32x4* __restrict__ B,
+                                                   const u32x4* __restrict__ Bv, uint64_t nq, u32x4* __restrict__ C,
+                                                   u32x4* __restrict__ Cv, uint64_t tiles, int xcd) {
+  constexpr int TQ = NT * E / 4;  // 16-byte units per tile
+  constexpr int R = (TQ + NT - 1) / NT;
+  __shared__ u32x4 sk[TQ];
+  __shared__ u32x4 sv[TQ];
+  const uint64_t Nq = mq + nq;
+  const uint64_t t = block_order(blockIdx.x, tiles, xcd);
+  const uint64_t q0 = t * (uint64_t)TQ;
+  const uint64_t q1 = std::min(q0 + (uint64_t)TQ, Nq);
+  const uint64_t ja = q0 * mq / Nq, jb = q1 * mq / Nq;  // Nq < 2^32: no overflow
+  const int len = (int)(q1 - q0), na = (int)(jb - ja);
+  const uint64_t kb = q0 - ja;
+  u32x4 rk[R], rv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x0 = (int)threadIdx.x + r * NT;
+    const int x = x0 < len ? x0 : 0;  // a slot past the tile re-reads its first unit
+    const bool from_a = x < na;
+    const uint64_t g = from_a ? ja + (uint64_t)x : kb + (uint64_t)(x - na);
+    rk[r] = __builtin_nontemporal_load((from_a ? A : B) + g);
+    rv[r] = __builtin_nontemporal_load((from_a ? Av : Bv) + g);
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int x = (int)threadIdx.x + r * NT;
+    if (x < len) {
+      sk[x] = rk[r];
+      sv[x] = rv[r];
+    }
+  }
+  __syncthreads();
+  for (int x = (int)threadIdx.x; x < len; x += NT) {
+    __builtin_nontemporal_store(sk[x], C + q0 + x);
+    __builtin_nontemporal_store(sv[x], Cv + q0 + x);
+  }
+}
+
 // Puts the 2h cuts in output order (A's cut first on equal ranks, which are
 // the same cut) and closes with (m + n, m): I / J get 2h + 1 entries.
 __global__ __launch_bounds__(256) void k_cross_rank_place(const uint64_t* __restrict__ ia,
@@ -262,6 +310,19 @@ int launch_check_sorted(int kt, const void* X, uint64_t len, uint32_t* flag, hip
   if (rc != CM_OK || len < 2) return rc;
   const uint64_t blocks = std::min<uint64_t>((len + 255) / 256, 4096);
   return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::check_sorted(X, len, flag, blocks, st); });
+}
+
+int launch_copy_tiles(int cfg, int xcd, const void* A, const uint32_t* Av, uint64_t m, const void* B,
+                      const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, hipStream_t st) {
+  return by_cfg(cfg, [&](auto nt, auto e) -> int {
+    constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+    static_assert((NT * E) % 4 == 0, "tiles must hold whole 16-byte units");
+    const uint64_t TQ = NT * E / 4, Nq = (m + n) / 4, tiles = (Nq + TQ - 1) / TQ;
+    hipLaunchKernelGGL((k_copy_tiles<NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st, (const u32x4*)A,
+                       (const u32x4*)Av, m / 4, (const u32x4*)B, (const u32x4*)Bv, n / 4, (u32x4*)C, (u32x4*)Cv,
+                       tiles, xcd);
+    return launch_status();
+  });
 }
 
 int launch_copy16(const void* src, void* dst, uint64_t count16, hipStream_t st) {

@@ -388,3 +388,19 @@ def test_records_argument_errors():
     assert lib.cm_gather_records(P(0x1000), 10, P(0x2000), 5, P(0x3000), 5, 8, P(0x2000),
                                  None) == EALIAS
     assert lib.cm_gather_records(None, 0, None, 0, None, 0, 8, None, None) == OK
+
+
+def test_copy_tiles_argument_errors():
+    lib = cm.load()
+    P = ctypes.c_void_p
+    A, Av, B, Bv, C, Cv = (P(0x100000 * k) for k in range(1, 7))
+    assert lib.cm_copy_tiles(-1, A, Av, 16, B, Bv, 16, C, Cv, None) == EINVAL
+    assert lib.cm_copy_tiles(cm.config_count(), A, Av, 16, B, Bv, 16, C, Cv, None) == EINVAL
+    assert lib.cm_copy_tiles(0, A, Av, 18, B, Bv, 16, C, Cv, None) == EINVAL  # m % 4
+    assert lib.cm_copy_tiles(0, A, Av, 16, B, Bv, 14, C, Cv, None) == EINVAL  # n % 4
+    assert lib.cm_copy_tiles(0, P(0x100004), Av, 16, B, Bv, 16, C, Cv, None) == EINVAL
+    assert lib.cm_copy_tiles(0, None, Av, 16, B, Bv, 16, C, Cv, None) == EINVAL
+    assert lib.cm_copy_tiles(0, A, Av, 1 << 33, B, Bv, 1 << 33, C, Cv, None) == EINVAL
+    assert lib.cm_copy_tiles(0, A, Av, 16, B, Bv, 16, A, Cv, None) == EALIAS
+    assert lib.cm_copy_tiles(0, A, Av, 16, B, Bv, 16, C, C, None) == EALIAS
+    assert lib.cm_copy_tiles(0, None, None, 0, None, None, 0, None, None, None) == OK
