@@ -547,9 +547,10 @@ int cm_stable_sort_pairs(int key_type, const void *keys, const uint32_t *vals, u
  *   arena_bytes (>= 256; the caller keeps it alive until destroy; it must not
  *   overlap any request's inputs); max_batch in [1, 65536], max_inflight in
  *   [1, 16], max_requests in [1, 65535] (submitted and not yet released).
- *   Creates streams (default priority), events, pinned host descriptor
- *   buffers and per-batch device workspaces on the current device once;
- *   nothing is allocated afterwards.  CM_EINVAL / CM_EDTYPE / CM_EHIP.
+ *   Creates streams (default priority; one per batch in flight and two for
+ *   host requests' copies), events, pinned host descriptor buffers and
+ *   per-batch device workspaces on the current device once; nothing is
+ *   allocated afterwards.  CM_EINVAL / CM_EDTYPE / CM_EHIP.
  * cm_server_submit(server, A, A_val, m, B, B_val, n, inputs_stream,
  *   inputs_pending, &ticket): payload pointers all NULL iff the server has
  *   no payloads.  With inputs_pending set, the merge waits for the work
@@ -559,14 +560,31 @@ int cm_stable_sort_pairs(int key_type, const void *keys, const uint32_t *vals, u
  *   CM_ENOSPC (the outputs can never fit in the arena), CM_EBUSY (all
  *   max_requests slots are taken: poll and release, then retry),
  *   CM_ECANCELED (the server is shutting down).
+ * cm_server_submit_host(server, A, A_val, m, B, B_val, n, C, C_val,
+ *   &ticket): the same merge for data in host memory (pinned memory, from
+ *   hipHostMalloc, lets the copies overlap; pageable memory works but each
+ *   copy then blocks the scheduler thread while it is staged).  The request
+ *   is admitted when its outputs and its inputs both fit in the arena (the
+ *   inputs are staged there: keys of A and B, then their payloads); at
+ *   admission the runtime copies the inputs in on a copy stream of its own,
+ *   the batch waits for that copy, and after the batch the outputs are
+ *   copied to C (N keys) and C_val (N payloads) on a second copy stream.
+ *   The request is reported once its outputs are in C / C_val; until then
+ *   the caller keeps every host array alive, the inputs unchanged and the
+ *   outputs untouched.  Payload pointers all NULL iff the server has no
+ *   payloads.  CM_EINVAL (bad pointers or sizes), CM_EALIAS (C or C_val
+ *   overlaps an input or each other), CM_ENOSPC (inputs plus outputs can
+ *   never fit in the arena), CM_EBUSY, CM_ECANCELED as for submit.
  * cm_server_poll(server, done, capacity, &count, wait_us): moves up to
  *   `capacity` finished merges into done[] and sets count; waits up to
  *   wait_us microseconds for the first one if none is ready (0: do not
  *   wait).  Each entry: ticket; status (CM_OK, or the batch call's error, or
  *   CM_ECANCELED); C / C_val: the outputs (inside the arena; NULL for an
- *   empty merge); keys_offset / vals_offset: their byte offsets in the
- *   arena; queued_ns: submit to launch; latency_ns: submit to completion as
- *   seen by the scheduler.  Thread-safe.
+ *   empty merge; for a host request the caller's host arrays, the arena
+ *   copy staying at the offsets until release); keys_offset / vals_offset:
+ *   their byte offsets in the arena; queued_ns: submit to launch;
+ *   latency_ns: submit to completion as seen by the scheduler (for a host
+ *   request: outputs back in host memory).  Thread-safe.
  * cm_server_release(server, ticket): the client is done with a reported
  *   merge's outputs; its arena space and slot are reused.  CM_EINVAL for an
  *   unknown, unreported or already released ticket.
@@ -603,6 +621,9 @@ int cm_server_create(int key_type, int with_payload, void *arena, uint64_t arena
 int cm_server_submit(cm_server *server, const void *A, const uint32_t *A_val, uint64_t m,
                      const void *B, const uint32_t *B_val, uint64_t n, hipStream_t inputs_stream,
                      int inputs_pending, uint64_t *ticket);
+int cm_server_submit_host(cm_server *server, const void *A, const uint32_t *A_val, uint64_t m,
+                          const void *B, const uint32_t *B_val, uint64_t n, void *C,
+                          uint32_t *C_val, uint64_t *ticket);
 int cm_server_poll(cm_server *server, cm_server_done *done, uint32_t capacity, uint32_t *count,
                    int64_t wait_us);
 int cm_server_release(cm_server *server, uint64_t ticket);

@@ -55,7 +55,8 @@ EXPORTS = [
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
     "cm_set_coarse_stride", "cm_set_block_order", "cm_set_fine_lanes",
-    "cm_server_create", "cm_server_submit", "cm_server_poll", "cm_server_release",
+    "cm_server_create", "cm_server_submit", "cm_server_submit_host", "cm_server_poll",
+    "cm_server_release",
     "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_stable_sort",
     "cm_stable_sort_pairs", "cm_partition_ablation_workspace_size", "cm_merge_partition_ablation",
     "cm_origin_codes", "cm_gather_records",
@@ -141,6 +142,8 @@ def load():
                                      ctypes.c_uint32, ctypes.POINTER(vp)]),
         "cm_server_submit": (c_int, [vp, vp, vp, c_u64, vp, vp, c_u64, vp, c_int,
                                      ctypes.POINTER(c_u64)]),
+        "cm_server_submit_host": (c_int, [vp, vp, vp, c_u64, vp, vp, c_u64, vp, vp,
+                                          ctypes.POINTER(c_u64)]),
         "cm_server_poll": (c_int, [vp, vp, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint32),
                                    ctypes.c_int64]),
         "cm_server_release": (c_int, [vp, c_u64]),

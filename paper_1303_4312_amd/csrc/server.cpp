@@ -1,7 +1,8 @@
 // Serving runtime: admission against an output arena, one batched merge
 // launch per scheduler step, completion reporting.  The merge work itself is
 // cm_stable_merge_batch (Algorithm 2 over a batch of independent merges); this
-// file is scheduling only.
+// file is scheduling and, for requests whose data live in host memory, the
+// copies in and out on two copy streams of the runtime's own.
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <string.h>
@@ -35,9 +36,18 @@ struct Request {
   State state = kFree;
   cm_merge_desc d{};
   bool wait_ready = false;
-  hipEvent_t ready = nullptr;  // recorded on the client's stream at submit
-  uint64_t out_bytes = 0;      // arena bytes of the outputs (keys, then payloads)
+  hipEvent_t ready = nullptr;  // recorded on the client's stream at submit (host requests: on copy_in)
+  uint64_t out_bytes = 0;      // arena bytes held: outputs (keys, then payloads), then staged inputs
   uint64_t keys_off = 0, vals_off = 0;
+  // host request (cm_server_submit_host): inputs and outputs in host memory
+  bool host = false;
+  const void* hA = nullptr;
+  const uint32_t* hAv = nullptr;
+  const void* hB = nullptr;
+  const uint32_t* hBv = nullptr;
+  void* hC = nullptr;
+  uint32_t* hCv = nullptr;
+  int copy_status = CM_OK;  // enqueueing the copy in
   Clock::time_point t_submit, t_launch;
 };
 
@@ -52,6 +62,8 @@ struct Slot {  // one batch in flight
   int status = CM_OK;
   bool timed = false;  // start was recorded by this batch
   bool busy = false;
+  bool host_out = false;        // outputs of host requests are being copied out
+  hipEvent_t out_end = nullptr;  // recorded on copy_out after those copies
 };
 
 }  // namespace
@@ -63,6 +75,7 @@ struct cm_server {
   char* arena = nullptr;
   uint32_t max_batch = 0, max_inflight = 0, max_requests = 0;
   int device = 0;
+  hipStream_t copy_in = nullptr, copy_out = nullptr;  // host requests' copies
 
   std::mutex mu;
   std::condition_variable cv_sched, cv_done;
@@ -94,7 +107,10 @@ void destroy_resources(cm_server* s) {
     if (b.host) (void)hipHostFree(b.host);
     if (b.dev) (void)hipFree(b.dev);
     if (b.ws) (void)hipFree(b.ws);
+    if (b.out_end) (void)hipEventDestroy(b.out_end);
   }
+  if (s->copy_in) (void)hipStreamDestroy(s->copy_in);
+  if (s->copy_out) (void)hipStreamDestroy(s->copy_out);
   for (Request& r : s->reqs)
     if (r.ready) (void)hipEventDestroy(r.ready);
   if (s->ref) (void)hipEventDestroy(s->ref);
@@ -105,7 +121,36 @@ uint64_t out_bytes(const cm_server* s, uint64_t N) {
   return N ? round256(N * s->ks) + (s->val ? round256(N * 4) : 0) : 0;
 }
 
-// Admit pending requests in arrival order while their outputs fit (mu held).
+// Arena bytes a host request's inputs take when staged (keys of A and B,
+// then their payloads, each 256-byte aligned).
+uint64_t in_bytes(const cm_server* s, uint64_t m, uint64_t n) {
+  auto part = [](uint64_t b) { return b ? round256(b) : 0; };
+  return part(m * s->ks) + part(n * s->ks) + (s->val ? part(m * 4) + part(n * 4) : 0);
+}
+
+// Enqueue a host request's copy in to the arena at `base` on copy_in and
+// point its descriptor there; the merge waits for the copy (ready event).
+void stage_inputs(cm_server* s, Request& r, uint64_t base) {
+  char* p = s->arena + base;
+  auto put = [&](const void* src, uint64_t bytes) -> void* {
+    if (!bytes) return nullptr;
+    void* dst = p;
+    if (hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s->copy_in) != hipSuccess) r.copy_status = CM_EHIP;
+    p += round256(bytes);
+    return dst;
+  };
+  r.d.A = put(r.hA, r.d.m * s->ks);
+  r.d.B = put(r.hB, r.d.n * s->ks);
+  if (s->val) {
+    r.d.A_val = (const uint32_t*)put(r.hAv, r.d.m * 4);
+    r.d.B_val = (const uint32_t*)put(r.hBv, r.d.n * 4);
+  }
+  if (hipEventRecord(r.ready, s->copy_in) != hipSuccess) r.copy_status = CM_EHIP;
+  r.wait_ready = r.copy_status == CM_OK;
+}
+
+// Admit pending requests in arrival order while their outputs (and, for host
+// requests, their staged inputs) fit (mu held).
 void admit(cm_server* s) {
   while (!s->pending.empty()) {
     Request& r = s->reqs[s->pending.front()];
@@ -116,6 +161,7 @@ void admit(cm_server* s) {
     r.vals_off = s->val && N ? (uint64_t)off + round256(N * s->ks) : 0;
     r.d.C = N ? s->arena + r.keys_off : nullptr;
     r.d.C_val = s->val && N ? (uint32_t*)(s->arena + r.vals_off) : nullptr;
+    if (r.host && N) stage_inputs(s, r, (uint64_t)off + out_bytes(s, N));
     r.state = kAdmitted;
     s->admitted.push_back(s->pending.front());
     s->pending.pop_front();
@@ -139,6 +185,8 @@ void launch(cm_server* s, Slot& b) {
   uint64_t total = 0;
   int rc = cm_batch_prepare(s->kt, s->val ? 1 : 0, b.host, n, &total);
   for (uint32_t idx : b.reqs)
+    if (rc == CM_OK && s->reqs[idx].copy_status != CM_OK) rc = s->reqs[idx].copy_status;
+  for (uint32_t idx : b.reqs)
     if (rc == CM_OK && s->reqs[idx].wait_ready && hipStreamWaitEvent(b.stream, s->reqs[idx].ready, 0) != hipSuccess)
       rc = CM_EHIP;
   b.timed = false;
@@ -154,6 +202,24 @@ void launch(cm_server* s, Slot& b) {
   if (rc == CM_OK) rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, b.dev, n, total, b.ws, b.ws_bytes, b.stream);
   // the end event is recorded whatever happened, so completion is detected the same way
   if (hipEventRecord(b.end, b.stream) != hipSuccess && rc == CM_OK) rc = CM_EHIP;
+  // host requests: their outputs go back on copy_out once the batch has ended
+  b.host_out = false;
+  for (uint32_t idx : b.reqs) {
+    const Request& r = s->reqs[idx];
+    const uint64_t N = r.d.m + r.d.n;
+    if (!r.host || !N || rc != CM_OK) continue;
+    if (!b.host_out) {
+      if (hipStreamWaitEvent(s->copy_out, b.end, 0) != hipSuccess) rc = CM_EHIP;
+      b.host_out = true;
+    }
+    if (hipMemcpyAsync(r.hC, r.d.C, N * s->ks, hipMemcpyDeviceToHost, s->copy_out) != hipSuccess) rc = CM_EHIP;
+    if (s->val && hipMemcpyAsync(r.hCv, r.d.C_val, N * 4, hipMemcpyDeviceToHost, s->copy_out) != hipSuccess)
+      rc = CM_EHIP;
+  }
+  if (b.host_out && hipEventRecord(b.out_end, s->copy_out) != hipSuccess) {
+    rc = CM_EHIP;
+    b.host_out = false;  // complete on the batch's own end event
+  }
   b.status = rc;
   b.busy = true;
   s->st.batches += 1;
@@ -169,8 +235,8 @@ void finish(cm_server* s, Slot& b, int status) {
     cm_server_done e{};
     e.ticket = r.ticket;
     e.status = status;
-    e.C = r.d.C;
-    e.C_val = r.d.C_val;
+    e.C = r.host ? r.hC : r.d.C;
+    e.C_val = r.host ? r.hCv : r.d.C_val;
     e.keys_offset = r.keys_off;
     e.vals_offset = r.vals_off;
     e.queued_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r.t_launch - r.t_submit).count();
@@ -234,7 +300,8 @@ void scheduler(cm_server* s) {
     std::vector<Finished> finished;
     for (Slot& b : s->slots) {
       if (!b.busy) continue;
-      const hipError_t q = hipEventQuery(b.end);
+      // host requests are done once their outputs are back (after the batch's end)
+      const hipError_t q = hipEventQuery(b.host_out ? b.out_end : b.end);
       if (q == hipErrorNotReady) continue;
       Finished f{&b, b.status, false, 0.f, 0.f};
       if (q != hipSuccess && f.status == CM_OK) f.status = CM_EHIP;
@@ -286,6 +353,45 @@ double union_ms(std::vector<std::pair<float, float>> iv, double* span) {
 
 }  // namespace
 
+namespace {
+
+bool host_overlap(const void* a, uint64_t na, const void* b, uint64_t nb) {
+  if (!a || !b || !na || !nb) return false;
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  return x < y + nb && y < x + na;
+}
+
+// Queues request `idx` (filled in by the caller, which owns it until here).
+int queue_request(cm_server* s, uint32_t idx, uint64_t* ticket) {
+  Request& r = s->reqs[idx];
+  r.t_submit = Clock::now();
+  uint64_t t;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    t = r.ticket;
+    r.state = kPending;
+    s->pending.push_back(idx);
+    s->st.submitted += 1;
+  }
+  s->cv_sched.notify_one();
+  *ticket = t;
+  return CM_OK;
+}
+
+// Takes a free request slot and gives it a ticket (state stays kFree until queued).
+int take_slot(cm_server* s, uint32_t* idx) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop) return CM_ECANCELED;
+  if (s->free_slots.empty()) return CM_EBUSY;
+  *idx = s->free_slots.back();
+  s->free_slots.pop_back();
+  s->seq += 1;
+  s->reqs[*idx].ticket = (s->seq << 16) | *idx;
+  return CM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena_bytes, uint32_t max_batch,
@@ -321,9 +427,12 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
         hipEventCreate(&b.start) != hipSuccess || hipEventCreate(&b.end) != hipSuccess ||
         hipHostMalloc((void**)&b.host, (size_t)max_batch * sizeof(cm_merge_desc), hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&b.dev, (size_t)max_batch * sizeof(cm_merge_desc)) != hipSuccess ||
-        hipMalloc(&b.ws, b.ws_bytes) != hipSuccess)
+        hipMalloc(&b.ws, b.ws_bytes) != hipSuccess || hipEventCreate(&b.out_end) != hipSuccess)
       rc = CM_EHIP;
   }
+  if (rc == CM_OK && (hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking) != hipSuccess ||
+                      hipStreamCreateWithFlags(&s->copy_out, hipStreamNonBlocking) != hipSuccess))
+    rc = CM_EHIP;
   for (Request& r : s->reqs) {
     if (rc != CM_OK) break;
     if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess) rc = CM_EHIP;
@@ -341,6 +450,42 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
   return CM_OK;
 }
 
+
+int cm_server_submit_host(cm_server* s, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                          const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, uint64_t* ticket) {
+  if (!s || !ticket) return CM_EINVAL;
+  if (m + n < m) return CM_EINVAL;
+  const uint64_t N = m + n;
+  if ((m && !A) || (n && !B) || (N && !C)) return CM_EINVAL;
+  if (s->val ? ((m && !A_val) || (n && !B_val) || (N && !C_val)) : (A_val || B_val || C_val)) return CM_EINVAL;
+  const uint64_t kb = N * s->ks, vb = s->val ? N * 4 : 0;
+  for (const auto& in : {std::make_pair(A, m * s->ks), std::make_pair(B, n * s->ks),
+                         std::make_pair((const void*)A_val, s->val ? m * 4 : 0),
+                         std::make_pair((const void*)B_val, s->val ? n * 4 : 0)})
+    if (host_overlap(C, kb, in.first, in.second) || host_overlap(C_val, vb, in.first, in.second)) return CM_EALIAS;
+  if (host_overlap(C, kb, C_val, vb)) return CM_EALIAS;
+  const uint64_t bytes = out_bytes(s, N) + in_bytes(s, m, n);
+  if (bytes > s->ring.size()) return CM_ENOSPC;
+  uint32_t idx;
+  const int rc = take_slot(s, &idx);
+  if (rc != CM_OK) return rc;
+  Request& r = s->reqs[idx];
+  r.d = cm_merge_desc{};
+  r.d.m = m;
+  r.d.n = n;
+  r.out_bytes = bytes;
+  r.wait_ready = false;  // set when the copy in is enqueued at admission
+  r.host = true;
+  r.hA = A;
+  r.hAv = A_val;
+  r.hB = B;
+  r.hBv = B_val;
+  r.hC = C;
+  r.hCv = C_val;
+  r.copy_status = CM_OK;
+  return queue_request(s, idx, ticket);
+}
+
 int cm_server_submit(cm_server* s, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
                      const uint32_t* B_val, uint64_t n, hipStream_t inputs_stream, int inputs_pending,
                      uint64_t* ticket) {
@@ -352,15 +497,8 @@ int cm_server_submit(cm_server* s, const void* A, const uint32_t* A_val, uint64_
   const uint64_t bytes = out_bytes(s, N);
   if (bytes > s->ring.size()) return CM_ENOSPC;
   uint32_t idx;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stop) return CM_ECANCELED;
-    if (s->free_slots.empty()) return CM_EBUSY;
-    idx = s->free_slots.back();
-    s->free_slots.pop_back();
-    s->seq += 1;
-    s->reqs[idx].ticket = (s->seq << 16) | idx;  // state stays kFree until queued
-  }
+  const int rc = take_slot(s, &idx);
+  if (rc != CM_OK) return rc;
   Request& r = s->reqs[idx];  // only this thread touches it until it is queued
   r.d = cm_merge_desc{};
   r.d.A = A;
@@ -370,6 +508,8 @@ int cm_server_submit(cm_server* s, const void* A, const uint32_t* A_val, uint64_
   r.d.B_val = B_val;
   r.d.n = n;
   r.out_bytes = bytes;
+  r.host = false;
+  r.copy_status = CM_OK;
   r.wait_ready = inputs_pending != 0;
   if (r.wait_ready && hipEventRecord(r.ready, inputs_stream) != hipSuccess) {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -377,18 +517,7 @@ int cm_server_submit(cm_server* s, const void* A, const uint32_t* A_val, uint64_
     s->free_slots.push_back(idx);
     return CM_EHIP;
   }
-  r.t_submit = Clock::now();
-  uint64_t t;
-  {
-    std::lock_guard<std::mutex> lk(s->mu);
-    t = r.ticket;
-    r.state = kPending;
-    s->pending.push_back(idx);
-    s->st.submitted += 1;
-  }
-  s->cv_sched.notify_one();
-  *ticket = t;
-  return CM_OK;
+  return queue_request(s, idx, ticket);
 }
 
 int cm_server_poll(cm_server* s, cm_server_done* done, uint32_t capacity, uint32_t* count, int64_t wait_us) {

@@ -404,6 +404,7 @@ class NativeServer:
         self._check(rc, "cm_server_create")
         self._h = h
         self._ticket = ctypes.c_uint64()
+        self._host = {}  # ticket -> host tensors of a host request (kept alive until release)
         self._cap = 256
         self._done = (ServerDone * self._cap)()
         self._count = ctypes.c_uint32()
@@ -442,6 +443,51 @@ class NativeServer:
         self._check(rc, "cm_server_submit")
         return self.last_ticket
 
+    def submit_host(self, A, B, A_val=None, B_val=None, C=None, C_val=None):
+        """Queue a merge of host (CPU) tensors: the runtime copies the inputs
+        to its arena on a copy stream of its own, merges them in a batch and
+        copies the outputs back into C / C_val (pinned CPU tensors allocated
+        here unless given) on a second copy stream; the request is reported
+        by poll() once the outputs are in host memory.  Pinned inputs
+        (tensor.pin_memory()) let the copies overlap.  The tensors are kept
+        referenced here until release().  Returns the ticket; the outputs
+        are host_outputs(ticket)."""
+        torch = self.torch
+        ins = (A, B) + ((A_val, B_val) if self.with_payload else ())
+        for t in ins:
+            if t is None or not isinstance(t, torch.Tensor) or t.device.type != "cpu" \
+                    or t.dim() != 1 or not t.is_contiguous():
+                raise ValueError("inputs must be contiguous 1-D CPU tensors")
+        if A.dtype != self.key_dtype or B.dtype != self.key_dtype:
+            raise TypeError(f"keys must be {self.key_dtype}")
+        if not self.with_payload and (A_val is not None or B_val is not None):
+            raise ValueError("this server has no payloads")
+        N = A.numel() + B.numel()
+        if C is None:
+            C = torch.empty(N, dtype=self.key_dtype).pin_memory()
+        if self.with_payload and C_val is None:
+            C_val = torch.empty(N, dtype=torch.uint32).pin_memory()
+        outs = (C,) + ((C_val,) if self.with_payload else ())
+        for t in outs:
+            if t.device.type != "cpu" or not t.is_contiguous() or t.numel() != N:
+                raise ValueError("outputs must be contiguous CPU tensors of m + n elements")
+
+        def ptr(t):
+            return t.data_ptr() if t is not None and t.numel() else None
+        rc = self.lib.cm_server_submit_host(
+            self._h, ptr(A), ptr(A_val) if self.with_payload else None, A.numel(), ptr(B),
+            ptr(B_val) if self.with_payload else None, B.numel(), ptr(C),
+            ptr(C_val) if self.with_payload else None, ctypes.byref(self._ticket))
+        self._check(rc, "cm_server_submit_host")
+        t = self._ticket.value
+        self._host[t] = (ins, C, C_val)
+        return t
+
+    def host_outputs(self, ticket):
+        """The host output tensors of a host request: C, or (C, C_val)."""
+        _, C, C_val = self._host[ticket]
+        return (C, C_val) if self.with_payload else C
+
     def poll(self, wait_us=0):
         """Finished merges (cm_server_done entries), at most 256 per call."""
         self._check(self.lib.cm_server_poll(self._h, self._done, self._cap,
@@ -462,6 +508,7 @@ class NativeServer:
 
     def release(self, ticket):
         self._check(self.lib.cm_server_release(self._h, ticket), "cm_server_release")
+        self._host.pop(ticket, None)
 
     def stats(self) -> dict:
         st = ServerStats()

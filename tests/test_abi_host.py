@@ -299,6 +299,8 @@ def test_server_argument_errors():
     n = ctypes.c_uint32()
     assert lib.cm_server_submit(None, P(0x1000), P(0x2000), 4, P(0x3000), P(0x4000), 4, None, 0,
                                 ctypes.byref(t)) == EINVAL
+    assert lib.cm_server_submit_host(None, P(0x1000), P(0x2000), 4, P(0x3000), P(0x4000), 4,
+                                     P(0x5000), P(0x6000), ctypes.byref(t)) == EINVAL
     assert lib.cm_server_poll(None, None, 0, ctypes.byref(n), 0) == EINVAL
     assert lib.cm_server_release(None, 1) == EINVAL
     assert lib.cm_server_get_stats(None, None) == EINVAL

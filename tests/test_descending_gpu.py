@@ -114,20 +114,21 @@ def test_native_server_descending():
             A = desc_sorted(rng, int(rng.integers(0, 40_000)), np.float32, 300)
             B = desc_sorted(rng, int(rng.integers(0, 40_000)), np.float32, 300)
             Av, Bv = workloads.origin_payloads(A.size, B.size)
-            t = srv.submit(to_dev(A), to_dev(B), to_dev(Av), to_dev(Bv))
+            dev = [to_dev(x) for x in (A, B, Av, Bv)]  # kept alive until reported
+            t = srv.submit(*dev)
             tickets.append(t)
-            host[t] = (A, B, Av, Bv)
+            host[t] = (A, B, Av, Bv, dev)
         seen = {}
         t_end = time.time() + 60
         while len(seen) < len(tickets):
             assert time.time() < t_end
             for d in srv.poll(wait_us=2000):
                 assert d.status == 0
-                A, B, Av, Bv = host[d.ticket]
+                A, B, Av, Bv, _ = host[d.ticket]
                 C, Cv = srv.outputs(d, A.size + B.size)
                 seen[d.ticket] = (to_host(C), to_host(Cv))
                 srv.release(d.ticket)
     for t in tickets:
-        A, B, Av, Bv = host[t]
+        A, B, Av, Bv, _ = host[t]
         Ce, Cve = oracle.stable_merge(A, B, Av, Bv, descending=True)
         assert same_bits(seen[t][0], Ce) and same_bits(seen[t][1], Cve)

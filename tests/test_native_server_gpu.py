@@ -113,21 +113,22 @@ def test_native_server_keys_only_float():
                 A[:10] = -0.0
                 B[:10] = 0.0
                 A.sort(), B.sort()
-            t = srv.submit(to_dev(A), to_dev(B))
+            dA, dB = to_dev(A), to_dev(B)  # kept alive until the merge is reported
+            t = srv.submit(dA, dB)
             tickets.append(t)
-            host[t] = (A, B)
+            host[t] = (A, B, dA, dB)
         seen = {}
         t_end = time.time() + 60
         while len(seen) < len(tickets):
             assert time.time() < t_end
             for d in srv.poll(wait_us=2000):
                 assert d.status == 0
-                A, B = host[d.ticket]
+                A, B = host[d.ticket][:2]
                 seen[d.ticket] = to_host(srv.outputs(d, A.size + B.size))
                 srv.release(d.ticket)
         torch.cuda.synchronize()
     for t in tickets:
-        A, B = host[t]
+        A, B = host[t][:2]
         assert same_bits(seen[t], oracle.stable_merge(A, B))
 
 
@@ -155,3 +156,107 @@ def test_native_server_refuses_and_shuts_down_cleanly():
     t0 = time.time()
     srv.close()  # cancels them instead of waiting for space
     assert time.time() - t0 < 10
+
+
+def test_native_server_host_requests_match_alone_and_oracle():
+    """Requests whose data live in host memory (pinned and pageable), mixed
+    with device requests in one server whose arena holds about a third of
+    all inputs plus outputs: admission waits, the ring wraps, and every
+    host request's outputs come back to host memory equal to the merge run
+    alone."""
+    import torch
+    reqs = make_requests(36, seed=21, hi=1 << 16)
+    alone = []
+    for d in reqs:
+        C, Cv = cm.stable_merge_pairs(to_dev(d["A"]), to_dev(d["Av"]), to_dev(d["B"]), to_dev(d["Bv"]))
+        alone.append((to_host(C), to_host(Cv)))
+    total = sum(16 * (d["A"].size + d["B"].size) + 1024 for d in reqs)
+    srv = serve.NativeServer("uint32", True, arena_bytes=max(total // 3, 1 << 21), max_batch=8,
+                             max_inflight=2, max_requests=16)
+    kind, sizes, results, dev_inputs = {}, {}, {}, []
+
+    def collect(want):
+        t_end = time.time() + 60
+        while len(results) < want:
+            assert time.time() < t_end, "server did not finish in time"
+            for e in srv.poll(wait_us=2000):
+                assert e.status == 0, f"ticket {e.ticket}: status {e.status}"
+                k, N = kind[e.ticket], sizes[e.ticket]
+                if k == "host":
+                    C, Cv = srv.host_outputs(e.ticket)
+                    results[e.ticket] = (C.numpy().copy(), Cv.numpy().copy())
+                else:
+                    C, Cv = srv.outputs(e, N)
+                    results[e.ticket] = (to_host(C), to_host(Cv))
+                srv.release(e.ticket)
+
+    order = []
+    torch.cuda.synchronize()
+    for r, d in enumerate(reqs):
+        host = r % 3 != 2
+        while True:
+            try:
+                if host:
+                    ts = [torch.from_numpy(d[k]) for k in ("A", "B", "Av", "Bv")]
+                    if r % 2 == 0:
+                        ts = [t.pin_memory() for t in ts]
+                    t = srv.submit_host(ts[0], ts[1], ts[2], ts[3])
+                else:
+                    dv = [to_dev(d[k]) for k in ("A", "B", "Av", "Bv")]
+                    dev_inputs.append(dv)
+                    torch.cuda.synchronize()
+                    t = srv.submit(dv[0], dv[1], dv[2], dv[3])
+                break
+            except cm.CMError as exc:
+                assert exc.status == -9
+                collect(len(results) + 1)
+        kind[t] = "host" if host else "device"
+        sizes[t] = d["A"].size + d["B"].size
+        order.append(t)
+    collect(len(order))
+    st = srv.stats()
+    srv.close()
+    for r, t in enumerate(order):
+        C, Cv = results[t]
+        assert same_bits(C, alone[r][0]) and same_bits(Cv, alone[r][1]), f"request {r} ({kind[t]})"
+    for d, t in list(zip(reqs, order))[:6]:
+        Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        assert same_bits(results[t][0], Ce) and same_bits(results[t][1], Cve)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    assert st["arena_peak_bytes"] <= st["arena_bytes"]
+
+
+def test_native_server_host_request_errors():
+    import ctypes
+    import torch
+    srv = serve.NativeServer("uint32", True, arena_bytes=1 << 21, max_batch=4, max_inflight=1,
+                             max_requests=4)
+    lib, t = srv.lib, ctypes.c_uint64()
+    A = torch.zeros(1024, dtype=torch.uint32).pin_memory()
+    B = torch.zeros(1024, dtype=torch.uint32).pin_memory()
+    C = torch.zeros(2048, dtype=torch.uint32).pin_memory()
+    Cv = torch.zeros(2048, dtype=torch.uint32).pin_memory()
+    p = lambda x: x.data_ptr()
+    # outputs over an input, outputs over each other, missing outputs
+    assert lib.cm_server_submit_host(srv._h, p(A), p(A), 1024, p(B), p(B), 1024, p(A), p(Cv),
+                                     ctypes.byref(t)) == -4
+    assert lib.cm_server_submit_host(srv._h, p(A), p(A), 1024, p(B), p(B), 1024, p(C), p(C),
+                                     ctypes.byref(t)) == -4
+    assert lib.cm_server_submit_host(srv._h, p(A), p(A), 1024, p(B), p(B), 1024, None, p(Cv),
+                                     ctypes.byref(t)) == -1
+    # inputs plus outputs larger than the arena (made-up, disjoint addresses:
+    # the call refuses before touching them)
+    big, G = 1 << 17, 1 << 32
+    assert lib.cm_server_submit_host(srv._h, G, 2 * G, big, 3 * G, 4 * G, big, 5 * G, 6 * G,
+                                     ctypes.byref(t)) == -5
+    # an empty host request completes
+    e = torch.zeros(0, dtype=torch.uint32)
+    tk = srv.submit_host(e, e, e, e)
+    done = []
+    t_end = time.time() + 20
+    while not done:
+        assert time.time() < t_end
+        done = srv.poll(wait_us=2000)
+    assert done[0].ticket == tk and done[0].status == 0
+    srv.release(tk)
+    srv.close()
