@@ -430,19 +430,21 @@ def pcie_ceiling(nbytes=256 << 20, reps=10):
             "both_ways_gbs": run(True, True), "bytes_per_copy": nbytes}
 
 
-def host_ingress_leg(pool_size=16, count=400, slots=8, seed=5000):
-    """Serving with requests in host memory (beside the device-resident leg):
-    each request's inputs wait in pinned host memory, are copied to one of
-    `slots` device staging areas on a copy stream, merged by the library's
-    serving runtime (which waits for that copy: inputs_pending), and its
-    outputs are copied back to pinned host memory on a second copy stream.
-    A request is done once its outputs are on the host; then its ticket and
-    staging slot are freed.  Closed loop (a new request enters as soon as a
-    slot is free): requests/s, keys/s and PCIe bytes per second (both ways
-    together) against the box's plain pinned-copy rates; latency from entering
-    a slot to outputs on the host.  A first pass over the pool (also the
-    warm-up) checks every request's host outputs against the same merge run
-    alone on the device, byte for byte."""
+def host_ingress_leg(pool_size=16, count=400, slots=16, seed=5000):
+    """Serving with requests in host memory (beside the device-resident leg),
+    two ways.  The runtime's own host ingress (cm_server_submit_host, the
+    reported figures): each request's inputs wait in pinned host memory, the
+    runtime stages them in its arena over a copy stream, merges, and copies
+    the outputs back into pinned host buffers over a second copy stream.
+    And a client-side copy loop (client_copy_loop): the client copies the
+    inputs to one of `slots` device staging areas on its own stream and
+    submits them with inputs_pending, then copies the outputs back itself.
+    A request is done once its outputs are on the host.  Closed loop with
+    `slots` requests in flight: requests/s, keys/s and PCIe bytes per second
+    (both ways together) against the box's plain pinned-copy rates; latency
+    from entering to outputs on the host.  A first pass over the pool (also
+    the warm-up) checks every request's host outputs against the same merge
+    run alone, byte for byte."""
     import numpy as np
     import torch
     import paper_1303_4312_amd as cm
@@ -534,19 +536,76 @@ def host_ingress_leg(pool_size=16, count=400, slots=8, seed=5000):
                 "p99_ms": pick(0.99) * 1e3}
 
     run(pool_size, check=True)
-    res = run(count, check=False)
+    loop = run(count, check=False)
     srv.close()
-    del stage, back
+    del stage
+
+    # the runtime's own host ingress (cm_server_submit_host): it stages the
+    # inputs in its arena and copies both ways on its own copy streams
+    nsrv = serve.NativeServer("uint32", True, arena_bytes=20 * cap * slots, max_batch=64,
+                              max_inflight=2, max_requests=slots, device=dev)
+
+    def run_native(count, check):
+        free = list(range(slots))
+        info = {}  # ticket -> (request, slot, outputs, entered)
+        lat, done, sub, outputs, moved = [], 0, 0, 0, 0
+        t0 = time.perf_counter()
+        while done < count:
+            while sub < count and free:
+                slot = free.pop()
+                A, B, Av, Bv = pool[sub % pool_size]
+                N = A.numel() + B.numel()
+                hk, hv = back[slot]
+                entered = time.perf_counter()
+                t = nsrv.submit_host(A, B, Av, Bv, hk[:N], hv[:N])
+                info[t] = (sub, slot, N, entered)
+                moved += 8 * N
+                sub += 1
+            for d in nsrv.poll(wait_us=200):
+                if d.status != 0:
+                    raise cm.CMError(d.status, "serving request")
+                req, slot, n_out, entered = info.pop(d.ticket)
+                lat.append(time.perf_counter() - entered)
+                if check:
+                    Ce, Cve = alone[req % pool_size]
+                    hk, hv = back[slot]
+                    if not (np.array_equal(hk[:n_out].numpy(), Ce)
+                            and np.array_equal(hv[:n_out].numpy(), Cve)):
+                        raise AssertionError(f"host request {req}: outputs differ from the "
+                                             "merge run alone")
+                nsrv.release(d.ticket)
+                free.append(slot)
+                outputs += n_out
+                moved += 8 * n_out
+                done += 1
+        wall = time.perf_counter() - t0
+        lat.sort()
+
+        def pick(q):
+            return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+        return {"requests_per_s": count / wall, "keys_per_s": outputs / wall,
+                "pcie_bytes_per_s": moved / wall, "p50_ms": pick(0.5) * 1e3,
+                "p99_ms": pick(0.99) * 1e3}
+
+    run_native(pool_size, check=True)
+    res = run_native(count, check=False)
+    nsrv.close()
+    del back
     ceiling = pcie_ceiling()
+    loop["frac_of_pcie_both_ways"] = loop["pcie_bytes_per_s"] / 1e9 / ceiling["both_ways_gbs"]
+    loop["note"] = ("the client copies in and out on two streams of its own around "
+                    "cm_server_submit with inputs_pending")
     res.update({
         "workload": ("the serving requests (sides log-uniform in [2^10, 2^24], uint32 key + "
-                     "payload) held in pinned host memory; inputs copied in and outputs "
-                     "copied out on two copy streams"),
+                     "payload) held in pinned host memory"),
+        "runtime": ("cm_server_submit_host: the runtime stages inputs in its arena over one "
+                    "copy stream and returns outputs over a second"),
         "requests": count,
-        "staging_slots": slots,
+        "requests_in_flight": slots,
         "alone_vs_mix_checked": pool_size,
         "pcie_ceiling": ceiling,
         "frac_of_pcie_both_ways": res["pcie_bytes_per_s"] / 1e9 / ceiling["both_ways_gbs"],
+        "client_copy_loop": loop,
     })
     return res
 
@@ -1015,7 +1074,8 @@ def main():
         log(f"serving (host ingress): {hi['requests_per_s']:.0f} req/s, "
             f"{hi['pcie_bytes_per_s'] / 1e9:.1f} GB/s over PCIe "
             f"({hi['frac_of_pcie_both_ways']:.2f} of plain pinned copies both ways, "
-            f"{hi['pcie_ceiling']['both_ways_gbs']:.1f} GB/s), p50 {hi['p50_ms']:.2f} ms")
+            f"{hi['pcie_ceiling']['both_ways_gbs']:.1f} GB/s), p50 {hi['p50_ms']:.2f} ms; "
+            f"client copy loop {hi['client_copy_loop']['requests_per_s']:.0f} req/s")
 
     print(json.dumps(result), flush=True)
 

@@ -534,11 +534,13 @@ int cm_stable_sort_pairs(int key_type, const void *keys, const uint32_t *vals, u
 /*
  * Serving runtime (not part of the method; it feeds the batch call above).
  * A server owns a scheduler thread.  Clients submit single merges (device
- * inputs, sizes); the scheduler admits them in arrival order while their
- * outputs fit in an output arena in HBM (the caller's device buffer), packs
- * the admitted ones into one cm_stable_merge_batch launch per step (at most
- * max_batch merges; at most max_inflight batches in flight, each on its own
- * stream), and reports each finished merge once.  A finished merge's outputs
+ * inputs, sizes; or host data, see cm_server_submit_host); the scheduler
+ * admits them in arrival order while their outputs fit in an output arena in
+ * HBM (the caller's device buffer), packs the admitted ones whose inputs are
+ * in place (the producer's work, or the runtime's copy in, has completed)
+ * into one cm_stable_merge_batch launch per step (at most max_batch merges;
+ * at most max_inflight batches in flight, each on its own stream), and
+ * reports each finished merge once.  A finished merge's outputs
  * stay in the arena until the client releases its ticket.  Results are
  * those of cm_stable_merge_pairs / cm_stable_merge on the same inputs.
  *

@@ -47,7 +47,9 @@ struct Request {
   const uint32_t* hBv = nullptr;
   void* hC = nullptr;
   uint32_t* hCv = nullptr;
-  int copy_status = CM_OK;  // enqueueing the copy in
+  int copy_status = CM_OK;        // enqueueing the copy in
+  bool out_pending = false;       // outputs being copied back (done when out_done is)
+  hipEvent_t out_done = nullptr;  // recorded on copy_out after this request's copies
   Clock::time_point t_submit, t_launch;
 };
 
@@ -62,8 +64,6 @@ struct Slot {  // one batch in flight
   int status = CM_OK;
   bool timed = false;  // start was recorded by this batch
   bool busy = false;
-  bool host_out = false;        // outputs of host requests are being copied out
-  hipEvent_t out_end = nullptr;  // recorded on copy_out after those copies
 };
 
 }  // namespace
@@ -91,6 +91,7 @@ struct cm_server {
   // scheduler thread only
   std::deque<uint32_t> admitted;
   std::vector<Slot> slots;
+  std::vector<uint32_t> outgoing;  // host requests whose outputs are on their way back
   hipEvent_t ref = nullptr;  // time origin of the busy intervals
   std::vector<std::pair<float, float>> intervals;
 
@@ -107,12 +108,13 @@ void destroy_resources(cm_server* s) {
     if (b.host) (void)hipHostFree(b.host);
     if (b.dev) (void)hipFree(b.dev);
     if (b.ws) (void)hipFree(b.ws);
-    if (b.out_end) (void)hipEventDestroy(b.out_end);
   }
   if (s->copy_in) (void)hipStreamDestroy(s->copy_in);
   if (s->copy_out) (void)hipStreamDestroy(s->copy_out);
-  for (Request& r : s->reqs)
+  for (Request& r : s->reqs) {
     if (r.ready) (void)hipEventDestroy(r.ready);
+    if (r.out_done) (void)hipEventDestroy(r.out_done);
+  }
   if (s->ref) (void)hipEventDestroy(s->ref);
 }
 
@@ -169,19 +171,32 @@ void admit(cm_server* s) {
   }
 }
 
-// Launch up to max_batch admitted requests on slot b (scheduler thread).
-void launch(cm_server* s, Slot& b) {
-  const uint32_t n = (uint32_t)std::min<size_t>(s->max_batch, s->admitted.size());
+// Inputs in place: no producer to wait for, or its work (the client's, or
+// the runtime's copy in) has completed.
+bool inputs_ready(const Request& r) {
+  return !r.wait_ready || hipEventQuery(r.ready) != hipErrorNotReady;
+}
+
+// Launch up to max_batch admitted requests whose inputs are in place, in
+// admission order, on slot b (scheduler thread); requests still waiting
+// for their inputs stay admitted, so a batch never holds a slot while it
+// waits for a copy.  Returns the number launched.
+uint32_t launch(cm_server* s, Slot& b) {
   b.reqs.clear();
   const Clock::time_point now = Clock::now();
-  for (uint32_t k = 0; k < n; ++k) {
-    const uint32_t idx = s->admitted.front();
-    s->admitted.pop_front();
-    Request& r = s->reqs[idx];  // stays kAdmitted (not releasable) until reported
+  uint32_t n = 0;
+  for (auto it = s->admitted.begin(); it != s->admitted.end() && n < s->max_batch;) {
+    Request& r = s->reqs[*it];  // stays kAdmitted (not releasable) until reported
+    if (!inputs_ready(r)) {
+      ++it;
+      continue;
+    }
     r.t_launch = now;
-    b.host[k] = r.d;
-    b.reqs.push_back(idx);
+    b.host[n++] = r.d;
+    b.reqs.push_back(*it);
+    it = s->admitted.erase(it);
   }
+  if (n == 0) return 0;
   uint64_t total = 0;
   int rc = cm_batch_prepare(s->kt, s->val ? 1 : 0, b.host, n, &total);
   for (uint32_t idx : b.reqs)
@@ -202,34 +217,37 @@ void launch(cm_server* s, Slot& b) {
   if (rc == CM_OK) rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, b.dev, n, total, b.ws, b.ws_bytes, b.stream);
   // the end event is recorded whatever happened, so completion is detected the same way
   if (hipEventRecord(b.end, b.stream) != hipSuccess && rc == CM_OK) rc = CM_EHIP;
-  // host requests: their outputs go back on copy_out once the batch has ended
-  b.host_out = false;
+  // host requests: their outputs go back on copy_out once the batch has
+  // ended; each is reported when its own copies are done, and the slot is
+  // free again at the batch's end
+  bool waited = false;
   for (uint32_t idx : b.reqs) {
-    const Request& r = s->reqs[idx];
+    Request& r = s->reqs[idx];
+    r.out_pending = false;
     const uint64_t N = r.d.m + r.d.n;
     if (!r.host || !N || rc != CM_OK) continue;
-    if (!b.host_out) {
-      if (hipStreamWaitEvent(s->copy_out, b.end, 0) != hipSuccess) rc = CM_EHIP;
-      b.host_out = true;
-    }
-    if (hipMemcpyAsync(r.hC, r.d.C, N * s->ks, hipMemcpyDeviceToHost, s->copy_out) != hipSuccess) rc = CM_EHIP;
-    if (s->val && hipMemcpyAsync(r.hCv, r.d.C_val, N * 4, hipMemcpyDeviceToHost, s->copy_out) != hipSuccess)
+    if (!waited && hipStreamWaitEvent(s->copy_out, b.end, 0) != hipSuccess) rc = CM_EHIP;
+    waited = true;
+    if (rc == CM_OK && hipMemcpyAsync(r.hC, r.d.C, N * s->ks, hipMemcpyDeviceToHost, s->copy_out) != hipSuccess)
       rc = CM_EHIP;
+    if (rc == CM_OK && s->val &&
+        hipMemcpyAsync(r.hCv, r.d.C_val, N * 4, hipMemcpyDeviceToHost, s->copy_out) != hipSuccess)
+      rc = CM_EHIP;
+    if (rc == CM_OK && hipEventRecord(r.out_done, s->copy_out) != hipSuccess) rc = CM_EHIP;
+    r.out_pending = rc == CM_OK;
   }
-  if (b.host_out && hipEventRecord(b.out_end, s->copy_out) != hipSuccess) {
-    rc = CM_EHIP;
-    b.host_out = false;  // complete on the batch's own end event
-  }
+  if (rc != CM_OK)
+    for (uint32_t idx : b.reqs) s->reqs[idx].out_pending = false;  // reported with the error at the end
   b.status = rc;
   b.busy = true;
   s->st.batches += 1;
   s->st.max_batch_seen = std::max<uint64_t>(s->st.max_batch_seen, n);
+  return n;
 }
 
-// Report the requests of a finished slot (mu held).
-void finish(cm_server* s, Slot& b, int status) {
-  const Clock::time_point now = Clock::now();
-  for (uint32_t idx : b.reqs) {
+// Report one finished request (mu held).
+void finish_request(cm_server* s, uint32_t idx, int status, Clock::time_point now) {
+  {
     Request& r = s->reqs[idx];
     r.state = kDone;
     cm_server_done e{};
@@ -246,6 +264,18 @@ void finish(cm_server* s, Slot& b, int status) {
       s->st.completed += 1;
     else
       s->st.failed += 1;
+  }
+}
+
+// A slot's batch has ended (mu held): report its requests, except host
+// requests whose outputs are still on their way back, and free the slot.
+void finish(cm_server* s, Slot& b, int status) {
+  const Clock::time_point now = Clock::now();
+  for (uint32_t idx : b.reqs) {
+    if (status == CM_OK && s->reqs[idx].out_pending)
+      s->outgoing.push_back(idx);
+    else
+      finish_request(s, idx, status, now);
   }
   b.reqs.clear();
   b.busy = false;
@@ -274,7 +304,7 @@ void scheduler(cm_server* s) {
   std::unique_lock<std::mutex> lk(s->mu);
   for (;;) {
     admit(s);
-    int inflight = 0;
+    int inflight = s->outgoing.empty() ? 0 : 1;
     for (const Slot& b : s->slots) inflight += b.busy ? 1 : 0;
     if (s->stop && s->admitted.empty() && inflight == 0) {
       if (s->pending.empty()) break;
@@ -286,10 +316,7 @@ void scheduler(cm_server* s) {
     bool progressed = false;
     for (Slot& b : s->slots) {
       if (s->admitted.empty()) break;
-      if (!b.busy) {
-        launch(s, b);
-        progressed = true;
-      }
+      if (!b.busy && launch(s, b) > 0) progressed = true;
     }
     struct Finished {
       Slot* b;
@@ -300,8 +327,7 @@ void scheduler(cm_server* s) {
     std::vector<Finished> finished;
     for (Slot& b : s->slots) {
       if (!b.busy) continue;
-      // host requests are done once their outputs are back (after the batch's end)
-      const hipError_t q = hipEventQuery(b.host_out ? b.out_end : b.end);
+      const hipError_t q = hipEventQuery(b.end);
       if (q == hipErrorNotReady) continue;
       Finished f{&b, b.status, false, 0.f, 0.f};
       if (q != hipSuccess && f.status == CM_OK) f.status = CM_EHIP;
@@ -309,17 +335,32 @@ void scheduler(cm_server* s) {
                 hipEventElapsedTime(&f.t1, s->ref, b.end) == hipSuccess;
       finished.push_back(f);
     }
+    // host requests whose outputs were on their way back (scheduler-owned list)
+    std::vector<std::pair<uint32_t, int>> back;
+    for (size_t k = 0; k < s->outgoing.size();) {
+      const hipError_t q = hipEventQuery(s->reqs[s->outgoing[k]].out_done);
+      if (q == hipErrorNotReady) {
+        ++k;
+        continue;
+      }
+      back.emplace_back(s->outgoing[k], q == hipSuccess ? CM_OK : CM_EHIP);
+      s->outgoing[k] = s->outgoing.back();
+      s->outgoing.pop_back();
+    }
     lk.lock();
     for (const Finished& f : finished) {
       if (f.timed) s->intervals.emplace_back(f.t0, f.t1);
       finish(s, *f.b, f.status);
     }
-    if (!finished.empty()) {
+    const Clock::time_point now = Clock::now();
+    for (const auto& rb : back) finish_request(s, rb.first, rb.second, now);
+    if (!finished.empty() || !back.empty()) {
       progressed = true;
       s->cv_done.notify_all();
     }
     if (!progressed) {
-      bool any_busy = false;
+      // admitted requests still waiting for their inputs count as work in flight
+      bool any_busy = !s->outgoing.empty() || !s->admitted.empty();
       for (const Slot& b : s->slots) any_busy = any_busy || b.busy;
       // poll in-flight batches every 20 us; otherwise sleep until woken
       if (any_busy)
@@ -427,7 +468,7 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
         hipEventCreate(&b.start) != hipSuccess || hipEventCreate(&b.end) != hipSuccess ||
         hipHostMalloc((void**)&b.host, (size_t)max_batch * sizeof(cm_merge_desc), hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&b.dev, (size_t)max_batch * sizeof(cm_merge_desc)) != hipSuccess ||
-        hipMalloc(&b.ws, b.ws_bytes) != hipSuccess || hipEventCreate(&b.out_end) != hipSuccess)
+        hipMalloc(&b.ws, b.ws_bytes) != hipSuccess)
       rc = CM_EHIP;
   }
   if (rc == CM_OK && (hipStreamCreateWithFlags(&s->copy_in, hipStreamNonBlocking) != hipSuccess ||
@@ -435,7 +476,9 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
     rc = CM_EHIP;
   for (Request& r : s->reqs) {
     if (rc != CM_OK) break;
-    if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess) rc = CM_EHIP;
+    if (hipEventCreateWithFlags(&r.ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&r.out_done, hipEventDisableTiming) != hipSuccess)
+      rc = CM_EHIP;
   }
   if (rc == CM_OK && (hipEventCreate(&s->ref) != hipSuccess || hipEventRecord(s->ref, s->slots[0].stream) != hipSuccess ||
                       hipEventSynchronize(s->ref) != hipSuccess))
