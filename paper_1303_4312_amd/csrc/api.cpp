@@ -25,6 +25,7 @@ namespace {
 
 struct Settings {
   int cfg[CM_KEY_F32_DESC + 1][2] = {};       // [key type][payload] default configuration (0)
+  bool cfg_set[CM_KEY_F32_DESC + 1][2] = {};  // set by the caller (else sorts of 4-byte keys use kSortCfg)
   int search = 1;                             // bisection
   int partition = -1;                         // automatic (see resolve)
   Shape shape;                                // coarse stride, block order
@@ -43,6 +44,10 @@ std::mutex g_tuning_mu;
 
 int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
 
+// Default tile of a merge sort of 4-byte keys (256 x 9: fewest passes for
+// its speed; measured fastest of the eight at 2^26 and 2^28 uint32 keys).
+constexpr int kSortCfg = 6;
+
 Choice resolve(int op, int kt, bool val, uint64_t N) {
   {
     std::lock_guard<std::mutex> lk(g_tuning_mu);
@@ -52,7 +57,9 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
   int part = g_set.partition;
   if (part < 0)  // automatic: below 2^22 outputs a single merge skips the boundary pass
     part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
-  return Choice{g_set.cfg[kt][val ? 1 : 0], g_set.search, part};
+  int cfg = g_set.cfg[kt][val ? 1 : 0];
+  if (op == kOpSort && !g_set.cfg_set[kt][val ? 1 : 0] && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = kSortCfg;
+  return Choice{cfg, g_set.search, part};
 }
 
 // ---------------------------------------------------------------------------
@@ -525,6 +532,7 @@ int cm_set_config(int key_type, int with_payload, int config_id) {
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
   g_set.cfg[key_type][with_payload ? 1 : 0] = config_id;
+  g_set.cfg_set[key_type][with_payload ? 1 : 0] = true;
   return CM_OK;
 }
 

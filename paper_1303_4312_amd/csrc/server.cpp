@@ -149,6 +149,9 @@ void stage_inputs(cm_server* s, Request& r, uint64_t base) {
   }
   if (hipEventRecord(r.ready, s->copy_in) != hipSuccess) r.copy_status = CM_EHIP;
   r.wait_ready = r.copy_status == CM_OK;
+  // on a failure, copies already enqueued must not outlive the report (the
+  // client may free its host arrays once the request is reported)
+  if (r.copy_status != CM_OK) (void)hipStreamSynchronize(s->copy_in);
 }
 
 // Admit pending requests in arrival order while their outputs (and, for host
@@ -236,8 +239,12 @@ uint32_t launch(cm_server* s, Slot& b) {
     if (rc == CM_OK && hipEventRecord(r.out_done, s->copy_out) != hipSuccess) rc = CM_EHIP;
     r.out_pending = rc == CM_OK;
   }
-  if (rc != CM_OK)
-    for (uint32_t idx : b.reqs) s->reqs[idx].out_pending = false;  // reported with the error at the end
+  if (rc != CM_OK) {
+    // reported with the error at the batch's end; copies already enqueued
+    // must finish before that (the client may then free its host arrays)
+    if (waited) (void)hipStreamSynchronize(s->copy_out);
+    for (uint32_t idx : b.reqs) s->reqs[idx].out_pending = false;
+  }
   b.status = rc;
   b.busy = true;
   s->st.batches += 1;
