@@ -35,92 +35,92 @@ inline uint32_t resident_blocks(const void* kernel, int nt, int* cache) {
 template <typename K>
 int Launch<K>::block_co_ranks(const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B, uint64_t n,
                               uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
-    const uint64_t blocks = (nb + 255) / 256;
-    if (ch.partition == 0) {
-      hipLaunchKernelGGL((k_block_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
-                         (const K*)B, n, tile, nb, bj, ch.search);
-      return launch_status();
-    }
-    const uint32_t G = sh.coarse_stride;
-    const uint64_t nc = num_coarse(nb, G);
-    if (ch.partition == 1)
-      hipLaunchKernelGGL((k_coarse_co_rank<K, 64>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st,
-                         (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
-    else
-      hipLaunchKernelGGL((k_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st,
-                         (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
-    if (launch_status() != CM_OK) return CM_EHIP;
-    if (sh.fine_lanes == 2 || sh.fine_lanes == 4) {
-      const uint64_t lanes = nb * (uint64_t)sh.fine_lanes;
-      if (sh.fine_lanes == 2)
-        hipLaunchKernelGGL((k_fine_co_rank_group<K, 2>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st,
-                           (const K*)A, m, (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
-      else
-        hipLaunchKernelGGL((k_fine_co_rank_group<K, 4>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st,
-                           (const K*)A, m, (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
-    } else {
-      hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
-                         (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
-    }
+  const uint64_t blocks = (nb + 255) / 256;
+  if (ch.partition == 0) {
+    hipLaunchKernelGGL((k_block_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
+                       (const K*)B, n, tile, nb, bj, ch.search);
     return launch_status();
+  }
+  const uint32_t G = sh.coarse_stride;
+  const uint64_t nc = num_coarse(nb, G);
+  if (ch.partition == 1)
+    hipLaunchKernelGGL((k_coarse_co_rank<K, 64>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st,
+                       (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
+  else
+    hipLaunchKernelGGL((k_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st,
+                       (const K*)A, m, (const K*)B, n, tile * G, nc, coarse);
+  if (launch_status() != CM_OK) return CM_EHIP;
+  if (sh.fine_lanes == 2 || sh.fine_lanes == 4) {
+    const uint64_t lanes = nb * (uint64_t)sh.fine_lanes;
+    if (sh.fine_lanes == 2)
+      hipLaunchKernelGGL((k_fine_co_rank_group<K, 2>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st,
+                         (const K*)A, m, (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+    else
+      hipLaunchKernelGGL((k_fine_co_rank_group<K, 4>), dim3((unsigned)((lanes + 255) / 256)), dim3(256), 0, st,
+                         (const K*)A, m, (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+  } else {
+    hipLaunchKernelGGL((k_fine_co_rank<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)A, m,
+                       (const K*)B, n, tile, nb, G, (const uint64_t*)coarse, bj);
+  }
+  return launch_status();
 }
 
 template <typename K>
 int Launch<K>::merge_blocks(bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av, uint64_t m,
                             const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* bj,
                             uint64_t tiles, hipStream_t st) {
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
-      const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
-      const dim3 g((unsigned)tiles), b(NT);
-      // bj == nullptr: every block co-ranks its own ends (no boundary pass)
-      auto go = [&](auto val_c, auto vec_c) {
-        constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
-        if (bj)
-          hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv, n,
-                             (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
-        else
-          hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
-                             Bv, n, (K*)C, Cv, tiles, ch.search, sh.xcd_order);
-      };
-      using T_ = std::true_type;
-      using F_ = std::false_type;
-      if (val && vec)
-        go(T_{}, T_{});
-      else if (val)
-        go(T_{}, F_{});
-      else if (vec)
-        go(F_{}, T_{});
+  return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+    constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+    static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
+    const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
+    const dim3 g((unsigned)tiles), b(NT);
+    // bj == nullptr: every block co-ranks its own ends (no boundary pass)
+    auto go = [&](auto val_c, auto vec_c) {
+      constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
+      if (bj)
+        hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv, n,
+                           (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
       else
-        go(F_{}, F_{});
-      return launch_status();
-    });
+        hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
+                           Bv, n, (K*)C, Cv, tiles, ch.search, sh.xcd_order);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (val && vec)
+      go(T_{}, T_{});
+    else if (val)
+      go(T_{}, F_{});
+    else if (vec)
+      go(F_{}, T_{});
+    else
+      go(F_{}, F_{});
+    return launch_status();
+  });
 }
 
 template <typename K>
 int Launch<K>::stream_co_ranks(const void* A, uint64_t m, const void* B, uint64_t n, uint32_t P, uint64_t* J,
                                hipStream_t st) {
-    const uint64_t waves = (uint64_t)P + 1;
-    hipLaunchKernelGGL((k_stream_co_rank<K>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, (const K*)A, m,
-                       (const K*)B, n, P, J);
-    return launch_status();
+  const uint64_t waves = (uint64_t)P + 1;
+  hipLaunchKernelGGL((k_stream_co_rank<K>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, st, (const K*)A, m,
+                     (const K*)B, n, P, J);
+  return launch_status();
 }
 
 template <typename K>
 int Launch<K>::merge_stream(bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m, const void* B,
                             const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* I,
                             const uint64_t* J, uint32_t P, hipStream_t st) {
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      if (val)
-        hipLaunchKernelGGL((k_merge_stream<K, true, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
-                           (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
-      else
-        hipLaunchKernelGGL((k_merge_stream<K, false, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
-                           (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
-      return launch_status();
-    });
+  return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+    constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+    if (val)
+      hipLaunchKernelGGL((k_merge_stream<K, true, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
+                         (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
+    else
+      hipLaunchKernelGGL((k_merge_stream<K, false, NT, E>), dim3(P), dim3(NT), 0, st, (const K*)A, Av, m,
+                         (const K*)B, Bv, n, (K*)C, Cv, I, J, P, ch.search);
+    return launch_status();
+  });
 }
 
 template <typename K>
@@ -128,20 +128,20 @@ int Launch<K>::seg_block_co_ranks(const Choice& ch, const Shape& sh, const void*
                                   const void* B, const uint64_t* b_off, uint32_t S, uint64_t N, uint64_t tile,
                                   uint64_t nb, uint64_t* bj, uint32_t* bs, uint64_t* jc, uint32_t* sc,
                                   const uint32_t* flag, hipStream_t st) {
-    if (ch.partition == 0 || !jc || !sc) {
-      hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
-                         (const K*)A, a_off, (const K*)B, b_off, S, N, tile, nb, bj, bs, flag, ch.search);
-      return launch_status();
-    }
-    const uint32_t G = sh.coarse_stride;
-    const uint64_t nc = num_coarse(nb, G);
-    hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const K*)A,
-                       a_off, (const K*)B, b_off, S, N, tile * G, nc, jc, sc, flag, ch.search);
-    if (launch_status() != CM_OK) return CM_EHIP;
-    hipLaunchKernelGGL((k_seg_fine_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, (const K*)A,
-                       a_off, (const K*)B, b_off, N, tile, nb, G, (const uint64_t*)jc, (const uint32_t*)sc, bj, bs,
-                       flag);
+  if (ch.partition == 0 || !jc || !sc) {
+    hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                       (const K*)A, a_off, (const K*)B, b_off, S, N, tile, nb, bj, bs, flag, ch.search);
     return launch_status();
+  }
+  const uint32_t G = sh.coarse_stride;
+  const uint64_t nc = num_coarse(nb, G);
+  hipLaunchKernelGGL((k_seg_block_co_rank<K>), dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, (const K*)A,
+                     a_off, (const K*)B, b_off, S, N, tile * G, nc, jc, sc, flag, ch.search);
+  if (launch_status() != CM_OK) return CM_EHIP;
+  hipLaunchKernelGGL((k_seg_fine_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, (const K*)A,
+                     a_off, (const K*)B, b_off, N, tile, nb, G, (const uint64_t*)jc, (const uint32_t*)sc, bj, bs,
+                     flag);
+  return launch_status();
 }
 
 template <typename K>
@@ -149,91 +149,91 @@ int Launch<K>::seg_merge_blocks(bool val, const Choice& ch, const void* A, const
                                 const void* B, const uint32_t* Bv, const uint64_t* b_off, uint32_t S, uint64_t N,
                                 void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs, uint64_t tiles,
                                 const uint32_t* flag, hipStream_t st) {
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
-      // outputs 16-byte aligned: 16-byte stores (the inputs are staged element-wise)
-      const bool vst = val ? all_aligned16({C, Cv}) : all_aligned16({C});
-      auto go = [&](auto val_c, auto vst_c) {
-        constexpr bool V = decltype(val_c)::value, W = decltype(vst_c)::value;
-        hipLaunchKernelGGL((k_seg_merge_blocks<K, V, NT, E, W>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
-                           ch.search);
-      };
-      using T_ = std::true_type;
-      using F_ = std::false_type;
-      if (val && vst)
-        go(T_{}, T_{});
-      else if (val)
-        go(T_{}, F_{});
-      else if (vst)
-        go(F_{}, T_{});
-      else
-        go(F_{}, F_{});
-      return launch_status();
-    });
+  return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+    constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+    static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
+    // outputs 16-byte aligned: 16-byte stores (the inputs are staged element-wise)
+    const bool vst = val ? all_aligned16({C, Cv}) : all_aligned16({C});
+    auto go = [&](auto val_c, auto vst_c) {
+      constexpr bool V = decltype(val_c)::value, W = decltype(vst_c)::value;
+      hipLaunchKernelGGL((k_seg_merge_blocks<K, V, NT, E, W>), dim3((unsigned)tiles), dim3(NT), 0, st,
+                         (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
+                         ch.search);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
+    if (val && vst)
+      go(T_{}, T_{});
+    else if (val)
+      go(T_{}, F_{});
+    else if (vst)
+      go(F_{}, T_{});
+    else
+      go(F_{}, F_{});
+    return launch_status();
+  });
 }
 
 template <typename K>
 int Launch<K>::batch_co_ranks(const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
                               uint64_t* bj, hipStream_t st) {
-    hipLaunchKernelGGL((k_batch_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
-                       (const MergeDesc*)d, count, tile, nb, bj, ch.search);
-    return launch_status();
+  hipLaunchKernelGGL((k_batch_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
+                     (const MergeDesc*)d, count, tile, nb, bj, ch.search);
+  return launch_status();
 }
 
 template <typename K>
 int Launch<K>::batch_merge_blocks(bool val, const Choice& ch, const void* d, uint32_t count, const uint64_t* bj,
                                   uint64_t tiles, bool vec, hipStream_t st) {
-    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      const dim3 g((unsigned)tiles), b(NT);
-      const MergeDesc* q = (const MergeDesc*)d;
-      if (val && vec)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search);
-      else if (val)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                           ch.search);
-      else if (vec)
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, true>), g, b, 0, st, q, count, bj, tiles,
-                           ch.search);
-      else
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                           ch.search);
-      return launch_status();
-    });
+  return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
+    constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+    const dim3 g((unsigned)tiles), b(NT);
+    const MergeDesc* q = (const MergeDesc*)d;
+    if (val && vec)
+      hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search);
+    else if (val)
+      hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
+                         ch.search);
+    else if (vec)
+      hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, true>), g, b, 0, st, q, count, bj, tiles,
+                         ch.search);
+    else
+      hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
+                         ch.search);
+    return launch_status();
+  });
 }
 
 template <typename K>
 int Launch<K>::co_rank_many(int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m, const void* B,
                             uint64_t n, uint64_t* j_out, hipStream_t st) {
-    hipLaunchKernelGGL((k_co_rank_many<K>), dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, ranks, q,
-                       (const K*)A, m, (const K*)B, n, j_out, search);
-    return launch_status();
+  hipLaunchKernelGGL((k_co_rank_many<K>), dim3((unsigned)((q + 255) / 256)), dim3(256), 0, st, ranks, q,
+                     (const K*)A, m, (const K*)B, n, j_out, search);
+  return launch_status();
 }
 
 template <typename K>
 int Launch<K>::stream_resident(bool val, int cfg) {
-    return by_cfg(cfg, [&](auto nt, auto e) -> int {
-      constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-      static int cache_v = 0, cache_k = 0;
-      return val ? (int)resident_blocks((const void*)k_merge_stream<K, true, NT, E>, NT, &cache_v)
-                 : (int)resident_blocks((const void*)k_merge_stream<K, false, NT, E>, NT, &cache_k);
-    });
+  return by_cfg(cfg, [&](auto nt, auto e) -> int {
+    constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
+    static int cache_v = 0, cache_k = 0;
+    return val ? (int)resident_blocks((const void*)k_merge_stream<K, true, NT, E>, NT, &cache_v)
+               : (int)resident_blocks((const void*)k_merge_stream<K, false, NT, E>, NT, &cache_k);
+  });
 }
 
 template <typename K>
 int Launch<K>::check_sorted(const void* X, uint64_t len, uint32_t* flag, uint64_t blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_check_sorted<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)X, len, flag);
-    return launch_status();
+  hipLaunchKernelGGL((k_check_sorted<K>), dim3((unsigned)blocks), dim3(256), 0, st, (const K*)X, len, flag);
+  return launch_status();
 }
 
 template <typename K>
 int Launch<K>::cross_rank_cuts(const void* A, uint64_t m, const void* B, uint64_t n, uint32_t h, uint64_t* ia,
                                uint64_t* ja, uint64_t* ib, uint64_t* jb, unsigned blocks, hipStream_t st) {
-    hipLaunchKernelGGL((k_cross_rank_cuts<K>), dim3(blocks), dim3(256), 0, st, (const K*)A, m, (const K*)B, n, h, ia,
-                       ja, ib, jb);
-    return launch_status();
+  hipLaunchKernelGGL((k_cross_rank_cuts<K>), dim3(blocks), dim3(256), 0, st, (const K*)A, m, (const K*)B, n, h, ia,
+                     ja, ib, jb);
+  return launch_status();
 }
 
 }  // namespace cm
