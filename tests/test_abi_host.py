@@ -406,3 +406,27 @@ def test_copy_tiles_argument_errors():
     assert lib.cm_copy_tiles(0, A, Av, 16, B, Bv, 16, A, Cv, None) == EALIAS
     assert lib.cm_copy_tiles(0, A, Av, 16, B, Bv, 16, C, C, None) == EALIAS
     assert lib.cm_copy_tiles(0, None, None, 0, None, None, 0, None, None, None) == OK
+
+
+def test_sort_default_tile_until_a_config_is_set():
+    """Sorts of 4-byte keys use the 256 x 9 tile until cm_set_config is
+    called for their key type; merges and 8-byte-key sorts use tile 0.
+    Checked in a fresh interpreter (other tests here set configurations)."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "import paper_1303_4312_amd as cm\n"
+        "N = 1 << 28\n"
+        "print(cm.tuning_get(cm.OP_SORT, 'uint32', True, N)[0],\n"
+        "      cm.tuning_get(cm.OP_SORT, 'float32', False, N)[0],\n"
+        "      cm.tuning_get(cm.OP_SORT, 'uint64', True, N)[0],\n"
+        "      cm.tuning_get(cm.OP_MERGE, 'uint32', True, N)[0])\n"
+        "cm.set_config('uint32', True, 0)\n"
+        "print(cm.tuning_get(cm.OP_SORT, 'uint32', True, N)[0],\n"
+        "      cm.tuning_get(cm.OP_SORT, 'uint32', False, N)[0])\n" % ROOT)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=300, check=True).stdout.split("\n")
+    assert out[0].split() == ["6", "6", "0", "0"]
+    assert out[1].split() == ["0", "6"]
+    assert cm.config_info(6) == (256, 9)
