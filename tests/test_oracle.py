@@ -278,3 +278,26 @@ def test_origin_payload_encodes_stability():
     bad_v = np.concatenate([d["Bv"], d["Av"]])[order]
     bad = keys[order].astype(np.uint64) << np.uint64(32) | bad_v.astype(np.uint64)
     assert not np.all(np.diff(bad.astype(np.int64)) > 0)
+
+
+@pytest.mark.parametrize("m", [1, 3, 11, 1001, 65537])
+def test_pair_duplicates_closed_form(m):
+    """Keys A[x] = x >> 1 and B[y] = y >> 1 (each value twice; m = n odd, so
+    the last value once on each side), payloads x and y.  Ties go to A first
+    (Section 2's stable merge), so value v's two A copies precede its two B
+    copies: C[p] = p >> 2 and C_val[p] = 2 (p >> 2) + (p & 1) for p < N - 2,
+    then A's last element, then B's.  The GPU test past 2^32 outputs uses
+    this closed form."""
+    n = m
+    A = (np.arange(m) >> 1).astype(np.uint32)
+    B = (np.arange(n) >> 1).astype(np.uint32)
+    Av = np.arange(m, dtype=np.uint32)
+    Bv = np.arange(n, dtype=np.uint32)
+    C, Cv = oracle.stable_merge(A, B, Av, Bv)
+    N = m + n
+    p = np.arange(N, dtype=np.int64)
+    ek, ev = p >> 2, 2 * (p >> 2) + (p & 1)
+    ek[N - 2], ev[N - 2] = (m - 1) >> 1, m - 1
+    ek[N - 1], ev[N - 1] = (n - 1) >> 1, n - 1
+    assert np.array_equal(C, ek.astype(np.uint32))
+    assert np.array_equal(Cv, ev.astype(np.uint32))
