@@ -28,6 +28,14 @@
 
 namespace cm {
 
+// Orders this wave's LDS writes before its later LDS reads (lanes of one
+// wave exchanging data through LDS; no other wave takes part).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename K, bool VAL, int NT, int E>
 __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, const uint32_t* __restrict__ Xv,
                                                     uint64_t N, K* __restrict__ Y, uint32_t* __restrict__ Yv,
@@ -41,12 +49,25 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
   for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
-    for (int x = (int)threadIdx.x; x < T; x += NT) {
+    // every load in flight before the first LDS write waits for one (a slot
+    // past the run re-reads its first element: len >= 1)
+    K lk[E];
+    uint32_t lv[VAL ? E : 1];
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int x = (int)threadIdx.x + r * NT;
+      const uint64_t g = i0 + (uint64_t)(x < len ? x : 0);
+      lk[r] = X[g];
+      if constexpr (VAL) lv[r] = Xv[g];
+    }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int x = (int)threadIdx.x + r * NT;  // < T = NT * E
       // pads: the last key of the order, after every real key (and after
       // equal real keys, being later)
-      s_k[0][x] = x < len ? X[i0 + x] : key_last<K>();
+      s_k[0][x] = x < len ? lk[r] : key_last<K>();
       if constexpr (VAL)
-        if (x < len) s_v[x] = Xv[i0 + x];
+        if (x < len) s_v[x] = lv[r];
     }
     __syncthreads();
 
@@ -78,9 +99,12 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
       s_k[0][q0 + e] = k[e];
       s_i[0][q0 + e] = id[e];
     }
-    __syncthreads();
+    wave_sync();  // the first round pairs neighbouring threads of one wave
 
-    // merge runs of R = E, 2E, 4E, ... pairwise in LDS
+    // merge runs of R = E, 2E, 4E, ... pairwise in LDS.  A round reads only
+    // what the threads of its own pair wrote in the round before; while a
+    // pair's threads (2R / E of them, a power of two) fit in one wave, the
+    // rounds need no workgroup barrier.
     int src = 0;
     for (int R = E; R < T; R <<= 1) {
       const int per = (2 * R) / E;  // threads per merged pair
@@ -100,7 +124,12 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
         s_k[src ^ 1][pair * 2 * R + d + e] = ok[e];
         s_i[src ^ 1][pair * 2 * R + d + e] = os[e] >= 0 ? si[os[e]] : si[R + ~os[e]];
       }
-      __syncthreads();
+      // the next round's pairs (4R / E threads) inside one wave: wave order
+      // suffices; otherwise (and before the stores) the whole workgroup
+      if (4 * R < T && 2 * per <= 64)
+        wave_sync();
+      else
+        __syncthreads();
       src ^= 1;
     }
 
