@@ -62,3 +62,32 @@ def test_merge_past_2_32_outputs(partition, restore_settings):
     assert check(C, Cv, m, n) == 0
     del C, Cv
     torch.cuda.empty_cache()
+
+
+def test_segmented_past_2_32_outputs():
+    """The segmented form over the same arrays: an empty segment, the whole
+    merge, an empty segment (offsets past 2^32), same closed form."""
+    import torch
+    free, _ = torch.cuda.mem_get_info()
+    if free < (80 << 30):
+        pytest.skip("needs about 69 GB of free device memory")
+    m = n = (1 << 31) + 3
+    print(f"\n[max size] segmented, m = n = {m}", flush=True)
+    A = torch.empty(m, dtype=torch.uint32, device="cuda")
+    B = torch.empty(n, dtype=torch.uint32, device="cuda")
+    Av = torch.empty(m, dtype=torch.uint32, device="cuda")
+    Bv = torch.empty(n, dtype=torch.uint32, device="cuda")
+    for s in range(0, m, CHUNK):
+        e = min(m, s + CHUNK)
+        fill(A, s, e, lambda x: x >> 1)
+        fill(B, s, e, lambda x: x >> 1)
+        fill(Av, s, e, lambda x: x)
+        fill(Bv, s, e, lambda x: x)
+    a_off = torch.tensor([0, 0, m, m], dtype=torch.uint64, device="cuda")
+    b_off = torch.tensor([0, 0, n, n], dtype=torch.uint64, device="cuda")
+    C, Cv = cm.stable_merge_segmented(A, a_off, B, b_off, Av, Bv)
+    torch.cuda.synchronize()
+    del A, B, Av, Bv
+    assert check(C, Cv, m, n) == 0
+    del C, Cv
+    torch.cuda.empty_cache()
