@@ -876,8 +876,9 @@ def main():
             setattr(args, "no_" + leg, True)
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU runs are not part of this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the library "
+              "has no multi-GPU path; a merge would shard by output range, each GPU "
+              "co-ranking its two ends.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
