@@ -25,7 +25,7 @@ namespace {
 
 struct Settings {
   int cfg[CM_KEY_F32_DESC + 1][2] = {};       // [key type][payload] default configuration (0)
-  bool cfg_set[CM_KEY_F32_DESC + 1][2] = {};  // set by the caller (else sorts of 4-byte keys use kSortCfg)
+  bool cfg_set[CM_KEY_F32_DESC + 1][2] = {};  // set by the caller (else the defaults of resolve)
   int search = 1;                             // bisection
   int partition = -1;                         // automatic (see resolve)
   Shape shape;                                // coarse stride, block order
@@ -44,9 +44,14 @@ std::mutex g_tuning_mu;
 
 int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
 
-// Default tile of a merge sort of 4-byte keys (256 x 9: fewest passes for
-// its speed; measured fastest of the eight at 2^26 and 2^28 uint32 keys).
+// Default tiles where the process-wide configuration has not been set for
+// the key type (measured on MI355X): a merge sort of 4-byte keys, 256 x 9
+// (fastest of the eight at 2^26 and 2^28 uint32 keys), and a single merge
+// of keys without payloads, 256 x 9 (within 4 % of the best tile for uint32,
+// uint64 and float32 keys at 2^27-2^28 per side, where 256 x 7 is up to
+// 39 % slower).
 constexpr int kSortCfg = 6;
+constexpr int kKeysMergeCfg = 6;
 
 Choice resolve(int op, int kt, bool val, uint64_t N) {
   {
@@ -58,7 +63,10 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
   if (part < 0)  // automatic: below 2^22 outputs a single merge skips the boundary pass
     part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
   int cfg = g_set.cfg[kt][val ? 1 : 0];
-  if (op == kOpSort && !g_set.cfg_set[kt][val ? 1 : 0] && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = kSortCfg;
+  if (!g_set.cfg_set[kt][val ? 1 : 0]) {
+    if (op == kOpSort && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = kSortCfg;
+    if (op == kOpMerge && !val) cfg = kKeysMergeCfg;
+  }
   return Choice{cfg, g_set.search, part};
 }
 
