@@ -294,9 +294,9 @@ def partition_ablation_leg(A, Av, B, Bv, C, Cv, P=2048, reps=5):
 
 def generic_order_leg(A, Av, B, Bv, reps=10):
     """The merge under the reversed key order (the step's arrays reversed,
-    CM_KEY_*_DESC) against the same merge ascending, and the merge of the
-    same keys carrying 8-byte records (origin codes merged, records gathered
-    by code).  Median whole-call times from the library's events; the record
+    CM_KEY_*_DESC) against the same merge ascending, the same keys merged
+    without payloads (default tile), and the merge of the same keys carrying
+    8-byte records (origin codes merged, records gathered by code).  Median whole-call times from the library's events; the record
     merge is timed end to end with torch events (two calls)."""
     import torch
     import paper_1303_4312_amd as cm
@@ -317,6 +317,7 @@ def generic_order_leg(A, Av, B, Bv, reps=10):
 
     asc = calls(lambda: cm.stable_merge_pairs(A, Av, B, Bv, C, Cv))
     desc = calls(lambda: cm.stable_merge_pairs(Ad, Avd, Bd, Bvd, C, Cv, descending=True))
+    keys = calls(lambda: cm.stable_merge(A, B, C))  # keys only: 2 K bytes per output
     Arec = torch.arange(A.numel(), dtype=torch.int64, device=A.device)
     Brec = -torch.arange(B.numel(), dtype=torch.int64, device=A.device) - 1
     cm.merge_records(A, B, Arec, Brec)
@@ -333,6 +334,8 @@ def generic_order_leg(A, Av, B, Bv, reps=10):
     return {
         "ascending_call_ms": asc[0], "ascending_merge_kernel_ms": asc[1],
         "descending_call_ms": desc[0], "descending_merge_kernel_ms": desc[1],
+        "keys_only_call_ms": keys[0], "keys_only_merge_kernel_ms": keys[1],
+        "keys_only_kernel_gbs": 2 * N * A.element_size() / (keys[1] * 1e-3) / 1e9,
         "records_8byte_ms": rec_ms,
         "records_8byte_keys_per_s": N / (rec_ms * 1e-3),
         "records_note": "codes filled, keys merged with codes, 8-byte records gathered by code",
@@ -1034,7 +1037,9 @@ def main():
         result["generic_order"] = generic_order_leg(A, Av, B, Bv)
         go = result["generic_order"]
         log(f"descending merge {go['descending_call_ms']:.3f} ms vs ascending "
-            f"{go['ascending_call_ms']:.3f} ms; with 8-byte records {go['records_8byte_ms']:.3f} ms")
+            f"{go['ascending_call_ms']:.3f} ms; keys only {go['keys_only_call_ms']:.3f} ms "
+            f"({go['keys_only_kernel_gbs']:.0f} GB/s); with 8-byte records "
+            f"{go['records_8byte_ms']:.3f} ms")
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
