@@ -434,3 +434,12 @@ def test_sort_default_tile_until_a_config_is_set():
     assert out[1].split() == ["0", "6"]
     assert out[2].split() == ["6", "0"]
     assert cm.config_info(6) == (256, 9)
+
+
+def test_c_client_builds_against_the_header(tmp_path):
+    """A C program (tests/c_abi_client.c) compiles against include/ and
+    links against the shared library alone (run on the GPU by
+    tests/test_c_client_gpu.py)."""
+    from tests import c_client
+    exe = c_client.build(str(tmp_path))
+    assert os.path.exists(exe)
