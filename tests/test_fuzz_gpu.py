@@ -2,8 +2,8 @@
 once: key type and order, payload or not, sizes (zero, tiny, ragged, up to
 3e5 per side), key distribution (few distinct values, wide, all equal, long
 runs of one side), base alignment, tile configuration, co-rank search and
-boundary mode, single merge and segmented form.  Every result bit for bit
-against the oracle."""
+boundary mode, single merge, segmented form, merge sort and batches of
+separate merges.  Every result bit for bit against the oracle."""
 import zlib
 
 import numpy as np
@@ -111,3 +111,57 @@ def test_random_segmented_case(case, restore_settings):
     C, Cv = to_host(C), to_host(Cv)
     assert same_bits(C, Ce), f"keys differ at {first_difference(C, Ce)}"
     assert same_bits(Cv, Cve), f"payloads differ at {first_difference(Cv, Cve)}"
+
+
+@pytest.mark.parametrize("case", range(24))
+def test_random_sort_case(case, restore_settings):
+    """Stable merge sort of random keys (ties broken by input position),
+    keys only or with payloads, in place or not, any tile configuration."""
+    import torch
+    rng = np.random.default_rng(zlib.crc32(b"fuzz-sort") + case)
+    dtype = DTYPES[case % 3]
+    descending = bool(rng.integers(0, 2))
+    payload = bool(rng.integers(0, 2))
+    in_place = bool(rng.integers(0, 2))
+    n = draw_size(rng) * int(rng.integers(1, 4))
+    cfg = int(rng.integers(0, cm.config_count()))
+    print(f"\n[fuzz sort {case}] {np.dtype(dtype).name} desc={descending} pairs={payload} "
+          f"n={n} cfg={cfg} in_place={in_place}", flush=True)
+    span = int(rng.choice([3, 1000, 1 << 30]))
+    keys = rng.integers(0, span, n)
+    keys = (keys.astype(np.float32) / 4 if np.dtype(dtype) == np.float32 else keys.astype(dtype))
+    vals = np.arange(n, dtype=np.uint32)
+    cm.set_config(np.dtype(dtype).name, payload, cfg)
+    dk = to_dev(keys)
+    dv = to_dev(vals) if payload else None
+    out = (dk, dv) if in_place else (None, None)
+    res = cm.stable_sort(dk, dv, out[0], out[1], descending=descending)
+    if payload:
+        Ke, Ve = oracle.stable_sort(keys, vals, descending=descending)
+        assert same_bits(to_host(res[0]), Ke) and same_bits(to_host(res[1]), Ve)
+    else:
+        assert same_bits(to_host(res), oracle.stable_sort(keys, descending=descending))
+
+
+@pytest.mark.parametrize("case", range(12))
+def test_random_batch_case(case):
+    """A batch of separately allocated merges of random sizes (some empty)
+    in one launch, each against the oracle."""
+    rng = np.random.default_rng(zlib.crc32(b"fuzz-batch") + case)
+    dtype = DTYPES[case % 3]
+    count = int(rng.integers(1, 40))
+    merges, host = [], []
+    for _ in range(count):
+        m, n = draw_size(rng) // 4, draw_size(rng) // 4
+        A = draw_keys(rng, m, dtype, "few", False)
+        B = draw_keys(rng, n, dtype, "wide", False)
+        Av = np.arange(m, dtype=np.uint32)
+        Bv = (np.arange(n, dtype=np.uint32) | np.uint32(1 << 31)).astype(np.uint32)
+        merges.append((to_dev(A), to_dev(Av), to_dev(B), to_dev(Bv)))
+        host.append((A, Av, B, Bv))
+    print(f"\n[fuzz batch {case}] {np.dtype(dtype).name} {count} merges, "
+          f"{sum(a.size + b.size for a, _, b, _ in host)} outputs", flush=True)
+    outs = cm.stable_merge_batch(merges)
+    for (A, Av, B, Bv), (C, Cv) in zip(host, outs):
+        Ce, Cve = oracle.stable_merge(A, B, Av, Bv)
+        assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
