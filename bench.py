@@ -872,6 +872,8 @@ def main():
     ap.add_argument("--only-step", action="store_true",
                     help="run the timed step only (no other leg): the form profiled under "
                          "rocprofv3")
+    ap.add_argument("--only-sort", action="store_true",
+                    help="run the merge-sort leg only and print its record (for profiling)")
     args = ap.parse_args()
     if args.only_step:
         for leg in ("cpu_baseline", "batched", "latency", "serving", "boundary_ab", "ablation",
@@ -887,6 +889,12 @@ def main():
     import numpy as np
     import torch
     import paper_1303_4312_amd as cm
+
+    if args.only_sort:
+        r = sort_leg()
+        log(f"sort: {r['ms']:.2f} ms ({r['keys_per_s'] / 1e9:.1f} G keys/s)")
+        print(json.dumps({"sort": r}), flush=True)
+        return
 
     log(f"generating workload {args.workload}")
     d, desc = workload_inputs(args.workload)
