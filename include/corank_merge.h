@@ -255,8 +255,9 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     for (key_type, with_payload) in this process (not thread-safe against
  *     concurrent merges; set it before launching).  Until cm_set_config is
  *     called for (key_type, with_payload), the calls use configuration 0
- *     (256 x 7), except sorts of 4-byte keys and single merges without
- *     payloads, which use configuration 6 (256 x 9).
+ *     (256 x 7), except sorts of 4-byte keys (configuration 6, 256 x 9,
+ *     with payloads; 1, 256 x 11, without) and single merges without
+ *     payloads (6).
  *   cm_set_search: co-rank search of the per-thread searches inside a
  *     block and of the one-level boundary pass: 0 = Algorithm 1, 1 = plain
  *     bisection over the diagonal (default).  Both return the unique pair

@@ -45,12 +45,14 @@ std::mutex g_tuning_mu;
 int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
 
 // Default tiles where the process-wide configuration has not been set for
-// the key type (measured on MI355X): a merge sort of 4-byte keys, 256 x 9
-// (fastest of the eight at 2^26 and 2^28 uint32 keys), and a single merge
-// of keys without payloads, 256 x 9 (within 4 % of the best tile for uint32,
-// uint64 and float32 keys at 2^27-2^28 per side, where 256 x 7 is up to
-// 39 % slower).
+// the key type (measured on MI355X): a merge sort of 4-byte keys with
+// payloads, 256 x 9 (fastest of the eight at 2^26 and 2^28 uint32 keys),
+// without payloads 256 x 11 (8.3 ms for 2^28 uint32 keys against 9.9 ms at
+// 256 x 7); a single merge of keys without payloads, 256 x 9 (within 4 % of
+// the best tile for uint32, uint64 and float32 keys at 2^27-2^28 per side,
+// where 256 x 7 is up to 39 % slower).
 constexpr int kSortCfg = 6;
+constexpr int kSortKeysCfg = 1;
 constexpr int kKeysMergeCfg = 6;
 
 Choice resolve(int op, int kt, bool val, uint64_t N) {
@@ -64,7 +66,7 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
     part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
   int cfg = g_set.cfg[kt][val ? 1 : 0];
   if (!g_set.cfg_set[kt][val ? 1 : 0]) {
-    if (op == kOpSort && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = kSortCfg;
+    if (op == kOpSort && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = val ? kSortCfg : kSortKeysCfg;
     if (op == kOpMerge && !val) cfg = kKeysMergeCfg;
   }
   return Choice{cfg, g_set.search, part};

@@ -44,7 +44,9 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
   constexpr int T = NT * E;
   static_assert(T <= 65536, "run positions are 16-bit");
   __shared__ K s_k[2][T];
-  __shared__ uint16_t s_i[2][T];  // position in the run each key came from
+  // position in the run each key came from (payloads follow it; keys alone
+  // need none: the merges move the keys themselves, ties in order)
+  __shared__ uint16_t s_i[VAL ? 2 : 1][VAL ? T : 1];
   __shared__ uint32_t s_v[VAL ? T : 1];
   for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
     const uint64_t i0 = t * (uint64_t)T;
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       k[e] = s_k[0][q0 + e];
-      id[e] = (uint16_t)(q0 + e);
+      if constexpr (VAL) id[e] = (uint16_t)(q0 + e);
     }
 #pragma unroll
     for (int r = 0; r < E; ++r) {
@@ -88,16 +90,18 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
           const K tk = k[e];
           k[e] = k[e + 1];
           k[e + 1] = tk;
-          const uint16_t ti = id[e];
-          id[e] = id[e + 1];
-          id[e + 1] = ti;
+          if constexpr (VAL) {
+            const uint16_t ti = id[e];
+            id[e] = id[e + 1];
+            id[e + 1] = ti;
+          }
         }
       }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       s_k[0][q0 + e] = k[e];
-      s_i[0][q0 + e] = id[e];
+      if constexpr (VAL) s_i[0][q0 + e] = id[e];
     }
     wave_sync();  // the first round pairs neighbouring threads of one wave
 
@@ -118,11 +122,13 @@ __global__ __launch_bounds__(NT) void k_sort_blocks(const K* __restrict__ X, con
       K ok[E];
       int os[E];
       merge_run<K, E>(sa, R, sb, R, a, d - a, E, ok, os);
-      const uint16_t* si = s_i[src] + pair * 2 * R;
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         s_k[src ^ 1][pair * 2 * R + d + e] = ok[e];
-        s_i[src ^ 1][pair * 2 * R + d + e] = os[e] >= 0 ? si[os[e]] : si[R + ~os[e]];
+        if constexpr (VAL) {
+          const uint16_t* si = s_i[src] + pair * 2 * R;
+          s_i[src ^ 1][pair * 2 * R + d + e] = os[e] >= 0 ? si[os[e]] : si[R + ~os[e]];
+        }
       }
       // the next round's pairs (4R / E threads) inside one wave: wave order
       // suffices; otherwise (and before the stores) the whole workgroup

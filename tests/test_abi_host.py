@@ -409,9 +409,10 @@ def test_copy_tiles_argument_errors():
 
 
 def test_sort_default_tile_until_a_config_is_set():
-    """Sorts of 4-byte keys and keys-only single merges use the 256 x 9
-    tile until cm_set_config is called for their (key type, payload); merges
-    with payloads and 8-byte-key sorts use tile 0.  Checked in a fresh
+    """Until cm_set_config is called for their (key type, payload): sorts
+    of 4-byte keys use the 256 x 9 tile with payloads and 256 x 11 without,
+    keys-only single merges 256 x 9; merges with payloads, segmented
+    batches and 8-byte-key sorts use tile 0.  Checked in a fresh
     interpreter (other tests here set configurations)."""
     import subprocess
     import sys
@@ -430,8 +431,8 @@ def test_sort_default_tile_until_a_config_is_set():
         "      cm.tuning_get(cm.OP_SEGMENTED, 'uint32', False, N)[0])\n" % ROOT)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                          timeout=300, check=True).stdout.split("\n")
-    assert out[0].split() == ["6", "6", "0", "0"]
-    assert out[1].split() == ["0", "6"]
+    assert out[0].split() == ["6", "1", "0", "0"]
+    assert out[1].split() == ["0", "1"]
     assert out[2].split() == ["6", "0"]
     assert cm.config_info(6) == (256, 9)
 
