@@ -50,10 +50,14 @@ int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
 // without payloads 256 x 11 (8.3 ms for 2^28 uint32 keys against 9.9 ms at
 // 256 x 7); a single merge of keys without payloads, 256 x 9 (within 4 % of
 // the best tile for uint32, uint64 and float32 keys at 2^27-2^28 per side,
-// where 256 x 7 is up to 39 % slower).
+// where 256 x 7 is up to 39 % slower; batches of separate merges run the
+// same block merge); a segmented batch, 256 x 15 (the 65,536-segment batch:
+// 1.17 ms keys only against 1.65 ms at 256 x 7, 2.04 ms against 2.10 ms
+// with payloads).
 constexpr int kSortCfg = 6;
 constexpr int kSortKeysCfg = 1;
 constexpr int kKeysMergeCfg = 6;
+constexpr int kSegCfg = 2;
 
 Choice resolve(int op, int kt, bool val, uint64_t N) {
   {
@@ -67,7 +71,8 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
   int cfg = g_set.cfg[kt][val ? 1 : 0];
   if (!g_set.cfg_set[kt][val ? 1 : 0]) {
     if (op == kOpSort && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = val ? kSortCfg : kSortKeysCfg;
-    if (op == kOpMerge && !val) cfg = kKeysMergeCfg;
+    if ((op == kOpMerge || op == kOpBatch) && !val) cfg = kKeysMergeCfg;
+    if (op == kOpSegmented) cfg = kSegCfg;
   }
   return Choice{cfg, g_set.search, part};
 }

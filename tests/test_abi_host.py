@@ -411,8 +411,8 @@ def test_copy_tiles_argument_errors():
 def test_sort_default_tile_until_a_config_is_set():
     """Until cm_set_config is called for their (key type, payload): sorts
     of 4-byte keys use the 256 x 9 tile with payloads and 256 x 11 without,
-    keys-only single merges 256 x 9; merges with payloads, segmented
-    batches and 8-byte-key sorts use tile 0.  Checked in a fresh
+    keys-only single merges 256 x 9, segmented batches 256 x 15; merges
+    with payloads and 8-byte-key sorts use tile 0.  Checked in a fresh
     interpreter (other tests here set configurations)."""
     import subprocess
     import sys
@@ -433,7 +433,7 @@ def test_sort_default_tile_until_a_config_is_set():
                          timeout=300, check=True).stdout.split("\n")
     assert out[0].split() == ["6", "1", "0", "0"]
     assert out[1].split() == ["0", "1"]
-    assert out[2].split() == ["6", "0"]
+    assert out[2].split() == ["6", "2"]
     assert cm.config_info(6) == (256, 9)
 
 
