@@ -212,7 +212,7 @@ def batched_leg(steps, warmup, tune):
         "per_merge_ms": t_each * 1e3,
         "per_merge_calls": a_off.numel() - 1,
         "per_merge_note": ("one cm_stable_merge_pairs call per merge on its sub-arrays, default "
-                           "choice per size (below 2^22 outputs: one kernel launch per call)"),
+                           "choice per size (below 2^24 outputs: one kernel launch per call)"),
         "speedup": t_each / t_batch,
         "identical_output": same,
     }

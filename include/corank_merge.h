@@ -264,7 +264,8 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     of Lemma 1.
  *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
  *     -1 (default) = automatic: mode 4 for single merges of fewer than
- *     2^22 outputs, else mode 2; 0 = one GPU thread per boundary over the
+ *     2^24 outputs with payloads (2^22 keys only; from 2^21 outputs with
+ *     the 512 x 11 tile unless cm_set_config was called), else mode 2; 0 = one GPU thread per boundary over the
  *     whole diagonal; 1 = two levels: every coarse boundary by a whole wave
  *     with a 64-ary search, then the others by bisection between their two
  *     coarse neighbours; 2 = two levels with 16 lanes (a 16-ary search) per

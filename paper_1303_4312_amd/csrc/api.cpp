@@ -66,10 +66,12 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
     if (it != g_tuning.end()) return it->second.ch;
   }
   int part = g_set.partition;
-  if (part < 0)  // automatic: below 2^22 outputs a single merge skips the boundary pass
-    part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
+  const bool auto_part = part < 0;
+  if (auto_part)  // automatic: small single merges skip the boundary pass
+    part = (op == kOpMerge && N < (val ? kInBlockBelow : kInBlockKeysBelow)) ? 4 : 2;
   int cfg = g_set.cfg[kt][val ? 1 : 0];
   if (!g_set.cfg_set[kt][val ? 1 : 0]) {
+    if (op == kOpMerge && val && auto_part && part == 4 && N >= kInBlockWideFrom) cfg = kInBlockWideCfg;
     if (op == kOpSort && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = val ? kSortCfg : kSortKeysCfg;
     if ((op == kOpMerge || op == kOpBatch) && !val) cfg = kKeysMergeCfg;
     if (op == kOpSegmented) cfg = kSegCfg;

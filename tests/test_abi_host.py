@@ -176,12 +176,14 @@ def test_tuning_table_host_logic(tmp_path):
     cm.tuning_clear()
     assert cm.tuning_count() == 0
     default = cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000)
-    # automatic boundary pass: none below 2^22 outputs, two-level from there
-    # and for batches
+    # automatic boundary pass: none below 2^24 outputs with payloads (2^22
+    # keys only), two-level from there and for batches
     assert cm.get_partition() == -1
     assert default == (cm.get_config("uint32", True), cm.get_search(), 4)
-    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, (1 << 22) - 1)[2] == 4
-    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1 << 22)[2] == 2
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, (1 << 24) - 1)[2] == 4
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1 << 24)[2] == 2
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, (1 << 22) - 1)[2] == 4
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1 << 22)[2] == 2
     assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1000)[2] == 2
     cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, 3, 0, 0)  # size class 10: N in [512, 1024)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000) == (3, 0, 0)
