@@ -255,16 +255,16 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     for (key_type, with_payload) in this process (not thread-safe against
  *     concurrent merges; set it before launching).  Until cm_set_config is
  *     called for (key_type, with_payload), the calls use configuration 0
- *     (256 x 7), except sorts of 4-byte keys (configuration 6, 256 x 9,
- *     with payloads; 1, 256 x 11, without), single merges and batches
- *     without payloads (6) and segmented batches (2, 256 x 15).
+ *     (256 x 7), except sorts (configuration 6, 256 x 9; 1, 256 x 11, for
+ *     4-byte keys without payloads), single merges and batches without
+ *     payloads (6) and segmented batches (2, 256 x 15).
  *   cm_set_search: co-rank search of the per-thread searches inside a
  *     block and of the one-level boundary pass: 0 = Algorithm 1, 1 = plain
  *     bisection over the diagonal (default).  Both return the unique pair
  *     of Lemma 1.
  *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
  *     -1 (default) = automatic: mode 4 for single merges of fewer than
- *     2^24 outputs with payloads (2^22 keys only; from 2^21 outputs with
+ *     2^24 outputs (from 2^21 outputs with payloads, 2^22 keys only, with
  *     the 512 x 11 tile unless cm_set_config was called), else mode 2; 0 = one GPU thread per boundary over the
  *     whole diagonal; 1 = two levels: every coarse boundary by a whole wave
  *     with a 64-ary search, then the others by bisection between their two

@@ -597,7 +597,7 @@ def get_search() -> int:
 
 def set_partition(mode: int):
     """Block-boundary pass: -1 = automatic (the default: 4 below 2^24
-    outputs for a single merge with payloads, 2^22 keys only, else 2), 0 = one thread per boundary, 1 = two-level with a
+    outputs for a single merge, else 2), 0 = one thread per boundary, 1 = two-level with a
     64-lane coarse search, 2 = two-level with a 16-lane coarse search, 3 =
     one block per resident workgroup (streaming), 4 = no pass, each block
     co-ranks its own ends."""

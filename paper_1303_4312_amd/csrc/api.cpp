@@ -45,10 +45,11 @@ std::mutex g_tuning_mu;
 int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
 
 // Default tiles where the process-wide configuration has not been set for
-// the key type (measured on MI355X): a merge sort of 4-byte keys with
-// payloads, 256 x 9 (fastest of the eight at 2^26 and 2^28 uint32 keys),
-// without payloads 256 x 11 (8.3 ms for 2^28 uint32 keys against 9.9 ms at
-// 256 x 7); a single merge of keys without payloads, 256 x 9 (within 4 % of
+// the key type (measured on MI355X): a merge sort with payloads, 256 x 9
+// (fastest of the eight at 2^26 and 2^28 uint32 keys, within 1 % of the best
+// for 2^26 and 2^27 uint64 keys); without payloads 256 x 11 for 4-byte keys
+// (8.3 ms for 2^28 uint32 keys against 9.9 ms at 256 x 7) and 256 x 9 for
+// uint64 keys (6.9 ms for 2^27 against 7.7 ms); a single merge of keys without payloads, 256 x 9 (within 4 % of
 // the best tile for uint32, uint64 and float32 keys at 2^27-2^28 per side,
 // where 256 x 7 is up to 39 % slower; batches of separate merges run the
 // same block merge); a segmented batch, 256 x 15 (the 65,536-segment batch:
@@ -68,11 +69,12 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
   int part = g_set.partition;
   const bool auto_part = part < 0;
   if (auto_part)  // automatic: small single merges skip the boundary pass
-    part = (op == kOpMerge && N < (val ? kInBlockBelow : kInBlockKeysBelow)) ? 4 : 2;
+    part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
   int cfg = g_set.cfg[kt][val ? 1 : 0];
   if (!g_set.cfg_set[kt][val ? 1 : 0]) {
-    if (op == kOpMerge && val && auto_part && part == 4 && N >= kInBlockWideFrom) cfg = kInBlockWideCfg;
-    if (op == kOpSort && kt != CM_KEY_U64 && kt != CM_KEY_U64_DESC) cfg = val ? kSortCfg : kSortKeysCfg;
+    if (op == kOpMerge && auto_part && part == 4 && N >= (val ? kInBlockWideFrom : kInBlockWideKeysFrom))
+      cfg = kInBlockWideCfg;
+    if (op == kOpSort) cfg = (val || kt == CM_KEY_U64 || kt == CM_KEY_U64_DESC) ? kSortCfg : kSortKeysCfg;
     if ((op == kOpMerge || op == kOpBatch) && !val) cfg = kKeysMergeCfg;
     if (op == kOpSegmented) cfg = kSegCfg;
   }

@@ -45,12 +45,13 @@ constexpr int kMaxPartition = 4;
 // Measured on MI355X (uint32 pairs, back-to-back calls): with the 512 x 11
 // tile (fewest blocks, so fewest in-block searches) mode 4 takes 14.5 us at
 // 2^22 outputs against 20.9-24.8 us with the pass, 35.0 against 35.5-38.6 us
-// at 2^23, and draws level at 2^24; the 256 x 7 tile loses from 2^22.
-// Keys-only merges keep the earlier bound.
+// at 2^23, and draws level at 2^24; the 256 x 7 tile loses from 2^22.  Keys
+// only: 10.9 us at 2^22 against 17.7-20.0 us, 23.4 against 25.5 us at 2^23,
+// and the pass ahead at 2^24.
 constexpr uint64_t kInBlockBelow = 1ull << 24;
-constexpr uint64_t kInBlockKeysBelow = 1ull << 22;
-constexpr uint64_t kInBlockWideFrom = 1ull << 21;  // from here mode 4 takes the widest tile
-constexpr int kInBlockWideCfg = 7;                 // 512 x 11
+constexpr uint64_t kInBlockWideFrom = 1ull << 21;      // from here mode 4 takes the widest tile
+constexpr uint64_t kInBlockWideKeysFrom = 1ull << 22;  // the same, keys only
+constexpr int kInBlockWideCfg = 7;                     // 512 x 11
 
 // Launch-shape settings that never change results.
 struct Shape {

@@ -176,14 +176,14 @@ def test_tuning_table_host_logic(tmp_path):
     cm.tuning_clear()
     assert cm.tuning_count() == 0
     default = cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000)
-    # automatic boundary pass: none below 2^24 outputs with payloads (2^22
-    # keys only), two-level from there and for batches
+    # automatic boundary pass: none below 2^24 outputs, two-level from
+    # there and for batches
     assert cm.get_partition() == -1
     assert default == (cm.get_config("uint32", True), cm.get_search(), 4)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, (1 << 24) - 1)[2] == 4
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1 << 24)[2] == 2
-    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, (1 << 22) - 1)[2] == 4
-    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1 << 22)[2] == 2
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, (1 << 24) - 1)[2] == 4
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1 << 24)[2] == 2
     assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1000)[2] == 2
     cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, 3, 0, 0)  # size class 10: N in [512, 1024)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000) == (3, 0, 0)
@@ -413,8 +413,8 @@ def test_copy_tiles_argument_errors():
 def test_sort_default_tile_until_a_config_is_set():
     """Until cm_set_config is called for their (key type, payload): sorts
     of 4-byte keys use the 256 x 9 tile with payloads and 256 x 11 without,
-    keys-only single merges 256 x 9, segmented batches 256 x 15; merges
-    with payloads and 8-byte-key sorts use tile 0.  Checked in a fresh
+    uint64 sorts 256 x 9, keys-only single merges 256 x 9, segmented
+    batches 256 x 15; merges with payloads use tile 0.  Checked in a fresh
     interpreter (other tests here set configurations)."""
     import subprocess
     import sys
@@ -433,7 +433,7 @@ def test_sort_default_tile_until_a_config_is_set():
         "      cm.tuning_get(cm.OP_SEGMENTED, 'uint32', False, N)[0])\n" % ROOT)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                          timeout=300, check=True).stdout.split("\n")
-    assert out[0].split() == ["6", "1", "0", "0"]
+    assert out[0].split() == ["6", "1", "6", "0"]
     assert out[1].split() == ["0", "1"]
     assert out[2].split() == ["6", "2"]
     assert cm.config_info(6) == (256, 9)
