@@ -256,8 +256,8 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     concurrent merges; set it before launching).  Until cm_set_config is
  *     called for (key_type, with_payload), the calls use configuration 0
  *     (256 x 7), except sorts (configuration 6, 256 x 9; 1, 256 x 11, for
- *     4-byte keys without payloads), single merges and batches without
- *     payloads (6) and segmented batches (2, 256 x 15).
+ *     4-byte keys without payloads), single merges without payloads (6),
+ *     segmented batches and batches of separate merges (2, 256 x 15).
  *   cm_set_search: co-rank search of the per-thread searches inside a
  *     block and of the one-level boundary pass: 0 = Algorithm 1, 1 = plain
  *     bisection over the diagonal (default).  Both return the unique pair

@@ -51,10 +51,10 @@ int size_class(uint64_t N) { return N ? 64 - __builtin_clzll(N) : 0; }
 // (8.3 ms for 2^28 uint32 keys against 9.9 ms at 256 x 7) and 256 x 9 for
 // uint64 keys (6.9 ms for 2^27 against 7.7 ms); a single merge of keys without payloads, 256 x 9 (within 4 % of
 // the best tile for uint32, uint64 and float32 keys at 2^27-2^28 per side,
-// where 256 x 7 is up to 39 % slower; batches of separate merges run the
-// same block merge); a segmented batch, 256 x 15 (the 65,536-segment batch:
-// 1.17 ms keys only against 1.65 ms at 256 x 7, 2.04 ms against 2.10 ms
-// with payloads).
+// where 256 x 7 is up to 39 % slower); a segmented batch and a batch of
+// separate merges, 256 x 15 (the 65,536-segment batch: 1.17 ms keys only
+// against 1.65 ms at 256 x 7, 2.04 ms against 2.10 ms with payloads; the
+// serving runtime's batches: 131k against 123k requests/s at saturation).
 constexpr int kSortCfg = 6;
 constexpr int kSortKeysCfg = 1;
 constexpr int kKeysMergeCfg = 6;
@@ -75,8 +75,8 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
     if (op == kOpMerge && auto_part && part == 4 && N >= (val ? kInBlockWideFrom : kInBlockWideKeysFrom))
       cfg = kInBlockWideCfg;
     if (op == kOpSort) cfg = (val || kt == CM_KEY_U64 || kt == CM_KEY_U64_DESC) ? kSortCfg : kSortKeysCfg;
-    if ((op == kOpMerge || op == kOpBatch) && !val) cfg = kKeysMergeCfg;
-    if (op == kOpSegmented) cfg = kSegCfg;
+    if (op == kOpMerge && !val) cfg = kKeysMergeCfg;
+    if (op == kOpSegmented || op == kOpBatch) cfg = kSegCfg;
   }
   return Choice{cfg, g_set.search, part};
 }
