@@ -178,25 +178,34 @@ def _check(status: int, where: str):
         raise CMError(status, where)
 
 
+_torch_mod = None
+_key_of_dtype = None
+
+
 def _torch():
-    import torch
-    return torch
+    global _torch_mod
+    if _torch_mod is None:
+        import torch
+        _torch_mod = torch
+    return _torch_mod
 
 
 def _key_type(t, descending: bool = False) -> int:
     """C key type of tensor t: the ascending type, or its _DESC twin."""
-    torch = _torch()
-    kt = {torch.uint32: KEY_U32, torch.uint64: KEY_U64, torch.float32: KEY_F32}.get(t.dtype)
+    global _key_of_dtype
+    if _key_of_dtype is None:
+        torch = _torch()
+        _key_of_dtype = {torch.uint32: KEY_U32, torch.uint64: KEY_U64, torch.float32: KEY_F32}
+    kt = _key_of_dtype.get(t.dtype)
     if kt is None:
         raise TypeError(f"unsupported key dtype {t.dtype} (uint32, uint64, float32)")
     return kt + (KEY_DESC_OFFSET if descending else 0)
 
 
 def _dev(t, name, dtype=None):
-    torch = _torch()
-    if not isinstance(t, torch.Tensor):
+    if not isinstance(t, _torch().Tensor):
         raise TypeError(f"{name} must be a torch tensor")
-    if t.device.type != "cuda":
+    if not t.is_cuda:
         raise ValueError(f"{name} must be on a GPU")
     if t.dim() != 1 or not t.is_contiguous():
         raise ValueError(f"{name} must be a contiguous 1-D tensor")
@@ -206,13 +215,23 @@ def _dev(t, name, dtype=None):
 
 
 def _ptr(t):
-    return None if t is None or t.numel() == 0 else ctypes.c_void_p(t.data_ptr())
+    """Device address of a tensor (None when empty): a plain int, which the
+    declared c_void_p argument types convert."""
+    return None if t is None or t.numel() == 0 else t.data_ptr()
 
 
 def _stream(stream, device):
+    """Raw HIP stream handle: the given torch stream, else the device's
+    current one (read without building a Stream object when torch offers
+    that)."""
+    if stream is not None:
+        return stream.cuda_stream
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream(device)
-    return ctypes.c_void_p(s.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        index = device.index if device.index is not None else torch.cuda.current_device()
+        return raw(index)
+    return torch.cuda.current_stream(device).cuda_stream
 
 
 def merge_workspace_size(key_dtype, with_payload: bool, m: int, n: int) -> int:
@@ -228,12 +247,17 @@ def segmented_workspace_size(key_dtype, with_payload: bool, total_a: int, total_
 
 
 def _workspace(nbytes, device, workspace):
-    torch = _torch()
+    """(workspace, its bytes): the caller's, or a new one of `nbytes` bytes
+    (nbytes may be a callable, asked only when no workspace is given; the
+    library checks a given workspace's size itself)."""
+    if workspace is not None:
+        return workspace, workspace.numel() * workspace.element_size()
+    if callable(nbytes):
+        nbytes = nbytes()
     if nbytes == 0:
         return None, 0
-    if workspace is None:
-        workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-    return workspace, workspace.numel() * workspace.element_size()
+    torch = _torch()
+    return torch.empty(nbytes, dtype=torch.uint8, device=device), nbytes
 
 
 def co_rank_host(i: int, A, B, descending=False):
@@ -293,7 +317,7 @@ def stable_merge(A, B, C=None, workspace=None, stream=None, descending=False):
     if C.numel() != m + n:
         raise ValueError("C must hold m + n keys")
     kt = _key_type(A, descending)
-    ws, wsb = _workspace(load().cm_merge_workspace_size(kt, 0, m, n), A.device, workspace)
+    ws, wsb = _workspace(lambda: load().cm_merge_workspace_size(kt, 0, m, n), A.device, workspace)
     _check(load().cm_stable_merge(kt, _ptr(A), m, _ptr(B), n, _ptr(C), _ptr(ws), wsb,
                                   _stream(stream, A.device)), "cm_stable_merge")
     return C
@@ -319,7 +343,7 @@ def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, s
     if C.numel() != m + n or C_val.numel() != m + n:
         raise ValueError("C and C_val must hold m + n elements")
     kt = _key_type(A, descending)
-    ws, wsb = _workspace(load().cm_merge_workspace_size(kt, 1, m, n), A.device, workspace)
+    ws, wsb = _workspace(lambda: load().cm_merge_workspace_size(kt, 1, m, n), A.device, workspace)
     _check(load().cm_stable_merge_pairs(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n,
                                         _ptr(C), _ptr(C_val), _ptr(ws), wsb,
                                         _stream(stream, A.device)), "cm_stable_merge_pairs")
