@@ -160,7 +160,7 @@ def batched_leg(steps, warmup, tune):
     Cv = torch.empty(n, dtype=torch.uint32, device=dev)
     ws = torch.empty(cm.segmented_workspace_size("uint32", True, A.numel(), B.numel(),
                                                  a_off.numel() - 1), dtype=torch.uint8, device=dev)
-    tuned = cm.autotune_segmented(A, a_off, B, b_off, Av, Bv, reps=3) if tune else None
+    tuned = cm.autotune_segmented(A, a_off, B, b_off, Av, Bv, reps=5) if tune else None
     if tuned is not None:
         log(f"batched: autotuned choice (config, search, partition): {tuned}")
     choice = cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, n)
@@ -929,7 +929,7 @@ def main():
                                       stream=stream)
 
         def tune():
-            return cm.autotune_segmented(A, a_off, B, b_off, Av, Bv, reps=3)
+            return cm.autotune_segmented(A, a_off, B, b_off, Av, Bv, reps=5)
     else:  # the step is one single-merge call
         ws = torch.empty(max(cm.merge_workspace_size(key_dtype, True, m, n), 1),
                          dtype=torch.uint8, device=dev)
@@ -939,7 +939,7 @@ def main():
             cm.stable_merge_pairs(A, Av, B, Bv, C, Cv, workspace=ws, stream=stream)
 
         def tune():
-            return cm.autotune_merge(A, B, Av, Bv, reps=3)
+            return cm.autotune_merge(A, B, Av, Bv, reps=5)
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.uint32, device=dev)
