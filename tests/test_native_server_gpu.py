@@ -260,3 +260,22 @@ def test_native_server_host_request_errors():
     assert done[0].ticket == tk and done[0].status == 0
     srv.release(tk)
     srv.close()
+
+
+def test_native_server_close_with_host_requests_in_flight():
+    """Closing the server while host requests are admitted, merging or on
+    their way back finishes them first: afterwards every one that was
+    admitted has its outputs in host memory, equal to the oracle's."""
+    import torch
+    reqs = make_requests(12, seed=33, lo=1 << 12, hi=1 << 16)
+    srv = serve.NativeServer("uint32", True, arena_bytes=1 << 26, max_batch=4, max_inflight=2,
+                             max_requests=16)
+    tickets = []
+    for d in reqs:
+        ts = [torch.from_numpy(d[k]).pin_memory() for k in ("A", "B", "Av", "Bv")]
+        tickets.append(srv.submit_host(ts[0], ts[1], ts[2], ts[3]))
+    outs = [srv.host_outputs(t) for t in tickets]
+    srv.close()  # no poll: shutdown itself must drain the copies back
+    for d, (C, Cv) in zip(reqs, outs):
+        Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        assert same_bits(C.numpy(), Ce) and same_bits(Cv.numpy(), Cve)
