@@ -181,7 +181,8 @@ bool inputs_ready(const Request& r) {
 }
 
 // Launch up to max_batch admitted requests whose inputs are in place, in
-// admission order, on slot b (scheduler thread); requests still waiting
+// admission order, on slot b (scheduler thread, mu not held: the batch
+// counters are the caller's to update under mu); requests still waiting
 // for their inputs stay admitted, so a batch never holds a slot while it
 // waits for a copy.  Returns the number launched.
 uint32_t launch(cm_server* s, Slot& b) {
@@ -247,8 +248,6 @@ uint32_t launch(cm_server* s, Slot& b) {
   }
   b.status = rc;
   b.busy = true;
-  s->st.batches += 1;
-  s->st.max_batch_seen = std::max<uint64_t>(s->st.max_batch_seen, n);
   return n;
 }
 
@@ -320,11 +319,14 @@ void scheduler(cm_server* s) {
       continue;
     }
     lk.unlock();
-    bool progressed = false;
+    std::vector<uint32_t> launched;  // batch sizes, counted under mu below
     for (Slot& b : s->slots) {
       if (s->admitted.empty()) break;
-      if (!b.busy && launch(s, b) > 0) progressed = true;
+      if (b.busy) continue;
+      const uint32_t n = launch(s, b);
+      if (n > 0) launched.push_back(n);
     }
+    bool progressed = !launched.empty();
     struct Finished {
       Slot* b;
       int status;
@@ -355,6 +357,10 @@ void scheduler(cm_server* s) {
       s->outgoing.pop_back();
     }
     lk.lock();
+    for (const uint32_t n : launched) {
+      s->st.batches += 1;
+      s->st.max_batch_seen = std::max<uint64_t>(s->st.max_batch_seen, n);
+    }
     for (const Finished& f : finished) {
       if (f.timed) s->intervals.emplace_back(f.t0, f.t1);
       finish(s, *f.b, f.status);
