@@ -337,12 +337,16 @@ int cm_autotune_segmented(int key_type,
  * Tuning table.  Entries map (op, key_type, with_payload, size class) to
  * {config, search, partition}; op 0 = single merge, 1 = segmented batch,
  * 2 = batch of separate merges (size class of its total output count),
- * 3 = stable sort (size class of n; the partition field is unused);
+ * 3 = stable sort (size class of n; the partition field is unused).  A
+ * segmented batch takes partition 0 as the one-level pass and any other
+ * value as the two-level pass; a batch of separate merges always co-ranks
+ * its block boundaries in one level, whatever the entry says;
  * the size class of a merge of N outputs is the bit length of N (0..64).
  * A merge call uses the entry of its size class when there is one, else
  * the settings of cm_set_config / cm_set_search / cm_set_partition.
  *   cm_tuning_set: add or replace one entry.
- *   cm_tuning_get: choice[0..2] that a call of N outputs would use now.
+ *   cm_tuning_get: choice[0..2] that a call of N outputs would use now
+ *     (CM_EINVAL for an unknown op).
  *   cm_tuning_save / cm_tuning_load: text file, one entry per line
  *     "op key_type with_payload size_class config search partition ms";
  *     load merges the file into the table (CM_EINVAL on a malformed line,

@@ -707,12 +707,13 @@ int cm_tuning_set(int op, int key_type, int with_payload, int size_cls, int conf
 }
 
 int cm_tuning_get(int op, int key_type, int with_payload, uint64_t num_outputs, int* choice) {
+  if (op < kOpMerge || op > kOpSort) return CM_EINVAL;
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (!choice) return CM_EINVAL;
   const Choice ch = resolve(op, key_type, with_payload != 0, num_outputs);
   choice[0] = ch.cfg;
   choice[1] = ch.search;
-  choice[2] = ch.partition;
+  choice[2] = op == kOpBatch ? 0 : ch.partition;  // a batch always takes the one-level pass (batch_choice)
   return CM_OK;
 }
 

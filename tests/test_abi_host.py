@@ -185,6 +185,12 @@ def test_tuning_table_host_logic(tmp_path):
     assert cm.tuning_get(cm.OP_MERGE, "uint32", False, (1 << 24) - 1)[2] == 4
     assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1 << 24)[2] == 2
     assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1000)[2] == 2
+    # a batch of separate merges always co-ranks its boundaries in one level
+    assert cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 30)[2] == 0
+    with pytest.raises(cm.CMError):
+        cm.tuning_get(cm.OP_SORT + 1, "uint32", True, 1000)
+    with pytest.raises(cm.CMError):
+        cm.tuning_get(-1, "uint32", True, 1000)
     cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, 3, 0, 0)  # size class 10: N in [512, 1024)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000) == (3, 0, 0)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1024) == default
