@@ -424,7 +424,7 @@ int cm_stable_merge_segmented_each(int key_type,
  *   events on its stream before its first kernel, between its co-rank pass
  *   and its block-merge kernel, and after the block-merge kernel.  Creates
  *   the events (no device memory is allocated).  CM_EINVAL if capacity is 0
- *   or timing is already on.
+ *   or above 2^20, or timing is already on.
  * cm_timing_stop: waits for the recorded events, writes the number of timed
  *   calls and the mean duration in milliseconds of the co-rank pass and of
  *   the block-merge kernel over them, and releases the events.  If
@@ -473,7 +473,8 @@ int cm_timing_stop(uint32_t *calls, double *co_rank_ms_mean, double *merge_ms_me
  *   for i < N (device arrays; records contiguous).  Moves 16-, 8- or 4-byte
  *   words when width and every base allow.  A code past its array leaves
  *   out[i] untouched.  CM_EINVAL (width 0, null pointer with a nonzero
- *   size, m or n >= 2^31), CM_EALIAS (out overlaps an input), CM_EHIP.
+ *   size, m or n >= 2^31, N or m + n records of `width` bytes past 2^64
+ *   bytes), CM_EALIAS (out overlaps an input), CM_EHIP.
  */
 int cm_origin_codes(uint64_t m, uint64_t n, uint32_t *A_codes, uint32_t *B_codes,
                     hipStream_t stream);

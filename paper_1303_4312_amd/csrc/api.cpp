@@ -905,7 +905,7 @@ int cm_origin_codes(uint64_t m, uint64_t n, uint32_t* A_codes, uint32_t* B_codes
 int cm_gather_records(const uint32_t* codes, uint64_t N, const void* A_rec, uint64_t m, const void* B_rec,
                       uint64_t n, uint64_t width, void* out, hipStream_t stream) {
   if (width == 0 || (N && (!codes || !out)) || (m && !A_rec) || (n && !B_rec) || m >= (1ull << 31) ||
-      n >= (1ull << 31) || (N && width > UINT64_MAX / N))
+      n >= (1ull << 31) || (N && width > UINT64_MAX / N) || (m + n && width > UINT64_MAX / (m + n)))
     return CM_EINVAL;
   if (any_overlap({{out, N * width}}, {{codes, N * 4}, {A_rec, m * width}, {B_rec, n * width}})) return CM_EALIAS;
   if (N == 0) return CM_OK;
@@ -965,7 +965,7 @@ int cm_stable_sort_pairs(int key_type, const void* keys, const uint32_t* vals, u
 }
 
 int cm_timing_start(uint32_t capacity) {
-  if (capacity == 0 || g_timing.on) return CM_EINVAL;
+  if (capacity == 0 || capacity > (1u << 20) || g_timing.on) return CM_EINVAL;
   g_timing.ev = new hipEvent_t[3ull * capacity];
   for (uint64_t x = 0; x < 3ull * capacity; ++x) {
     if (hipEventCreate(&g_timing.ev[x]) != hipSuccess) {

@@ -287,6 +287,7 @@ def test_timing_argument_errors():
     u = ctypes.c_uint32()
     d = ctypes.c_double()
     assert lib.cm_timing_start(0) == EINVAL
+    assert lib.cm_timing_start((1 << 20) + 1) == EINVAL
     assert lib.cm_timing_stop(ctypes.byref(u), ctypes.byref(d), ctypes.byref(d), None, None,
                               None) == EINVAL
 
@@ -398,6 +399,9 @@ def test_records_argument_errors():
     assert lib.cm_gather_records(P(0x1000), 10, P(0x2000), 5, P(0x3000), 5, 8, P(0x2000),
                                  None) == EALIAS
     assert lib.cm_gather_records(None, 0, None, 0, None, 0, 8, None, None) == OK
+    # records past 2^64 bytes: one output, but a side whose records overflow
+    assert lib.cm_gather_records(P(0x1000), 1, P(0x2000), 5, P(0x3000), 5, 1 << 62,
+                                 P(0x4000), None) == EINVAL
 
 
 def test_copy_tiles_argument_errors():
