@@ -34,6 +34,8 @@
  *   - Output arrays must not overlap input arrays (CM_EALIAS).  A and B may
  *     overlap each other (both are only read).  A null pointer with a
  *     nonzero length is CM_EINVAL.  Zero lengths are valid.
+ *   - Every device array holds fewer than 2^48 elements (CM_EINVAL
+ *     otherwise), and a call's tile count stays below 2^31.
  */
 #ifndef CORANK_MERGE_H
 #define CORANK_MERGE_H

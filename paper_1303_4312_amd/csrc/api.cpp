@@ -173,7 +173,7 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
                uint64_t n, void* C, uint32_t* Cv, void* ws, size_t ws_bytes, hipStream_t st,
                const Choice* forced = nullptr, bool dry_run = false) {
   if (!key_type_ok(kt)) return CM_EDTYPE;
-  if (m + n < m) return CM_EINVAL;
+  if (!lengths_ok(m, n)) return CM_EINVAL;
   const uint64_t N = m + n;
   const size_t ks = key_bytes(kt);
   if ((m && !A) || (n && !B) || (N && !C)) return CM_EINVAL;
@@ -223,7 +223,7 @@ int seg_impl(int kt, const void* A, const uint32_t* Av, const uint64_t* a_off, u
              void* ws, size_t ws_bytes, hipStream_t st, const Choice* forced = nullptr, bool dry_run = false) {
   if (!key_type_ok(kt)) return CM_EDTYPE;
   const bool val = Av || Bv || Cv;
-  if (total_a + total_b < total_a) return CM_EINVAL;
+  if (!lengths_ok(total_a, total_b)) return CM_EINVAL;
   const uint64_t N = total_a + total_b;
   if (val && ((total_a && !Av) || (total_b && !Bv) || (N && !Cv))) return CM_EINVAL;
   if (S >= (1ull << 32)) return CM_EINVAL;
@@ -259,7 +259,10 @@ int seg_impl(int kt, const void* A, const uint32_t* Av, const uint64_t* a_off, u
 // Block size a batch of separate merges uses (from its total output count).
 Choice batch_choice(int kt, bool val, const cm_merge_desc* d, uint32_t count) {
   uint64_t N = 0;
-  for (uint32_t r = 0; r < count; ++r) N += d[r].m + d[r].n;
+  for (uint32_t r = 0; r < count; ++r) {  // saturating: only the size class matters here
+    const uint64_t x = d[r].m + d[r].n;
+    N = (x < d[r].m || N + x < N) ? UINT64_MAX : N + x;
+  }
   Choice ch = resolve(kOpBatch, kt, val, N);
   ch.partition = 0;  // per-merge boundaries: one-level pass
   return ch;
@@ -278,7 +281,7 @@ size_t sort_ws_bytes(int kt, bool val, uint64_t N) {
 int sort_impl(int kt, bool val, const void* X, const uint32_t* Xv, uint64_t N, void* Y, uint32_t* Yv, void* ws,
               size_t ws_bytes, hipStream_t st) {
   if (!key_type_ok(kt)) return CM_EDTYPE;
-  if (N && (!X || !Y)) return CM_EINVAL;
+  if (!lengths_ok(N, 0) || (N && (!X || !Y))) return CM_EINVAL;
   if (val && N && (!Xv || !Yv)) return CM_EINVAL;
   if (N == 0) return CM_OK;
   const size_t ks = key_bytes(kt);
@@ -388,7 +391,7 @@ int cm_version(void) { return 2; }
 int cm_co_rank(int key_type, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m, const void* B,
                uint64_t n, uint64_t* j_out, hipStream_t stream) {
   if (!key_type_ok(key_type)) return CM_EDTYPE;
-  if (m + n < m) return CM_EINVAL;
+  if (!lengths_ok(m, n) || !lengths_ok(q, 0)) return CM_EINVAL;
   if ((m && !A) || (n && !B) || (q && (!ranks || !j_out))) return CM_EINVAL;
   const size_t ks = key_bytes(key_type);
   if (any_overlap({{j_out, q * 8}}, {{ranks, q * 8}, {A, m * ks}, {B, n * ks}})) return CM_EALIAS;
@@ -467,9 +470,10 @@ int cm_batch_prepare(int key_type, int with_payload, cm_merge_desc* descs, uint3
   const uint64_t T = tile_size(ch.cfg);
   uint64_t blocks = 0;
   for (uint32_t r = 0; r < count; ++r) {
-    if (descs[r].m + descs[r].n < descs[r].m) return CM_EINVAL;
+    if (!lengths_ok(descs[r].m, descs[r].n)) return CM_EINVAL;
     descs[r].first_block = blocks;
     blocks += (descs[r].m + descs[r].n + T - 1) / T;
+    if (blocks >= (1ull << 31)) return CM_EINVAL;  // checked per merge: the sum cannot wrap
   }
   *total_blocks = blocks;
   return CM_OK;
@@ -496,13 +500,14 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
   bool vec = true;  // every array of every merge 16-byte aligned
   for (uint32_t r = 0; r < count; ++r) {
     const cm_merge_desc& q = descs_host[r];
-    if (q.m + q.n < q.m) return CM_EINVAL;
+    if (!lengths_ok(q.m, q.n)) return CM_EINVAL;
     const uint64_t N = q.m + q.n;
     if ((q.m && !q.A) || (q.n && !q.B) || (N && !q.C)) return CM_EINVAL;
     if (val && ((q.m && !q.A_val) || (q.n && !q.B_val) || (N && !q.C_val))) return CM_EINVAL;
     if (!val && (q.A_val || q.B_val || q.C_val)) return CM_EINVAL;
     if (q.first_block != blocks) return CM_EINVAL;
     blocks += (N + T - 1) / T;
+    if (blocks >= (1ull << 31)) return CM_EINVAL;
     vec = vec && (val ? all_aligned16({q.A, q.B, q.C, q.A_val, q.B_val, q.C_val}) : all_aligned16({q.A, q.B, q.C}));
     outs.push_back({q.C, N * ks});
     if (val) outs.push_back({q.C_val, N * 4});
@@ -923,7 +928,7 @@ int cm_merge_partition_ablation(int key_type, const void* A, const uint32_t* A_v
                                 hipStream_t stream) {
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   const bool val = A_val || B_val || C_val;
-  if (m + n < m || P < 2 || (P & 1) || P > (1u << 20) || (partition != 0 && partition != 1) || !bounds)
+  if (!lengths_ok(m, n) || P < 2 || (P & 1) || P > (1u << 20) || (partition != 0 && partition != 1) || !bounds)
     return CM_EINVAL;
   const uint64_t N = m + n;
   const size_t ks = key_bytes(key_type);

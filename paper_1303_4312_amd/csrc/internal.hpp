@@ -40,6 +40,11 @@ struct Choice {
                   // each block co-ranks its own ends
 };
 constexpr int kMaxPartition = 4;
+// Every device array of a call holds fewer elements than this, so that no
+// byte count or index sum of the host-side checks can wrap (2^48 elements of
+// 8 bytes is far beyond one GPU's memory).
+constexpr uint64_t kMaxLen = 1ull << 48;
+inline bool lengths_ok(uint64_t a, uint64_t b) { return a < kMaxLen && b < kMaxLen; }
 // Automatic boundary pass: single merges of fewer outputs than this skip the
 // pass (mode 4); larger ones, and batches, use the two-level pass (mode 2).
 // Measured on MI355X (uint32 pairs, back-to-back calls): with the 512 x 11

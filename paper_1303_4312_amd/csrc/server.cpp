@@ -510,7 +510,7 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
 int cm_server_submit_host(cm_server* s, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
                           const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, uint64_t* ticket) {
   if (!s || !ticket) return CM_EINVAL;
-  if (m + n < m) return CM_EINVAL;
+  if (!cm::lengths_ok(m, n)) return CM_EINVAL;
   const uint64_t N = m + n;
   if ((m && !A) || (n && !B) || (N && !C)) return CM_EINVAL;
   if (s->val ? ((m && !A_val) || (n && !B_val) || (N && !C_val)) : (A_val || B_val || C_val)) return CM_EINVAL;
@@ -546,7 +546,7 @@ int cm_server_submit(cm_server* s, const void* A, const uint32_t* A_val, uint64_
                      const uint32_t* B_val, uint64_t n, hipStream_t inputs_stream, int inputs_pending,
                      uint64_t* ticket) {
   if (!s || !ticket) return CM_EINVAL;
-  if (m + n < m) return CM_EINVAL;
+  if (!cm::lengths_ok(m, n)) return CM_EINVAL;
   const uint64_t N = m + n;
   if ((m && !A) || (n && !B)) return CM_EINVAL;
   if (s->val ? ((m && !A_val) || (n && !B_val)) : (A_val || B_val)) return CM_EINVAL;

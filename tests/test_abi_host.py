@@ -110,6 +110,14 @@ def test_merge_argument_errors_are_synchronous():
                                          big, None) == EINVAL
     assert lib.cm_stable_merge_segmented(0, A, None, P(0x70000000), 4, B, None, P(0x71000000), 4,
                                          1 << 32, C, None, ws, big, None) == EINVAL
+    # arrays of 2^48 elements or more (byte counts would wrap), even with room
+    huge = 1 << 48
+    assert lib.cm_stable_merge(0, A, huge, B, 4, C, ws, big, None) == EINVAL
+    assert lib.cm_stable_merge(0, A, 4, B, (1 << 64) - 1, C, ws, big, None) == EINVAL
+    assert lib.cm_stable_merge_segmented(0, A, None, P(0x70000000), huge, B, None, P(0x71000000),
+                                         4, 1, C, None, ws, big, None) == EINVAL
+    assert lib.cm_co_rank(0, P(0x80000000), 1, A, huge, B, 4, P(0x90000000), None) == EINVAL
+    assert lib.cm_stable_sort(0, A, huge, C, ws, big, None) == EINVAL
     # co_rank on device arrays
     assert lib.cm_co_rank(0, None, 3, A, 4, B, 4, P(0x80000000), None) == EINVAL
     assert lib.cm_co_rank(0, P(0x80000000), 4, A, 4, B, 4, P(0x80000000 + 8), None) == EALIAS
@@ -280,6 +288,19 @@ def test_batch_prepare_and_argument_errors():
     assert lib.cm_stable_merge_batch(0, 0, pay.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
                                      total.value, P(0x2000), need, None) == EINVAL
     assert lib.cm_stable_merge_batch(0, 0, None, None, 0, 0, None, 0, None) == OK
+    # a batch whose block count reaches 2^31 is refused (checked merge by
+    # merge, so the running sum cannot wrap); one such merge alone is fine
+    many = np.zeros(64, dtype=descs.dtype)
+    for r in range(64):
+        many[r] = (base + r * (1 << 44), 0, (1 << 40) - 1, base + r * (1 << 44) + (1 << 43), 0,
+                   1, base + r * (1 << 44) + (3 << 42), 0, 0)
+    assert lib.cm_batch_prepare(0, 0, many.ctypes.data_as(ctypes.c_void_p), 64,
+                                ctypes.byref(total)) == EINVAL
+    assert lib.cm_batch_prepare(0, 0, many.ctypes.data_as(ctypes.c_void_p), 1,
+                                ctypes.byref(total)) == OK
+    many["m"][5] = 1 << 48  # a side of 2^48 elements
+    assert lib.cm_batch_prepare(0, 0, many[5:].ctypes.data_as(ctypes.c_void_p), 1,
+                                ctypes.byref(total)) == EINVAL
 
 
 def test_timing_argument_errors():
