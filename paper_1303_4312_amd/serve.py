@@ -414,6 +414,19 @@ class NativeServer:
             from . import CMError
             raise CMError(rc, where)
 
+    def _check_inputs(self, A, B, A_val, B_val):
+        # the runtime reads m (n) keys and payloads from these addresses: a
+        # shorter payload array would be read past its end
+        if A.dtype != self.key_dtype or B.dtype != self.key_dtype:
+            raise TypeError(f"keys must be {self.key_dtype}")
+        if not self.with_payload:
+            if A_val is not None or B_val is not None:
+                raise ValueError("this server has no payloads")
+            return
+        if A_val.dtype != self.torch.uint32 or B_val.dtype != self.torch.uint32 \
+                or A_val.numel() != A.numel() or B_val.numel() != B.numel():
+            raise ValueError("payloads must be uint32 and as long as their keys")
+
     def submit_ptrs(self, A, A_val, m, B, B_val, n, stream=None, pending=False):
         """Raw form (device addresses and sizes); returns the status and
         sets self.last_ticket on success (CM_EBUSY = -9: no slot free)."""
@@ -430,10 +443,7 @@ class NativeServer:
         for t in (A, B) + ((A_val, B_val) if self.with_payload else ()):
             if t is None or t.device != self.device or t.dim() != 1 or not t.is_contiguous():
                 raise ValueError("inputs must be contiguous 1-D tensors on the server's device")
-        if A.dtype != self.key_dtype or B.dtype != self.key_dtype:
-            raise TypeError(f"keys must be {self.key_dtype}")
-        if not self.with_payload and (A_val is not None or B_val is not None):
-            raise ValueError("this server has no payloads")
+        self._check_inputs(A, B, A_val, B_val)
         s = stream if stream is not None else torch.cuda.current_stream(self.device)
         rc = self.submit_ptrs(A.data_ptr() if A.numel() else None,
                               A_val.data_ptr() if self.with_payload and A.numel() else None,
@@ -458,19 +468,18 @@ class NativeServer:
             if t is None or not isinstance(t, torch.Tensor) or t.device.type != "cpu" \
                     or t.dim() != 1 or not t.is_contiguous():
                 raise ValueError("inputs must be contiguous 1-D CPU tensors")
-        if A.dtype != self.key_dtype or B.dtype != self.key_dtype:
-            raise TypeError(f"keys must be {self.key_dtype}")
-        if not self.with_payload and (A_val is not None or B_val is not None):
-            raise ValueError("this server has no payloads")
+        self._check_inputs(A, B, A_val, B_val)
         N = A.numel() + B.numel()
         if C is None:
             C = torch.empty(N, dtype=self.key_dtype).pin_memory()
         if self.with_payload and C_val is None:
             C_val = torch.empty(N, dtype=torch.uint32).pin_memory()
-        outs = (C,) + ((C_val,) if self.with_payload else ())
-        for t in outs:
-            if t.device.type != "cpu" or not t.is_contiguous() or t.numel() != N:
-                raise ValueError("outputs must be contiguous CPU tensors of m + n elements")
+        outs = ((C, self.key_dtype),) + (((C_val, torch.uint32),) if self.with_payload else ())
+        for t, dtype in outs:
+            if not isinstance(t, torch.Tensor) or t.device.type != "cpu" or not t.is_contiguous() \
+                    or t.numel() != N or t.dtype != dtype:
+                raise ValueError("outputs must be contiguous CPU tensors of m + n elements "
+                                 "(keys of the server's key type, uint32 payloads)")
 
         def ptr(t):
             return t.data_ptr() if t is not None and t.numel() else None

@@ -249,6 +249,19 @@ def test_native_server_host_request_errors():
     big, G = 1 << 17, 1 << 32
     assert lib.cm_server_submit_host(srv._h, G, 2 * G, big, 3 * G, 4 * G, big, 5 * G, 6 * G,
                                      ctypes.byref(t)) == -5
+    # payloads shorter than their keys, or outputs of another type, are
+    # refused by the binding before the runtime could read or write past them
+    with pytest.raises(ValueError):
+        srv.submit_host(A, B, A[:1000], B)
+    with pytest.raises(ValueError):
+        srv.submit_host(A, B, A, B, C=C.view(torch.int32))
+    with pytest.raises(ValueError):
+        srv.submit_host(A, B, A, B, C_val=torch.zeros(2048, dtype=torch.uint8).pin_memory())
+    dA = A.cuda()
+    with pytest.raises(ValueError):
+        srv.submit(dA, dA, dA[:1023], dA)
+    with pytest.raises(ValueError):
+        srv.submit(dA, dA, dA.view(torch.int32), dA)
     # an empty host request completes
     e = torch.zeros(0, dtype=torch.uint32)
     tk = srv.submit_host(e, e, e, e)
