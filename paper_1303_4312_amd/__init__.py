@@ -251,6 +251,10 @@ def _workspace(nbytes, device, workspace):
     (nbytes may be a callable, asked only when no workspace is given; the
     library checks a given workspace's size itself)."""
     if workspace is not None:
+        torch = _torch()
+        if not isinstance(workspace, torch.Tensor) or not workspace.is_cuda \
+                or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous tensor on the GPU")
         return workspace, workspace.numel() * workspace.element_size()
     if callable(nbytes):
         nbytes = nbytes()
