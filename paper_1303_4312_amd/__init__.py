@@ -646,9 +646,11 @@ def set_fine_lanes(lanes: int):
     _check(load().cm_set_fine_lanes(lanes), "cm_set_fine_lanes")
 
 
-def set_block_order(xcd_contiguous: int):
-    """1: each XCD gets a contiguous run of blocks; 0: workgroup order."""
-    _check(load().cm_set_block_order(xcd_contiguous), "cm_set_block_order")
+def set_block_order(order: int):
+    """Block order of single merges, sort passes and copy_tiles: c >= 2
+    (default 32) runs of c blocks per XCD, 1 one contiguous run per XCD,
+    0 workgroup order."""
+    _check(load().cm_set_block_order(order), "cm_set_block_order")
 
 
 # ---------------------------------------------------------------------------

@@ -593,9 +593,9 @@ int cm_set_fine_lanes(int lanes) {
   return CM_OK;
 }
 
-int cm_set_block_order(int xcd_contiguous) {
-  if (xcd_contiguous != 0 && xcd_contiguous != 1) return CM_EINVAL;
-  g_set.shape.xcd_order = xcd_contiguous;
+int cm_set_block_order(int order) {
+  if (order < 0 || order > (1 << 20)) return CM_EINVAL;
+  g_set.shape.xcd_order = order;
   return CM_OK;
 }
 

@@ -61,7 +61,13 @@ constexpr int kInBlockWideCfg = 7;                     // 512 x 11
 // Launch-shape settings that never change results.
 struct Shape {
   uint32_t coarse_stride = 64;  // blocks between coarse boundaries
-  int xcd_order = 1;            // XCD-contiguous block order in the block merge
+  // Block order of the single-merge kernels (block_order): runs of 32 blocks
+  // per XCD.  Measured on MI355X against one contiguous run per XCD (same
+  // process, the eight tiles): 3-6 % less time per call for the uint32 Zipf
+  // merge, 3-9 % for uint64 keys, 3-5 % for float32; runs of 64 within 1 %
+  // of 32; workgroup order 0-4 % slower than one run per XCD.  The segmented
+  // and batch kernels keep workgroup order (runs measured 1-4 % slower there).
+  int xcd_order = 32;
   int fine_lanes = 1;           // lanes per boundary in the fine pass (1: bisection; 2, 4)
 };
 

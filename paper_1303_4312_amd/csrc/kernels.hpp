@@ -265,14 +265,25 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
 }
 
 // Workgroups are handed to the 8 XCDs of the chip round-robin by index.
-// With `xcd` set, workgroup b takes block x * q + min(x, r) + b / 8 (x = b % 8,
-// q = P / 8, r = P % 8): a bijection of [0, P) that gives every XCD one
-// contiguous run of blocks, so neighbouring blocks, which share the cache
-// lines at their window edges, run under the same L2.
+// block_order is a bijection of [0, P) that hands each XCD runs of
+// neighbouring blocks, which share the cache lines at their window edges,
+// so that they run under the same L2.  xcd = 1: workgroup b takes block
+// x * q + min(x, r) + b / 8 (x = b % 8, q = P / 8, r = P % 8), one contiguous
+// run per XCD, so eight distant address ranges stream at once.  xcd = c >= 2:
+// runs of c blocks, the XCDs side by side, so the blocks in flight at any
+// time cover one narrow address range (measured faster: see Shape).
 __device__ __forceinline__ uint64_t block_order(uint64_t b, uint64_t P, int xcd) {
   if (!xcd) return b;
-  const uint64_t x = b & 7, q = P >> 3, r = P & 7;
-  return x * q + (x < r ? x : r) + (b >> 3);
+  if (xcd == 1) {
+    const uint64_t x = b & 7, q = P >> 3, r = P & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+  }
+  // runs of c = xcd tiles: in each group of 8c tiles, XCD x takes tiles
+  // [x c, (x + 1) c); a last partial group keeps workgroup order
+  const uint64_t c = (uint64_t)xcd, group = 8 * c, g = b / group;
+  if ((g + 1) * group > P) return b;
+  const uint64_t w = b - g * group;
+  return g * group + (w & 7) * c + (w >> 3);
 }
 
 template <typename K, bool VAL, int NT, int E, bool VEC>

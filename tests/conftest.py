@@ -34,7 +34,7 @@ def restore_settings():
     cm.set_search(search)
     cm.set_partition(partition)
     cm.set_coarse_stride(64)
-    cm.set_block_order(1)
+    cm.set_block_order(32)  # the default
     cm.set_fine_lanes(1)
     for (kt, v), c in cfgs.items():
         cm.set_config(kt, v, c)

@@ -140,6 +140,11 @@ def test_config_table(restore_settings):
     cm.set_config("uint32", True, old)
     assert cm.load().cm_set_config(0, 1, n) == ECONFIG
     assert cm.load().cm_set_search(2) == EINVAL
+    # block order: workgroup order, one run per XCD, or runs of up to 2^20 blocks
+    for order in (0, 1, 2, 32, 1 << 20):
+        assert cm.load().cm_set_block_order(order) == OK
+    assert cm.load().cm_set_block_order(-1) == EINVAL
+    assert cm.load().cm_set_block_order((1 << 20) + 1) == EINVAL
     for mode in range(-1, 5):
         cm.set_partition(mode)
         assert cm.get_partition() == mode

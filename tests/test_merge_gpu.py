@@ -78,11 +78,13 @@ def test_all_configs_pairs_and_keys(dtype, search, partition):
 
 @pytest.mark.parametrize("partition,stride,xcd,lanes", [
     (0, 64, 1, 1), (1, 64, 1, 1), (2, 64, 0, 1), (1, 16, 0, 1), (2, 16, 1, 1), (3, 64, 1, 1),
-    (4, 64, 1, 1), (4, 64, 0, 1), (2, 64, 1, 2), (2, 16, 0, 4), (1, 64, 1, 4), (2, 64, 1, 4)])
+    (4, 64, 1, 1), (4, 64, 0, 1), (2, 64, 1, 2), (2, 16, 0, 4), (1, 64, 1, 4), (2, 64, 1, 4),
+    (2, 64, 32, 1), (2, 64, 2, 1), (1, 16, 3, 1), (4, 64, 8, 1), (0, 64, 5, 1)])
 def test_two_level_partition_edges(partition, stride, xcd, lanes):
     """Block counts around multiples of the coarse stride, with the co-rank
-    windows of the fine pass both wide and degenerate; both block orders;
-    1, 2 or 4 lanes per fine boundary."""
+    windows of the fine pass both wide and degenerate; every block order
+    (workgroup order, one run per XCD, runs of c blocks with full groups
+    and a partial last group); 1, 2 or 4 lanes per fine boundary."""
     cm.set_partition(partition)
     cm.set_coarse_stride(stride)
     cm.set_block_order(xcd)
