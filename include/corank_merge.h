@@ -286,14 +286,15 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *   cm_set_fine_lanes: lanes that search each boundary of the two-level
  *     pass's fine step inside its coarse window: 1 = bisection, 2 or 4 = a
  *     ternary or 5-ary search (fewer dependent rounds, more lanes).
- *   cm_set_block_order: the order in which a single merge, a sort pass and
- *     cm_copy_tiles hand blocks to the chip's 8 XCDs (workgroups reach the
+ *   cm_set_block_order: the order in which a single merge, a batch of
+ *     separate merges, a sort pass and cm_copy_tiles hand blocks to the
+ *     chip's 8 XCDs (workgroups reach the
  *     XCDs round-robin), so that neighbouring blocks, which share the cache
  *     lines at their window edges, run under one L2: c >= 2 (default 32) =
  *     runs of c blocks per XCD, the XCDs side by side (the blocks in flight
  *     stay within one address range); 1 = one contiguous run per XCD; 0 =
  *     workgroup order.  At most 2^20 (else CM_EINVAL).  Segmented batches
- *     and batches of separate merges keep workgroup order.
+ *     keep workgroup order.
  *   The cm_get_* calls return the current setting.
  *   (Settings are process-wide and not thread-safe against concurrent
  *   merges; set them before launching.)

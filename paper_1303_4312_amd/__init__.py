@@ -647,9 +647,9 @@ def set_fine_lanes(lanes: int):
 
 
 def set_block_order(order: int):
-    """Block order of single merges, sort passes and copy_tiles: c >= 2
-    (default 32) runs of c blocks per XCD, 1 one contiguous run per XCD,
-    0 workgroup order."""
+    """Block order of single merges, batches of separate merges, sort passes
+    and copy_tiles: c >= 2 (default 32) runs of c blocks per XCD, 1 one
+    contiguous run per XCD, 0 workgroup order."""
     _check(load().cm_set_block_order(order), "cm_set_block_order")
 
 

@@ -530,7 +530,8 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
   int rc = launch_batch_co_ranks(key_type, ch, descs_dev, count, T, total_blocks + count, bj, stream);
   if (rc != CM_OK) return rc;
   timing_mark(1, stream);
-  rc = launch_batch_merge_blocks(key_type, val, ch, descs_dev, count, bj, total_blocks, vec, stream);
+  rc = launch_batch_merge_blocks(key_type, val, ch, descs_dev, count, bj, total_blocks, vec, g_set.shape.xcd_order,
+                                 stream);
   timing_mark(2, stream);
   return rc;
 }

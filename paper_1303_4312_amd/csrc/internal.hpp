@@ -61,12 +61,14 @@ constexpr int kInBlockWideCfg = 7;                     // 512 x 11
 // Launch-shape settings that never change results.
 struct Shape {
   uint32_t coarse_stride = 64;  // blocks between coarse boundaries
-  // Block order of the single-merge kernels (block_order): runs of 32 blocks
-  // per XCD.  Measured on MI355X against one contiguous run per XCD (same
-  // process, the eight tiles): 3-6 % less time per call for the uint32 Zipf
-  // merge, 3-9 % for uint64 keys, 3-5 % for float32; runs of 64 within 1 %
-  // of 32; workgroup order 0-4 % slower than one run per XCD.  The segmented
-  // and batch kernels keep workgroup order (runs measured 1-4 % slower there).
+  // Block order of the single-merge and batch kernels (block_order): runs of
+  // 32 blocks per XCD.  Measured on MI355X against one contiguous run per XCD
+  // (same process, the eight tiles): 3-6 % less time per call for the uint32
+  // Zipf merge, 3-9 % for uint64 keys, 3-5 % for float32; runs of 64 within
+  // 1 % of 32; workgroup order 0-4 % slower than one run per XCD.  A batch of
+  // 64 serving-sized merges: 1-2.5 % faster than workgroup order (8,192
+  // small merges: equal).  The segmented kernel keeps workgroup order (runs
+  // measured 1-4 % slower there).
   int xcd_order = 32;
   int fine_lanes = 1;           // lanes per boundary in the fine pass (1: bisection; 2, 4)
 };
@@ -143,7 +145,7 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
 int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
                           uint64_t* bj, hipStream_t st);
 int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
-                              const uint64_t* bj, uint64_t tiles, bool vec, hipStream_t st);
+                              const uint64_t* bj, uint64_t tiles, bool vec, int xcd, hipStream_t st);
 
 // Co-ranks of q arbitrary ranks.
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,

@@ -657,11 +657,12 @@ __global__ __launch_bounds__(256) void k_batch_co_rank(const MergeDesc* __restri
 template <typename K, bool VAL, int NT, int E, bool VEC>
 __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __restrict__ d, uint32_t count,
                                                            const uint64_t* __restrict__ bj, uint64_t num_tiles,
-                                                           int search) {
+                                                           int search, int xcd) {
   constexpr int T = NT * E;
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
   __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
-  for (uint64_t g = blockIdx.x; g < num_tiles; g += gridDim.x) {
+  for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
+    const uint64_t g = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
     const uint32_t r = desc_of(d, count, g, 0);
     const MergeDesc q = d[r];
     const uint64_t t = g - q.first_block;
@@ -670,7 +671,7 @@ __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __re
     const uint64_t slot = q.first_block + r + t;
     merge_block<K, VAL, NT, E, VEC>((const K*)q.A, q.A_val, q.m, (const K*)q.B, q.B_val, q.n, (K*)q.C, q.C_val, i0,
                                     len, bj[slot], bj[slot + 1], search, s_key, s_val);
-    if (g + gridDim.x < num_tiles) __syncthreads();
+    if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }
 

@@ -295,8 +295,8 @@ int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t coun
 }
 
 int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
-                              const uint64_t* bj, uint64_t tiles, bool vec, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::batch_merge_blocks(val, ch, d, count, bj, tiles, vec, st); });
+                              const uint64_t* bj, uint64_t tiles, bool vec, int xcd, hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::batch_merge_blocks(val, ch, d, count, bj, tiles, vec, xcd, st); });
 }
 
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,

@@ -184,22 +184,22 @@ int Launch<K>::batch_co_ranks(const Choice& ch, const void* d, uint32_t count, u
 
 template <typename K>
 int Launch<K>::batch_merge_blocks(bool val, const Choice& ch, const void* d, uint32_t count, const uint64_t* bj,
-                                  uint64_t tiles, bool vec, hipStream_t st) {
+                                  uint64_t tiles, bool vec, int xcd, hipStream_t st) {
   return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
     constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
     const dim3 g((unsigned)tiles), b(NT);
     const MergeDesc* q = (const MergeDesc*)d;
     if (val && vec)
-      hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search);
+      hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search, xcd);
     else if (val)
       hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                         ch.search);
+                         ch.search, xcd);
     else if (vec)
       hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, true>), g, b, 0, st, q, count, bj, tiles,
-                         ch.search);
+                         ch.search, xcd);
     else
       hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                         ch.search);
+                         ch.search, xcd);
     return launch_status();
   });
 }

@@ -64,6 +64,20 @@ def test_batch_all_configs():
         cm.tuning_clear()
 
 
+@pytest.mark.parametrize("order", [0, 1, 2, 3, 32])
+def test_batch_every_block_order(order, restore_settings):
+    """The batch kernel's block order (runs of c blocks per XCD with full
+    groups and a partial last group, one run per XCD, workgroup order) only
+    changes which workgroup merges which block."""
+    reqs = requests(12, seed=3, lo=1, hi=1 << 15)
+    merges = [(to_dev(d["A"]), to_dev(d["Av"]), to_dev(d["B"]), to_dev(d["Bv"])) for d in reqs]
+    cm.set_block_order(order)
+    outs = cm.stable_merge_batch(merges)
+    for d, (C, Cv) in zip(reqs, outs):
+        Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
+
+
 def test_serving_result_alone_equals_in_the_mix():
     import torch
     reqs = requests(24, seed=3)
