@@ -253,7 +253,7 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  * outputs.  Every configuration gives bit-identical results; they differ
  * only in speed.  cm_config_count() configurations are numbered from 0.
  *   cm_config_info: NT and E of configuration id (CM_ECONFIG if unknown).
- *   cm_set_config / cm_get_config: the configuration used by the merge calls
+ *   cm_set_config: the configuration used by the merge calls
  *     for (key_type, with_payload) in this process (not thread-safe against
  *     concurrent merges; set it before launching).  Until cm_set_config is
  *     called for (key_type, with_payload), the calls use configuration 0
@@ -267,8 +267,8 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
  *     -1 (default) = automatic: mode 4 for single merges of fewer than
  *     2^24 outputs (from 2^21 outputs with payloads, 2^22 keys only, with
- *     the 512 x 11 tile unless cm_set_config was called), else mode 2; 0 = one GPU thread per boundary over the
- *     whole diagonal; 1 = two levels: every coarse boundary by a whole wave
+ *     the 512 x 11 tile unless cm_set_config was called), else mode 2;
+ *     0 = one GPU thread per boundary over the whole diagonal; 1 = two levels: every coarse boundary by a whole wave
  *     with a 64-ary search, then the others by bisection between their two
  *     coarse neighbours; 2 = two levels with 16 lanes (a 16-ary search) per
  *     coarse boundary; 3 = Algorithm 2 with one block per resident workgroup:
@@ -288,14 +288,17 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     ternary or 5-ary search (fewer dependent rounds, more lanes).
  *   cm_set_block_order: the order in which a single merge, a batch of
  *     separate merges, a sort pass and cm_copy_tiles hand blocks to the
- *     chip's 8 XCDs (workgroups reach the
- *     XCDs round-robin), so that neighbouring blocks, which share the cache
- *     lines at their window edges, run under one L2: c >= 2 (default 32) =
- *     runs of c blocks per XCD, the XCDs side by side (the blocks in flight
- *     stay within one address range); 1 = one contiguous run per XCD; 0 =
- *     workgroup order.  At most 2^20 (else CM_EINVAL).  Segmented batches
- *     keep workgroup order.
- *   The cm_get_* calls return the current setting.
+ *     chip's 8 XCDs (workgroups reach the XCDs round-robin), so that
+ *     neighbouring blocks, which share the cache lines at their window
+ *     edges, run under one L2: c >= 2 (default 32) = runs of c blocks per
+ *     XCD, the XCDs side by side (the blocks in flight stay within one
+ *     address range); 1 = one contiguous run per XCD; 0 = workgroup order.
+ *     At most 2^20 (else CM_EINVAL).  Segmented batches keep workgroup
+ *     order.
+ *   cm_get_config / cm_get_search / cm_get_partition return the current
+ *     setting (cm_get_config: the value set for the pair, 0 until set, not
+ *     the per-operation default above; cm_tuning_get reports the choice a
+ *     call would actually make).
  *   (Settings are process-wide and not thread-safe against concurrent
  *   merges; set them before launching.)
  */
