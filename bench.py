@@ -296,8 +296,11 @@ def generic_order_leg(A, Av, B, Bv, reps=10):
     """The merge under the reversed key order (the step's arrays reversed,
     CM_KEY_*_DESC) against the same merge ascending, the same keys merged
     without payloads (default tile), and the merge of the same keys carrying
-    8-byte records (origin codes merged, records gathered by code).  Median whole-call times from the library's events; the record
-    merge is timed end to end with torch events (two calls)."""
+    8-byte records two ways: origin codes merged and the records gathered by
+    code, and the records moved by the merge itself as uint64 payloads
+    (cm_stable_merge_pairs64; the two outputs must be identical).  Median
+    whole-call times from the library's events; the code-and-gather path is
+    timed end to end with torch events."""
     import torch
     import paper_1303_4312_amd as cm
     N = A.numel() + B.numel()
@@ -331,6 +334,11 @@ def generic_order_leg(A, Av, B, Bv, reps=10):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     rec_ms = statistics.median(ts)
+    _, Crec = cm.merge_records(A, B, Arec, Brec)
+    Cn = torch.empty(N, dtype=torch.uint64, device=A.device)
+    nat = calls(lambda: cm.stable_merge_pairs(A, Arec.view(torch.uint64), B, Brec.view(torch.uint64), C, Cn))
+    same = bool(torch.equal(Cn.view(torch.int64), Crec.view(torch.int64)))
+    del Crec, Cn
     return {
         "ascending_call_ms": asc[0], "ascending_merge_kernel_ms": asc[1],
         "descending_call_ms": desc[0], "descending_merge_kernel_ms": desc[1],
@@ -339,6 +347,11 @@ def generic_order_leg(A, Av, B, Bv, reps=10):
         "records_8byte_ms": rec_ms,
         "records_8byte_keys_per_s": N / (rec_ms * 1e-3),
         "records_note": "codes filled, keys merged with codes, 8-byte records gathered by code",
+        "records_8byte_native_call_ms": nat[0], "records_8byte_native_merge_kernel_ms": nat[1],
+        "records_8byte_native_keys_per_s": N / (nat[0] * 1e-3),
+        "records_8byte_native_kernel_gbs": 2 * N * (A.element_size() + 8) / (nat[1] * 1e-3) / 1e9,
+        "records_8byte_native_identical": same,
+        "records_native_note": "the records as uint64 payloads of the merge (cm_stable_merge_pairs64)",
     }
 
 
@@ -1055,7 +1068,10 @@ def main():
         log(f"descending merge {go['descending_call_ms']:.3f} ms vs ascending "
             f"{go['ascending_call_ms']:.3f} ms; keys only {go['keys_only_call_ms']:.3f} ms "
             f"({go['keys_only_kernel_gbs']:.0f} GB/s); with 8-byte records "
-            f"{go['records_8byte_ms']:.3f} ms")
+            f"{go['records_8byte_ms']:.3f} ms by code and gather, "
+            f"{go['records_8byte_native_call_ms']:.3f} ms as uint64 payloads "
+            f"({go['records_8byte_native_kernel_gbs']:.0f} GB/s, identical: "
+            f"{go['records_8byte_native_identical']})")
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:

@@ -149,6 +149,24 @@ int cm_stable_merge_pairs(int key_type,
                           hipStream_t stream);
 
 /*
+ * Stable merge of (key, uint64 payload) pairs (Sections 1-3): as
+ * cm_stable_merge_pairs with 8-byte payloads (A_val: m, B_val: n, C_val:
+ * m + n uint64 device arrays), moved by the same kernels; for 8-byte
+ * records (a pointer, an index, two packed 4-byte fields) without an
+ * origin-code pass and a gather.  Same workspace
+ * (cm_merge_workspace_size(key_type, 1, m, n)), tile and boundary choice
+ * as cm_stable_merge_pairs, except that boundary mode 3 (the streaming
+ * kernel, 4-byte payloads only) runs as mode 2.
+ * Errors: CM_EINVAL, CM_EDTYPE, CM_EALIAS, CM_ENOSPC, CM_EHIP.
+ */
+int cm_stable_merge_pairs64(int key_type,
+                            const void *A, const uint64_t *A_val, uint64_t m,
+                            const void *B, const uint64_t *B_val, uint64_t n,
+                            void *C, uint64_t *C_val,
+                            void *workspace, size_t workspace_bytes,
+                            hipStream_t stream);
+
+/*
  * Batch of separately allocated merges (each one instance of the problem of
  * Section 2), run in one pass of Algorithm 2: every merge is cut into
  * blocks of the batch's block size, blocks never span two merges, and one

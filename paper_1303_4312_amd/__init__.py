@@ -45,7 +45,7 @@ KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
 
 EXPORTS = [
     "cm_status_string", "cm_version", "cm_co_rank_host", "cm_co_rank",
-    "cm_merge_workspace_size", "cm_stable_merge", "cm_stable_merge_pairs",
+    "cm_merge_workspace_size", "cm_stable_merge", "cm_stable_merge_pairs", "cm_stable_merge_pairs64",
     "cm_segmented_workspace_size", "cm_stable_merge_segmented", "cm_check_sorted",
     "cm_config_count", "cm_config_info", "cm_set_config", "cm_get_config",
     "cm_set_search", "cm_get_search", "cm_set_partition", "cm_get_partition",
@@ -98,6 +98,8 @@ def load():
         "cm_stable_merge": (c_int, [c_int, vp, c_u64, vp, c_u64, vp, vp, c_size, vp]),
         "cm_stable_merge_pairs": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp,
                                           c_size, vp]),
+        "cm_stable_merge_pairs64": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp,
+                                            c_size, vp]),
         "cm_segmented_workspace_size": (c_size, [c_int, c_int, c_u64, c_u64, c_u64]),
         "cm_stable_merge_segmented": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
                                               c_u64, vp, vp, vp, c_size, vp]),
@@ -329,28 +331,34 @@ def stable_merge(A, B, C=None, workspace=None, stream=None, descending=False):
 
 def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, stream=None,
                        descending=False):
-    """Stable merge of (key, uint32 payload) pairs; returns (C, C_val)."""
+    """Stable merge of (key, payload) pairs with uint32 payloads
+    (cm_stable_merge_pairs) or uint64 payloads (cm_stable_merge_pairs64);
+    returns (C, C_val)."""
     torch = _torch()
     A = _dev(A, "A")
     B = _dev(B, "B", A.dtype)
-    A_val = _dev(A_val, "A_val", torch.uint32)
-    B_val = _dev(B_val, "B_val", torch.uint32)
+    A_val = _dev(A_val, "A_val")
+    if A_val.dtype not in (torch.uint32, torch.uint64):
+        raise TypeError("payloads must be uint32 or uint64")
+    vt = A_val.dtype
+    B_val = _dev(B_val, "B_val", vt)
     m, n = A.numel(), B.numel()
     if A_val.numel() != m or B_val.numel() != n:
         raise ValueError("payload lengths must match key lengths")
     if C is None:
         C = torch.empty(m + n, dtype=A.dtype, device=A.device)
     if C_val is None:
-        C_val = torch.empty(m + n, dtype=torch.uint32, device=A.device)
+        C_val = torch.empty(m + n, dtype=vt, device=A.device)
     C = _dev(C, "C", A.dtype)
-    C_val = _dev(C_val, "C_val", torch.uint32)
+    C_val = _dev(C_val, "C_val", vt)
     if C.numel() != m + n or C_val.numel() != m + n:
         raise ValueError("C and C_val must hold m + n elements")
     kt = _key_type(A, descending)
     ws, wsb = _workspace(lambda: load().cm_merge_workspace_size(kt, 1, m, n), A.device, workspace)
-    _check(load().cm_stable_merge_pairs(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n,
-                                        _ptr(C), _ptr(C_val), _ptr(ws), wsb,
-                                        _stream(stream, A.device)), "cm_stable_merge_pairs")
+    fn, name = ((load().cm_stable_merge_pairs, "cm_stable_merge_pairs") if vt == torch.uint32 else
+                (load().cm_stable_merge_pairs64, "cm_stable_merge_pairs64"))
+    _check(fn(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n, _ptr(C), _ptr(C_val), _ptr(ws), wsb,
+              _stream(stream, A.device)), name)
     return C, C_val
 
 

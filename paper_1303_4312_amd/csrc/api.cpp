@@ -169,8 +169,9 @@ SegWs seg_ws(void* ws, uint64_t N) {
 // implementations
 
 // With dry_run set, only the argument checks run (nothing is launched).
-int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, const void* B, const uint32_t* Bv,
-               uint64_t n, void* C, uint32_t* Cv, void* ws, size_t ws_bytes, hipStream_t st,
+// Payloads (with val) are vb = 4 or 8 bytes wide.
+int merge_impl(int kt, bool val, int vb, const void* A, const void* Av, uint64_t m, const void* B, const void* Bv,
+               uint64_t n, void* C, void* Cv, void* ws, size_t ws_bytes, hipStream_t st,
                const Choice* forced = nullptr, bool dry_run = false) {
   if (!key_type_ok(kt)) return CM_EDTYPE;
   if (!lengths_ok(m, n)) return CM_EINVAL;
@@ -181,11 +182,11 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
   if (N == 0) return CM_OK;
   const size_t need = merge_ws_bytes(N);
   if (!ws || ws_bytes < need) return CM_ENOSPC;
-  const Span ins[] = {{A, m * ks}, {B, n * ks}, {Av, val ? m * 4 : 0}, {Bv, val ? n * 4 : 0}};
-  if (any_overlap({{C, N * ks}, {Cv, val ? N * 4 : 0}, {ws, need}},
-                  {ins[0], ins[1], ins[2], ins[3]}))
-    return CM_EALIAS;
-  const Choice ch = forced ? *forced : resolve(kOpMerge, kt, val, N);
+  const uint64_t vs = val ? (uint64_t)vb : 0;
+  const Span ins[] = {{A, m * ks}, {B, n * ks}, {Av, m * vs}, {Bv, n * vs}};
+  if (any_overlap({{C, N * ks}, {Cv, N * vs}, {ws, need}}, {ins[0], ins[1], ins[2], ins[3]})) return CM_EALIAS;
+  Choice ch = forced ? *forced : resolve(kOpMerge, kt, val, N);
+  if (vb == 8 && ch.partition == 3) ch.partition = 2;  // the streaming kernel moves 4-byte payloads only
   const uint64_t T = tile_size(ch.cfg);
   const uint64_t tiles = (N + T - 1) / T;
   if (tiles >= (1ull << 31)) return CM_EINVAL;
@@ -198,14 +199,15 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
     int rc = launch_stream_co_ranks(kt, A, m, B, n, P, bj, st);
     if (rc != CM_OK) return rc;
     timing_mark(1, st);
-    rc = launch_merge_stream(kt, val, ch, A, Av, m, B, Bv, n, C, Cv, nullptr, bj, P, st);
+    rc = launch_merge_stream(kt, val, ch, A, (const uint32_t*)Av, m, B, (const uint32_t*)Bv, n, C, (uint32_t*)Cv,
+                             nullptr, bj, P, st);
     timing_mark(2, st);
     return rc;
   }
   if (ch.partition == 4) {  // every block co-ranks its own ends: no boundary pass
     timing_mark(0, st);
     timing_mark(1, st);
-    const int rc = launch_merge_blocks(kt, val, ch, g_set.shape, A, Av, m, B, Bv, n, C, Cv, nullptr, tiles, st);
+    const int rc = launch_merge_blocks(kt, val, vb, ch, g_set.shape, A, Av, m, B, Bv, n, C, Cv, nullptr, tiles, st);
     timing_mark(2, st);
     return rc;
   }
@@ -213,7 +215,7 @@ int merge_impl(int kt, bool val, const void* A, const uint32_t* Av, uint64_t m, 
   int rc = launch_block_co_ranks(kt, ch, g_set.shape, A, m, B, n, T, tiles + 1, bj, coarse, st);
   if (rc != CM_OK) return rc;
   timing_mark(1, st);
-  rc = launch_merge_blocks(kt, val, ch, g_set.shape, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st);
+  rc = launch_merge_blocks(kt, val, vb, ch, g_set.shape, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st);
   timing_mark(2, st);
   return rc;
 }
@@ -408,13 +410,19 @@ size_t cm_merge_workspace_size(int key_type, int with_payload, uint64_t m, uint6
 
 int cm_stable_merge(int key_type, const void* A, uint64_t m, const void* B, uint64_t n, void* C, void* workspace,
                     size_t workspace_bytes, hipStream_t stream) {
-  return merge_impl(key_type, false, A, nullptr, m, B, nullptr, n, C, nullptr, workspace, workspace_bytes, stream);
+  return merge_impl(key_type, false, 4, A, nullptr, m, B, nullptr, n, C, nullptr, workspace, workspace_bytes, stream);
 }
 
 int cm_stable_merge_pairs(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
                           const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, void* workspace,
                           size_t workspace_bytes, hipStream_t stream) {
-  return merge_impl(key_type, true, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes, stream);
+  return merge_impl(key_type, true, 4, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes, stream);
+}
+
+int cm_stable_merge_pairs64(int key_type, const void* A, const uint64_t* A_val, uint64_t m, const void* B,
+                            const uint64_t* B_val, uint64_t n, void* C, uint64_t* C_val, void* workspace,
+                            size_t workspace_bytes, hipStream_t stream) {
+  return merge_impl(key_type, true, 8, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes, stream);
 }
 
 size_t cm_segmented_workspace_size(int key_type, int with_payload, uint64_t total_a, uint64_t total_b,
@@ -453,7 +461,7 @@ int cm_stable_merge_segmented_each(int key_type, const void* A, const uint32_t* 
   for (uint64_t s = 0; s < num_seg && rc == CM_OK; ++s) {
     const uint64_t a0 = a_off_host[s], b0 = b_off_host[s];
     const uint64_t ms = a_off_host[s + 1] - a0, ns = b_off_host[s + 1] - b0;
-    rc = merge_impl(key_type, val, A ? (const char*)A + a0 * ks : nullptr, val && A_val ? A_val + a0 : nullptr, ms,
+    rc = merge_impl(key_type, val, 4, A ? (const char*)A + a0 * ks : nullptr, val && A_val ? A_val + a0 : nullptr, ms,
                     B ? (const char*)B + b0 * ks : nullptr, val && B_val ? B_val + b0 : nullptr, ns,
                     C ? (char*)C + (a0 + b0) * ks : nullptr, val && C_val ? C_val + a0 + b0 : nullptr, workspace,
                     workspace_bytes, stream);
@@ -608,7 +616,7 @@ int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (reps < 1 || reps > 10000 || m + n == 0) return CM_EINVAL;
   const bool val = A_val || B_val || C_val;
-  const int check = merge_impl(key_type, val, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes,
+  const int check = merge_impl(key_type, val, 4, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes,
                                stream, nullptr, true);
   if (check != CM_OK) return check;
   Choice win{0, 1, 1};
@@ -621,8 +629,8 @@ int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64
         double ms = 0;
         const int rc = time_calls(
             [&] {
-              return merge_impl(key_type, val, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes,
-                                stream, &ch);
+              return merge_impl(key_type, val, 4, A, A_val, m, B, B_val, n, C, C_val, workspace,
+                                workspace_bytes, stream, &ch);
             },
             reps, stream, &ms);
         if (rc != CM_OK) return rc;
@@ -829,7 +837,7 @@ int cm_plan_create_merge(int key_type, const void* A, const uint32_t* A_val, uin
                          size_t workspace_bytes, cm_plan** plan) {
   if (!plan) return CM_EINVAL;
   *plan = nullptr;
-  const int rc = merge_impl(key_type, A_val || B_val || C_val, A, A_val, m, B, B_val, n, C, C_val, workspace,
+  const int rc = merge_impl(key_type, A_val || B_val || C_val, 4, A, A_val, m, B, B_val, n, C, C_val, workspace,
                             workspace_bytes, nullptr, nullptr, true);
   if (rc != CM_OK) return rc;
   MergeArgs a{key_type, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes};
@@ -838,7 +846,7 @@ int cm_plan_create_merge(int key_type, const void* A, const uint32_t* A_val, uin
       [](void* ctx, hipStream_t s) {
         const MergeArgs& x = *(const MergeArgs*)ctx;
         const bool val = x.Av || x.Bv || x.Cv;
-        return merge_impl(x.kt, val, x.A, x.Av, x.m, x.B, x.Bv, x.n, x.C, x.Cv, x.ws, x.ws_bytes, s);
+        return merge_impl(x.kt, val, 4, x.A, x.Av, x.m, x.B, x.Bv, x.n, x.C, x.Cv, x.ws, x.ws_bytes, s);
       },
       &a);
 }

@@ -100,8 +100,9 @@ int launch_sort_pass(int kt, bool val, const Choice& ch, const Shape& shape, con
 
 // Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj
 // (bj == nullptr: each block searches its own two boundary co-ranks).
-int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
-                        uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
+// Payloads (with val) are vbytes = 4 or 8 bytes wide.
+int launch_merge_blocks(int kt, bool val, int vbytes, const Choice& ch, const Shape& sh, const void* A,
+                        const void* Av, uint64_t m, const void* B, const void* Bv, uint64_t n, void* C, void* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st);
 
 // Algorithm 2 with one block per resident workgroup: the number of blocks P

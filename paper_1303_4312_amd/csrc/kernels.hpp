@@ -192,11 +192,11 @@ __device__ __forceinline__ void merge_run(const K* sA, int a_len, const K* sB, i
 // element by element.  s_key / s_val hold T + 16 elements.  Called by every
 // thread of the workgroup; ends with the block stored (LDS reusable after a
 // barrier).
-template <typename K, bool VAL, int NT, int E, bool VEC>
-__device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint32_t* __restrict__ Av, uint64_t m,
-                                            const K* __restrict__ B, const uint32_t* __restrict__ Bv, uint64_t n,
-                                            K* __restrict__ C, uint32_t* __restrict__ Cv, uint64_t i0, int len,
-                                            uint64_t j0, uint64_t j1, int search, K* s_key, uint32_t* s_val) {
+template <typename K, bool VAL, int NT, int E, bool VEC, typename V = uint32_t>
+__device__ __forceinline__ void merge_block(const K* __restrict__ A, const V* __restrict__ Av, uint64_t m,
+                                            const K* __restrict__ B, const V* __restrict__ Bv, uint64_t n,
+                                            K* __restrict__ C, V* __restrict__ Cv, uint64_t i0, int len,
+                                            uint64_t j0, uint64_t j1, int search, K* s_key, V* s_val) {
   const int a_len = window_a_len(j0, j1, len);
   const int b_len = len - a_len;
   const uint64_t k0 = i0 - j0;
@@ -206,19 +206,18 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
     // all requested before the first LDS write waits for them
     constexpr int T = NT * E;
     constexpr int RK = (T / kPerVec<K> + 4 + NT - 1) / NT;
-    constexpr int RV = VAL ? (T / 4 + 4 + NT - 1) / NT : 1;
+    constexpr int RV = VAL ? (T / kPerVec<V> + 4 + NT - 1) / NT : 1;
     const PairSpan sk = pair_span<K>(j0, a_len, k0, b_len);
-    const PairSpan sv = pair_span<uint32_t>(j0, a_len, k0, b_len);
+    const PairSpan sv = pair_span<V>(j0, a_len, k0, b_len);
     auto stage = [&](auto full) {
       constexpr bool FULL = decltype(full)::value;
       vec16 rk[RK], rv[RV];
       load_pair_vec<K, NT, RK, FULL>(A, m, j0, B, n, k0, sk, rk);
-      if constexpr (VAL) load_pair_vec<uint32_t, NT, RV, FULL>(Av, m, j0, Bv, n, k0, sv, rv);
+      if constexpr (VAL) load_pair_vec<V, NT, RV, FULL>(Av, m, j0, Bv, n, k0, sv, rv);
       write_pair_vec<K, NT, RK>(s_key, sk, rk);
-      if constexpr (VAL) write_pair_vec<uint32_t, NT, RV>(s_val, sv, rv);
+      if constexpr (VAL) write_pair_vec<V, NT, RV>(s_val, sv, rv);
     };
-    // payload vectors are partial wherever key vectors are (4-byte payloads)
-    if (pair_has_partial<K>(m, j0, n, k0, sk) || (VAL && pair_has_partial<uint32_t>(m, j0, n, k0, sv)))
+    if (pair_has_partial<K>(m, j0, n, k0, sk) || (VAL && pair_has_partial<V>(m, j0, n, k0, sv)))
       stage(std::false_type{});
     else
       stage(std::true_type{});
@@ -227,7 +226,7 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
     pav = sv.pa;
     pbv = sv.pb;
   } else {
-    load_windows<K, VAL, NT, E>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
+    load_windows<K, VAL, NT, E, V>(A, Av, j0, B, Bv, k0, a_len, len, s_key, s_val);
   }
   __syncthreads();
 
@@ -241,7 +240,7 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
   int os[E];
   const int avail = len - d;
   merge_run<K, E>(sA, a_len, sB, b_len, a, d - a, avail, ok, os);
-  uint32_t ov[E];
+  V ov[E];
   if constexpr (VAL) {
 #pragma unroll
     for (int e = 0; e < E; ++e)
@@ -258,9 +257,9 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const uint3
   __syncthreads();
   if constexpr (VEC) {
     store_span_vec<K, NT>(C, i0, len, s_key);
-    if constexpr (VAL) store_span_vec<uint32_t, NT>(Cv, i0, len, s_val);
+    if constexpr (VAL) store_span_vec<V, NT>(Cv, i0, len, s_val);
   } else {
-    store_block<K, VAL, NT, E>(C, Cv, i0, len, s_key, s_val);
+    store_block<K, VAL, NT, E, V>(C, Cv, i0, len, s_key, s_val);
   }
 }
 
@@ -286,22 +285,22 @@ __device__ __forceinline__ uint64_t block_order(uint64_t b, uint64_t P, int xcd)
   return g * group + (w & 7) * c + (w >> 3);
 }
 
-template <typename K, bool VAL, int NT, int E, bool VEC>
-__global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+template <typename K, bool VAL, int NT, int E, bool VEC, typename V = uint32_t>
+__global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const V* __restrict__ Av,
                                                      uint64_t m, const K* __restrict__ B,
-                                                     const uint32_t* __restrict__ Bv, uint64_t n,
-                                                     K* __restrict__ C, uint32_t* __restrict__ Cv,
+                                                     const V* __restrict__ Bv, uint64_t n,
+                                                     K* __restrict__ C, V* __restrict__ Cv,
                                                      const uint64_t* __restrict__ bj, uint64_t num_tiles,
                                                      int search, int xcd) {
   constexpr int T = NT * E;
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
-  __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
+  __shared__ __attribute__((aligned(16))) V s_val[VAL ? T + 16 : 1];
   const uint64_t N = m + n;
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
     const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
-    merge_block<K, VAL, NT, E, VEC>(A, Av, m, B, Bv, n, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
+    merge_block<K, VAL, NT, E, VEC, V>(A, Av, m, B, Bv, n, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
     if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }
@@ -313,16 +312,16 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, co
 // twice, once by each block that shares it; no workspace is read or written.
 // Worth it where the launch and the pass cost more than a few extra memory
 // round trips per block (small merges).
-template <typename K, bool VAL, int NT, int E, bool VEC>
-__global__ __launch_bounds__(NT) void k_merge_blocks_self(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+template <typename K, bool VAL, int NT, int E, bool VEC, typename V = uint32_t>
+__global__ __launch_bounds__(NT) void k_merge_blocks_self(const K* __restrict__ A, const V* __restrict__ Av,
                                                           uint64_t m, const K* __restrict__ B,
-                                                          const uint32_t* __restrict__ Bv, uint64_t n,
-                                                          K* __restrict__ C, uint32_t* __restrict__ Cv,
+                                                          const V* __restrict__ Bv, uint64_t n,
+                                                          K* __restrict__ C, V* __restrict__ Cv,
                                                           uint64_t num_tiles, int search, int xcd) {
   static_assert(NT >= 128, "two waves search the block ends");
   constexpr int T = NT * E;
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
-  __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
+  __shared__ __attribute__((aligned(16))) V s_val[VAL ? T + 16 : 1];
   __shared__ uint64_t s_j[2];
   const uint64_t N = m + n;
   const int wave = (int)(threadIdx.x >> 6);
@@ -338,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_merge_blocks_self(const K* __restrict__ 
       if ((threadIdx.x & 63) == 0) s_j[wave] = j;
     }
     __syncthreads();
-    merge_block<K, VAL, NT, E, VEC>(A, Av, m, B, Bv, n, C, Cv, i0, len, s_j[0], s_j[1], search, s_key, s_val);
+    merge_block<K, VAL, NT, E, VEC, V>(A, Av, m, B, Bv, n, C, Cv, i0, len, s_j[0], s_j[1], search, s_key, s_val);
     if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }

@@ -214,10 +214,12 @@ int launch_block_co_ranks(int kt, const Choice& ch, const Shape& sh, const void*
   return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::block_co_ranks(ch, sh, A, m, B, n, tile, nb, bj, coarse, st); });
 }
 
-int launch_merge_blocks(int kt, bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av,
-                        uint64_t m, const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv,
+int launch_merge_blocks(int kt, bool val, int vbytes, const Choice& ch, const Shape& sh, const void* A,
+                        const void* Av, uint64_t m, const void* B, const void* Bv, uint64_t n, void* C, void* Cv,
                         const uint64_t* bj, uint64_t tiles, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::merge_blocks(val, ch, sh, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st); });
+  return by_key(kt, [&](auto key) -> int {
+    return Launch<decltype(key)>::merge_blocks(val, vbytes, ch, sh, A, Av, m, B, Bv, n, C, Cv, bj, tiles, st);
+  });
 }
 
 // Resident workgroups per CU of `kernel` at nt threads, times the CU count;

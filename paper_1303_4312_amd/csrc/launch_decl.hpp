@@ -17,9 +17,9 @@ template <typename K>
 struct Launch {
   static int block_co_ranks(const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B, uint64_t n,
                             uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
-  static int merge_blocks(bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av, uint64_t m,
-                          const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* bj,
-                          uint64_t tiles, hipStream_t st);
+  static int merge_blocks(bool val, int vbytes, const Choice& ch, const Shape& sh, const void* A, const void* Av,
+                          uint64_t m, const void* B, const void* Bv, uint64_t n, void* C, void* Cv,
+                          const uint64_t* bj, uint64_t tiles, hipStream_t st);
   static int stream_co_ranks(const void* A, uint64_t m, const void* B, uint64_t n, uint32_t P, uint64_t* J,
                              hipStream_t st);
   static int merge_stream(bool val, const Choice& ch, const void* A, const uint32_t* Av, uint64_t m, const void* B,

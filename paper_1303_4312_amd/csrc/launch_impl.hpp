@@ -66,34 +66,41 @@ int Launch<K>::block_co_ranks(const Choice& ch, const Shape& sh, const void* A, 
 }
 
 template <typename K>
-int Launch<K>::merge_blocks(bool val, const Choice& ch, const Shape& sh, const void* A, const uint32_t* Av, uint64_t m,
-                            const void* B, const uint32_t* Bv, uint64_t n, void* C, uint32_t* Cv, const uint64_t* bj,
-                            uint64_t tiles, hipStream_t st) {
+int Launch<K>::merge_blocks(bool val, int vbytes, const Choice& ch, const Shape& sh, const void* A, const void* Av,
+                            uint64_t m, const void* B, const void* Bv, uint64_t n, void* C, void* Cv,
+                            const uint64_t* bj, uint64_t tiles, hipStream_t st) {
   return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
     constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
     static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
     const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
     const dim3 g((unsigned)tiles), b(NT);
     // bj == nullptr: every block co-ranks its own ends (no boundary pass)
-    auto go = [&](auto val_c, auto vec_c) {
+    auto go = [&](auto val_c, auto vec_c, auto pay) {
       constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
+      using P = decltype(pay);  // payload type
       if (bj)
-        hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B, Bv, n,
-                           (K*)C, Cv, bj, tiles, ch.search, sh.xcd_order);
+        hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W, P>), g, b, 0, st, (const K*)A, (const P*)Av, m,
+                           (const K*)B, (const P*)Bv, n, (K*)C, (P*)Cv, bj, tiles, ch.search, sh.xcd_order);
       else
-        hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W>), g, b, 0, st, (const K*)A, Av, m, (const K*)B,
-                           Bv, n, (K*)C, Cv, tiles, ch.search, sh.xcd_order);
+        hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W, P>), g, b, 0, st, (const K*)A, (const P*)Av, m,
+                           (const K*)B, (const P*)Bv, n, (K*)C, (P*)Cv, tiles, ch.search, sh.xcd_order);
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
-    if (val && vec)
-      go(T_{}, T_{});
-    else if (val)
-      go(T_{}, F_{});
-    else if (vec)
-      go(F_{}, T_{});
-    else
-      go(F_{}, F_{});
+    if (val && vbytes == 8) {
+      if (vec)
+        go(T_{}, T_{}, uint64_t{});
+      else
+        go(T_{}, F_{}, uint64_t{});
+    } else if (val && vec) {
+      go(T_{}, T_{}, uint32_t{});
+    } else if (val) {
+      go(T_{}, F_{}, uint32_t{});
+    } else if (vec) {
+      go(F_{}, T_{}, uint32_t{});
+    } else {
+      go(F_{}, F_{}, uint32_t{});
+    }
     return launch_status();
   });
 }

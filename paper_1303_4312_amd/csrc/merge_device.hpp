@@ -190,17 +190,17 @@ __device__ __forceinline__ int window_a_len(uint64_t j0, uint64_t j1, int len) {
 // write.  The loads are unconditional (a slot past the block re-reads its
 // first element, len >= 1), so no copy between branches waits on a load in
 // flight.  Consecutive lanes read consecutive addresses (one break at a_len).
-template <typename K, bool VAL, int NT, int E>
+template <typename K, bool VAL, int NT, int E, typename V = uint32_t>
 struct WindowRegs {
   K k[E];
-  uint32_t v[VAL ? E : 1];
+  V v[VAL ? E : 1];
 };
 
-template <typename K, bool VAL, int NT, int E>
-__device__ __forceinline__ void load_window_regs(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+template <typename K, bool VAL, int NT, int E, typename V = uint32_t>
+__device__ __forceinline__ void load_window_regs(const K* __restrict__ A, const V* __restrict__ Av,
                                                  uint64_t ja, const K* __restrict__ B,
-                                                 const uint32_t* __restrict__ Bv, uint64_t kb, int a_len,
-                                                 int len, WindowRegs<K, VAL, NT, E>& w) {
+                                                 const V* __restrict__ Bv, uint64_t kb, int a_len,
+                                                 int len, WindowRegs<K, VAL, NT, E, V>& w) {
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int x0 = (int)threadIdx.x + r * NT;
@@ -210,15 +210,15 @@ __device__ __forceinline__ void load_window_regs(const K* __restrict__ A, const 
     const K* pk = from_a ? A : B;
     w.k[r] = pk[g];
     if constexpr (VAL) {
-      const uint32_t* pv = from_a ? Av : Bv;
+      const V* pv = from_a ? Av : Bv;
       w.v[r] = pv[g];
     }
   }
 }
 
-template <typename K, bool VAL, int NT, int E>
-__device__ __forceinline__ void write_window_regs(int len, const WindowRegs<K, VAL, NT, E>& w, K* s_key,
-                                                  uint32_t* s_val) {
+template <typename K, bool VAL, int NT, int E, typename V = uint32_t>
+__device__ __forceinline__ void write_window_regs(int len, const WindowRegs<K, VAL, NT, E, V>& w, K* s_key,
+                                                  V* s_val) {
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int x = (int)threadIdx.x + r * NT;
@@ -229,21 +229,21 @@ __device__ __forceinline__ void write_window_regs(int len, const WindowRegs<K, V
   }
 }
 
-template <typename K, bool VAL, int NT, int E>
-__device__ __forceinline__ void load_windows(const K* __restrict__ A, const uint32_t* __restrict__ Av,
+template <typename K, bool VAL, int NT, int E, typename V = uint32_t>
+__device__ __forceinline__ void load_windows(const K* __restrict__ A, const V* __restrict__ Av,
                                              uint64_t ja, const K* __restrict__ B,
-                                             const uint32_t* __restrict__ Bv, uint64_t kb, int a_len,
-                                             int len, K* s_key, uint32_t* s_val) {
-  WindowRegs<K, VAL, NT, E> w;
-  load_window_regs<K, VAL, NT, E>(A, Av, ja, B, Bv, kb, a_len, len, w);
-  write_window_regs<K, VAL, NT, E>(len, w, s_key, s_val);
+                                             const V* __restrict__ Bv, uint64_t kb, int a_len,
+                                             int len, K* s_key, V* s_val) {
+  WindowRegs<K, VAL, NT, E, V> w;
+  load_window_regs<K, VAL, NT, E, V>(A, Av, ja, B, Bv, kb, a_len, len, w);
+  write_window_regs<K, VAL, NT, E, V>(len, w, s_key, s_val);
 }
 
 // Writes the block's LDS contents (already in output order) to C[i0, i0 + len)
 // with lane-contiguous stores.
-template <typename K, bool VAL, int NT, int E>
-__device__ __forceinline__ void store_block(K* __restrict__ C, uint32_t* __restrict__ Cv, uint64_t i0,
-                                            int len, const K* s_key, const uint32_t* s_val) {
+template <typename K, bool VAL, int NT, int E, typename V = uint32_t>
+__device__ __forceinline__ void store_block(K* __restrict__ C, V* __restrict__ Cv, uint64_t i0,
+                                            int len, const K* s_key, const V* s_val) {
 #pragma unroll
   for (int r = 0; r < E; ++r) {
     const int x = (int)threadIdx.x + r * NT;

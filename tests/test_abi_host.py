@@ -96,6 +96,16 @@ def test_merge_argument_errors_are_synchronous():
     assert lib.cm_stable_merge(0, A, 4, B, 4, P(0x10000000 + 8), ws, big, None) == EALIAS
     assert lib.cm_stable_merge_pairs(0, A, P(0x50000000), 4, B, P(0x60000000), 4, C,
                                      P(0x50000000), ws, big, None) == EALIAS
+    # 8-byte payloads: overlaps are judged on 8-byte elements (C_val 24 bytes
+    # into A_val's 32 overlaps)
+    assert lib.cm_stable_merge_pairs64(0, A, None, 4, B, P(0x60000000), 4, C, P(0x70000000),
+                                       ws, big, None) == EINVAL
+    assert lib.cm_stable_merge_pairs64(0, A, P(0x50000000), 4, B, P(0x60000000), 4, C,
+                                       P(0x50000000 + 24), ws, big, None) == EALIAS
+    assert lib.cm_stable_merge_pairs64(9, A, P(0x50000000), 4, B, P(0x60000000), 4, C,
+                                       P(0x70000000), ws, big, None) == EDTYPE
+    assert lib.cm_stable_merge_pairs64(0, None, None, 0, None, None, 0, None, None, None, 0,
+                                       None) == OK
     # workspace too small
     need = lib.cm_merge_workspace_size(0, 0, 1 << 20, 1 << 20)
     assert need > 0
