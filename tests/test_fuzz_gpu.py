@@ -82,6 +82,41 @@ def test_random_merge_case(case, restore_settings):
         assert same_bits(C, Ce), f"keys differ at {first_difference(C, Ce)}"
 
 
+@pytest.mark.parametrize("case", range(60))
+def test_random_merge_case_8byte_payloads(case, restore_settings):
+    """As above with uint64 payloads (cm_stable_merge_pairs64); expected:
+    the oracle's merge with origin payloads, the records gathered by origin
+    on the host."""
+    from paper_1303_4312_amd import workloads
+    rng = np.random.default_rng(zlib.crc32(b"fuzz-pairs64") + case)
+    dtype = DTYPES[case % 3]
+    descending = bool(rng.integers(0, 2))
+    dist = ("few", "wide", "equal", "runs")[int(rng.integers(0, 4))]
+    m, n = draw_size(rng), draw_size(rng)
+    offset = int(rng.integers(0, 2)) * int(rng.integers(1, 4))
+    cfg = int(rng.integers(0, cm.config_count()))
+    search = int(rng.integers(0, 2))
+    partition = int(rng.choice([-1, 0, 1, 2, 3, 4]))
+    print(f"\n[fuzz pairs64 {case}] {np.dtype(dtype).name} desc={descending} {dist} m={m} n={n} "
+          f"offset={offset} cfg={cfg} search={search} partition={partition}", flush=True)
+    A = draw_keys(rng, m, dtype, dist, descending)
+    B = draw_keys(rng, n, dtype, dist, descending)
+    cm.set_config(np.dtype(dtype).name, True, cfg)
+    cm.set_search(search)
+    cm.set_partition(partition)
+    Arec = rng.integers(0, 1 << 63, m, dtype=np.uint64)
+    Brec = rng.integers(0, 1 << 63, n, dtype=np.uint64)
+    C, Cv = cm.stable_merge_pairs(to_dev(A, offset), to_dev(Arec, offset), to_dev(B, offset),
+                                  to_dev(Brec, offset), descending=descending)
+    Av, Bv = workloads.origin_payloads(m, n)
+    Ce, codes = oracle.stable_merge(A, B, Av, Bv, descending=descending)
+    origin = np.where(codes < (1 << 31), codes, m + (codes & 0x7FFFFFFF)).astype(np.int64)
+    Cve = np.concatenate([Arec, Brec])[origin]
+    C, Cv = to_host(C), to_host(Cv)
+    assert same_bits(C, Ce), f"keys differ at {first_difference(C, Ce)}"
+    assert same_bits(Cv, Cve), f"payloads differ at {first_difference(Cv, Cve)}"
+
+
 @pytest.mark.parametrize("case", range(40))
 def test_random_segmented_case(case, restore_settings):
     import torch
