@@ -400,6 +400,14 @@ int cm_tuning_count(void);
  *   cm_plan_create_*: CM_OK and *plan set, or an error of the merge call,
  *     or CM_EHIP if capture or instantiation failed (*plan = NULL).
  *   cm_plan_launch: one graph launch on `stream`.
+ *   cm_plan_update_merge / cm_plan_update_segmented: re-point a plan made by
+ *     the matching create call at other buffers and sizes (same arguments
+ *     as create, tuning choice made anew): the call is captured again and
+ *     applied to the plan's executable graph in place when only kernel
+ *     arguments and grid sizes change, else a new executable graph replaces
+ *     it.  Not while a launch of the plan may still run.  CM_EINVAL for a
+ *     plan of the other kind, an error of the merge call (the plan is then
+ *     unchanged), or CM_EHIP.
  *   cm_plan_destroy: frees the plan (not while a launch may still run).
  */
 typedef struct cm_plan cm_plan;
@@ -416,6 +424,18 @@ int cm_plan_create_segmented(int key_type,
                              void *C, uint32_t *C_val,
                              void *workspace, size_t workspace_bytes, cm_plan **plan);
 int cm_plan_launch(cm_plan *plan, hipStream_t stream);
+int cm_plan_update_merge(cm_plan *plan, int key_type,
+                         const void *A, const uint32_t *A_val, uint64_t m,
+                         const void *B, const uint32_t *B_val, uint64_t n,
+                         void *C, uint32_t *C_val,
+                         void *workspace, size_t workspace_bytes);
+int cm_plan_update_segmented(cm_plan *plan, int key_type,
+                             const void *A, const uint32_t *A_val, const uint64_t *a_off,
+                             uint64_t total_a,
+                             const void *B, const uint32_t *B_val, const uint64_t *b_off,
+                             uint64_t total_b, uint64_t num_seg,
+                             void *C, uint32_t *C_val,
+                             void *workspace, size_t workspace_bytes);
 int cm_plan_destroy(cm_plan *plan);
 
 /*

@@ -53,6 +53,7 @@ EXPORTS = [
     "cm_autotune_merge", "cm_autotune_segmented", "cm_tuning_set", "cm_tuning_get",
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
+    "cm_plan_update_merge", "cm_plan_update_segmented",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
     "cm_set_coarse_stride", "cm_set_block_order", "cm_set_fine_lanes",
     "cm_server_create", "cm_server_submit", "cm_server_submit_host", "cm_server_poll",
@@ -134,6 +135,9 @@ def load():
         "cm_plan_create_segmented": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64, c_u64,
                                              vp, vp, vp, c_size, ctypes.POINTER(vp)]),
         "cm_plan_launch": (c_int, [vp, vp]),
+        "cm_plan_update_merge": (c_int, [vp, c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp, c_size]),
+        "cm_plan_update_segmented": (c_int, [vp, c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64, c_u64,
+                                             vp, vp, vp, c_size]),
         "cm_batch_prepare": (c_int, [c_int, c_int, vp, ctypes.c_uint32, ctypes.POINTER(c_u64)]),
         "cm_batch_workspace_size": (c_size, [c_u64, ctypes.c_uint32]),
         "cm_stable_merge_batch": (c_int, [c_int, c_int, vp, vp, ctypes.c_uint32, c_u64, vp, c_size,
@@ -767,12 +771,46 @@ class Plan:
     Holds references to every buffer it was built on (they must stay alive
     and in place); outputs are the attributes C and C_val."""
 
-    def __init__(self, handle, device, keep, C, C_val):
+    def __init__(self, handle, device, keep, C, C_val, kind="merge"):
         self._handle = handle
         self._device = device
         self._keep = keep
         self.C = C
         self.C_val = C_val
+        self._kind = kind
+
+    def update(self, A, B, A_val=None, B_val=None, C=None, C_val=None, workspace=None):
+        """Re-point a single-merge plan at other arrays (cm_plan_update_merge);
+        waits for the device first, so no earlier launch is still running."""
+        if self._handle is None or self._kind != "merge":
+            raise RuntimeError("update() needs an open plan made by plan_merge")
+        kt, with_val, m, n, A, A_val, B, B_val, C, C_val = _pair_args(A, B, A_val, B_val, C, C_val)
+        ws, wsb = _workspace(load().cm_merge_workspace_size(kt, int(with_val), m, n), A.device,
+                             workspace)
+        _torch().cuda.synchronize(self._device)
+        _check(load().cm_plan_update_merge(self._handle, kt, _ptr(A), _ptr(A_val), m, _ptr(B),
+                                           _ptr(B_val), n, _ptr(C), _ptr(C_val), _ptr(ws), wsb),
+               "cm_plan_update_merge")
+        self._keep = (A, A_val, B, B_val, ws)
+        self.C, self.C_val = C, C_val
+
+    def update_segmented(self, A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=None,
+                         workspace=None):
+        """Re-point a segmented plan (cm_plan_update_segmented); waits for the
+        device first."""
+        if self._handle is None or self._kind != "segmented":
+            raise RuntimeError("update_segmented() needs an open plan made by plan_segmented")
+        kt, with_val, ta, tb, S, A, A_val, a_off, B, B_val, b_off, C, C_val = _seg_args(
+            A, a_off, B, b_off, A_val, B_val, C, C_val)
+        ws, wsb = _workspace(load().cm_segmented_workspace_size(kt, int(with_val), ta, tb, S),
+                             A.device, workspace)
+        _torch().cuda.synchronize(self._device)
+        _check(load().cm_plan_update_segmented(self._handle, kt, _ptr(A), _ptr(A_val), _ptr(a_off),
+                                               ta, _ptr(B), _ptr(B_val), _ptr(b_off), tb, S,
+                                               _ptr(C), _ptr(C_val), _ptr(ws), wsb),
+               "cm_plan_update_segmented")
+        self._keep = (A, A_val, a_off, B, B_val, b_off, ws)
+        self.C, self.C_val = C, C_val
 
     def launch(self, stream=None):
         if self._handle is None:
@@ -816,7 +854,7 @@ def plan_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=Non
                                            _ptr(B_val), _ptr(b_off), tb, S, _ptr(C), _ptr(C_val),
                                            _ptr(ws), wsb, ctypes.byref(h)),
            "cm_plan_create_segmented")
-    return Plan(h, A.device, (A, A_val, a_off, B, B_val, b_off, ws), C, C_val)
+    return Plan(h, A.device, (A, A_val, a_off, B, B_val, b_off, ws), C, C_val, kind="segmented")
 
 
 # layout of cm_merge_desc (nine 64-bit fields)

@@ -367,6 +367,7 @@ using namespace cm;
 struct cm_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  int kind = 0;  // 0: single merge, 1: segmented batch
 };
 
 extern "C" {
@@ -776,21 +777,36 @@ int cm_tuning_load(const char* path) {
 
 // ---- graph plans
 
-static int plan_capture(cm_plan** out, int (*body)(void*, hipStream_t), void* ctx) {
-  if (!out) return CM_EINVAL;
+// Captures body(ctx, s) on a private stream into a new graph (*out; left
+// null on failure).
+static int capture_graph(int (*body)(void*, hipStream_t), void* ctx, hipGraph_t* out) {
   *out = nullptr;
   hipStream_t s;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return CM_EHIP;
-  cm_plan* p = new cm_plan;
   int rc = CM_OK;
+  hipGraph_t g = nullptr;
   g_capturing = true;
   if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) rc = CM_EHIP;
   const int body_rc = rc == CM_OK ? body(ctx, s) : rc;
-  if (rc == CM_OK && hipStreamEndCapture(s, &p->graph) != hipSuccess) rc = CM_EHIP;
+  if (rc == CM_OK && hipStreamEndCapture(s, &g) != hipSuccess) rc = CM_EHIP;
   g_capturing = false;
   if (rc == CM_OK) rc = body_rc;
-  if (rc == CM_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) rc = CM_EHIP;
   (void)hipStreamDestroy(s);
+  if (rc != CM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  *out = g;
+  return CM_OK;
+}
+
+static int plan_capture(cm_plan** out, int kind, int (*body)(void*, hipStream_t), void* ctx) {
+  if (!out) return CM_EINVAL;
+  *out = nullptr;
+  cm_plan* p = new cm_plan;
+  p->kind = kind;
+  int rc = capture_graph(body, ctx, &p->graph);
+  if (rc == CM_OK && hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess) rc = CM_EHIP;
   if (rc != CM_OK) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
@@ -798,6 +814,34 @@ static int plan_capture(cm_plan** out, int (*body)(void*, hipStream_t), void* ct
     return rc;
   }
   *out = p;
+  return CM_OK;
+}
+
+// Re-points plan p at the call body(ctx) describes: a new capture, applied
+// to the executable graph in place when its topology is unchanged (same
+// kernels, new arguments and grid sizes), else a new executable graph.  On
+// failure the plan is left as it was.
+static int plan_recapture(cm_plan* p, int (*body)(void*, hipStream_t), void* ctx) {
+  hipGraph_t g = nullptr;
+  int rc = capture_graph(body, ctx, &g);
+  if (rc != CM_OK) return rc;
+  hipGraphNode_t err_node = nullptr;
+  hipGraphExecUpdateResult res;
+  if (hipGraphExecUpdate(p->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+    (void)hipGraphDestroy(p->graph);
+    p->graph = g;
+    return CM_OK;
+  }
+  (void)hipGetLastError();  // a refused update is not an error of later calls
+  hipGraphExec_t e = nullptr;
+  if (hipGraphInstantiate(&e, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return CM_EHIP;
+  }
+  (void)hipGraphExecDestroy(p->exec);
+  (void)hipGraphDestroy(p->graph);
+  p->exec = e;
+  p->graph = g;
   return CM_OK;
 }
 
@@ -832,6 +876,17 @@ struct SegArgs {
   size_t ws_bytes;
 };
 
+static int merge_body(void* ctx, hipStream_t s) {
+  const MergeArgs& x = *(const MergeArgs*)ctx;
+  const bool val = x.Av || x.Bv || x.Cv;
+  return merge_impl(x.kt, val, 4, x.A, x.Av, x.m, x.B, x.Bv, x.n, x.C, x.Cv, x.ws, x.ws_bytes, s);
+}
+
+static int seg_body(void* ctx, hipStream_t s) {
+  const SegArgs& x = *(const SegArgs*)ctx;
+  return seg_impl(x.kt, x.A, x.Av, x.a_off, x.ta, x.B, x.Bv, x.b_off, x.tb, x.S, x.C, x.Cv, x.ws, x.ws_bytes, s);
+}
+
 int cm_plan_create_merge(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
                          const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, void* workspace,
                          size_t workspace_bytes, cm_plan** plan) {
@@ -841,14 +896,18 @@ int cm_plan_create_merge(int key_type, const void* A, const uint32_t* A_val, uin
                             workspace_bytes, nullptr, nullptr, true);
   if (rc != CM_OK) return rc;
   MergeArgs a{key_type, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes};
-  return plan_capture(
-      plan,
-      [](void* ctx, hipStream_t s) {
-        const MergeArgs& x = *(const MergeArgs*)ctx;
-        const bool val = x.Av || x.Bv || x.Cv;
-        return merge_impl(x.kt, val, 4, x.A, x.Av, x.m, x.B, x.Bv, x.n, x.C, x.Cv, x.ws, x.ws_bytes, s);
-      },
-      &a);
+  return plan_capture(plan, 0, merge_body, &a);
+}
+
+int cm_plan_update_merge(cm_plan* plan, int key_type, const void* A, const uint32_t* A_val, uint64_t m,
+                         const void* B, const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val,
+                         void* workspace, size_t workspace_bytes) {
+  if (!plan || !plan->exec || plan->kind != 0) return CM_EINVAL;
+  const int rc = merge_impl(key_type, A_val || B_val || C_val, 4, A, A_val, m, B, B_val, n, C, C_val, workspace,
+                            workspace_bytes, nullptr, nullptr, true);
+  if (rc != CM_OK) return rc;
+  MergeArgs a{key_type, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes};
+  return plan_recapture(plan, merge_body, &a);
 }
 
 int cm_plan_create_segmented(int key_type, const void* A, const uint32_t* A_val, const uint64_t* a_off,
@@ -862,14 +921,20 @@ int cm_plan_create_segmented(int key_type, const void* A, const uint32_t* A_val,
   if (rc != CM_OK) return rc;
   SegArgs a{key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val, workspace,
             workspace_bytes};
-  return plan_capture(
-      plan,
-      [](void* ctx, hipStream_t s) {
-        const SegArgs& x = *(const SegArgs*)ctx;
-        return seg_impl(x.kt, x.A, x.Av, x.a_off, x.ta, x.B, x.Bv, x.b_off, x.tb, x.S, x.C, x.Cv, x.ws,
-                        x.ws_bytes, s);
-      },
-      &a);
+  return plan_capture(plan, 1, seg_body, &a);
+}
+
+int cm_plan_update_segmented(cm_plan* plan, int key_type, const void* A, const uint32_t* A_val,
+                             const uint64_t* a_off, uint64_t total_a, const void* B, const uint32_t* B_val,
+                             const uint64_t* b_off, uint64_t total_b, uint64_t num_seg, void* C, uint32_t* C_val,
+                             void* workspace, size_t workspace_bytes) {
+  if (!plan || !plan->exec || plan->kind != 1) return CM_EINVAL;
+  const int rc = seg_impl(key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val,
+                          workspace, workspace_bytes, nullptr, nullptr, true);
+  if (rc != CM_OK) return rc;
+  SegArgs a{key_type, A, A_val, a_off, total_a, B, B_val, b_off, total_b, num_seg, C, C_val, workspace,
+            workspace_bytes};
+  return plan_recapture(plan, seg_body, &a);
 }
 
 int cm_plan_launch(cm_plan* plan, hipStream_t stream) {

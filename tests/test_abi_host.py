@@ -248,6 +248,10 @@ def test_plan_and_tuner_argument_errors():
     assert lib.cm_plan_create_merge(0, None, None, 5, None, None, 0, P(0x1000), None, P(0x2000),
                                     1 << 20, ctypes.byref(h)) == EINVAL
     assert lib.cm_plan_launch(None, None) == EINVAL
+    assert lib.cm_plan_update_merge(None, 0, None, None, 0, None, None, 0, None, None, None,
+                                    0) == EINVAL
+    assert lib.cm_plan_update_segmented(None, 0, None, None, None, 0, None, None, None, 0, 0,
+                                        None, None, None, 0) == EINVAL
     assert lib.cm_plan_destroy(None) == EINVAL
     best = (ctypes.c_int * 3)()
     assert lib.cm_autotune_merge(0, P(0x1000), None, 4, P(0x2000), None, 4, P(0x3000), None,

@@ -127,3 +127,72 @@ def test_timing_events_per_call():
     # off again: a second stop is an error
     with pytest.raises(cm.CMError):
         cm.timing_stop()
+
+
+def _replays_match(plan, Ce, Cve, eager, reps=3):
+    import torch
+    for rep in range(reps):
+        plan.C.zero_()
+        if plan.C_val is not None:
+            plan.C_val.zero_()
+        eager()  # the program's own work between replays
+        torch.cuda.synchronize()
+        out = plan.launch()
+        torch.cuda.synchronize()
+        C, Cv = out if plan.C_val is not None else (out, None)
+        assert same_bits(to_host(C), Ce), f"replay {rep}: keys"
+        if Cve is not None:
+            assert same_bits(to_host(Cv), Cve), f"replay {rep}: payloads"
+
+
+def test_plan_update_merge_same_and_new_shapes():
+    """cm_plan_update_merge: other arrays of the same sizes (the executable
+    graph updated in place), then sizes across the 2^24-output switch of
+    the boundary pass (another kernel sequence: a new executable graph),
+    then back; every replay against the oracle.  A refused update leaves
+    the plan as it was."""
+    import torch
+    print("[plan update] merge", flush=True)
+    shapes = [(40_000, 40_001, 1), (40_000, 40_001, 2), (9_000_000, 8_000_003, 3), (5, 70_000, 4)]
+    plan = None
+    for m, n, seed in shapes:
+        d = workloads.zipf(seed=seed, m=m, n=n)
+        A, Av, B, Bv = (to_dev(d[k]) for k in ("A", "Av", "B", "Bv"))
+        Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        if plan is None:
+            plan = cm.plan_merge(A, B, Av, Bv)
+        else:
+            plan.update(A, B, Av, Bv)
+        _replays_match(plan, Ce, Cve, lambda: cm.stable_merge_pairs(A, Av, B, Bv))
+    # an output over an input (checked before any capture): refused with
+    # CM_EALIAS, and the plan still replays the last call
+    ws = torch.empty(cm.merge_workspace_size("uint32", True, A.numel(), B.numel()),
+                     dtype=torch.uint8, device=A.device)
+    assert cm.load().cm_plan_update_merge(plan._handle, 0, A.data_ptr(), Av.data_ptr(), A.numel(),
+                                          B.data_ptr(), Bv.data_ptr(), B.numel(), A.data_ptr(),
+                                          Av.data_ptr(), ws.data_ptr(), ws.numel()) == -4
+    _replays_match(plan, Ce, Cve, lambda: None, reps=1)
+    # a merge plan is not a segmented plan
+    assert cm.load().cm_plan_update_segmented(plan._handle, 0, None, None, None, 0, None, None,
+                                              None, 0, 0, None, None, None, 0) == -1
+    plan.close()
+
+
+def test_plan_update_segmented():
+    print("[plan update] segmented", flush=True)
+    plan = None
+    for seed, S in ((5, 1000), (6, 1500), (7, 1500)):
+        d = workloads.segmented(seed=seed, num_seg=S, max_side=1 << 11, min_side=0)
+        A, B = to_dev(d["A"]), to_dev(d["B"])
+        a_off, b_off = to_dev(d["a_off"]), to_dev(d["b_off"])
+        Av, Bv = to_dev(d["Av"]), to_dev(d["Bv"])
+        Ce, Cve = oracle.stable_merge_segmented(d["A"], d["a_off"], d["B"], d["b_off"], d["Av"],
+                                                d["Bv"])
+        if plan is None:
+            plan = cm.plan_segmented(A, a_off, B, b_off, Av, Bv)
+        else:
+            plan.update_segmented(A, a_off, B, b_off, Av, Bv)
+        _replays_match(plan, Ce, Cve, lambda: cm.stable_merge_segmented(A, a_off, B, b_off))
+    with pytest.raises(RuntimeError):
+        plan.update(A, B, Av, Bv)
+    plan.close()
