@@ -313,10 +313,11 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     address range); 1 = one contiguous run per XCD; 0 = workgroup order.
  *     At most 2^20 (else CM_EINVAL).  Segmented batches keep workgroup
  *     order.
- *   cm_get_config / cm_get_search / cm_get_partition return the current
- *     setting (cm_get_config: the value set for the pair, 0 until set, not
- *     the per-operation default above; cm_tuning_get reports the choice a
- *     call would actually make).
+ *   cm_get_config / cm_get_search / cm_get_partition / cm_get_block_order /
+ *     cm_get_coarse_stride / cm_get_fine_lanes return the current setting
+ *     (cm_get_config: the value set for the pair, 0 until set, not the
+ *     per-operation default above; cm_tuning_get reports the choice a call
+ *     would actually make).
  *   (Settings are process-wide and not thread-safe against concurrent
  *   merges; set them before launching.)
  */
@@ -330,6 +331,9 @@ int cm_set_partition(int partition_mode);
 int cm_get_partition(void);
 int cm_set_coarse_stride(uint32_t blocks);
 int cm_set_block_order(int order);
+int cm_get_block_order(void);
+int cm_get_coarse_stride(void);
+int cm_get_fine_lanes(void);
 int cm_set_fine_lanes(int lanes);
 
 /*

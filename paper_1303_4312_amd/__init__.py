@@ -30,7 +30,8 @@ __all__ = [
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
     "stable_sort", "sort_workspace_size", "merge_partition_ablation", "origin_codes",
     "gather_records", "merge_records",
-    "launch_batch", "set_coarse_stride", "set_block_order", "set_fine_lanes",
+    "launch_batch", "set_coarse_stride", "set_block_order", "set_fine_lanes", "get_block_order",
+    "get_coarse_stride", "get_fine_lanes",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -53,7 +54,8 @@ EXPORTS = [
     "cm_autotune_merge", "cm_autotune_segmented", "cm_tuning_set", "cm_tuning_get",
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
-    "cm_plan_update_merge", "cm_plan_update_segmented",
+    "cm_plan_update_merge", "cm_plan_update_segmented", "cm_get_block_order",
+    "cm_get_coarse_stride", "cm_get_fine_lanes",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
     "cm_set_coarse_stride", "cm_set_block_order", "cm_set_fine_lanes",
     "cm_server_create", "cm_server_submit", "cm_server_submit_host", "cm_server_poll",
@@ -114,6 +116,9 @@ def load():
         "cm_set_partition": (c_int, [c_int]),
         "cm_set_coarse_stride": (c_int, [ctypes.c_uint32]),
         "cm_set_block_order": (c_int, [c_int]),
+        "cm_get_block_order": (c_int, []),
+        "cm_get_coarse_stride": (c_int, []),
+        "cm_get_fine_lanes": (c_int, []),
         "cm_set_fine_lanes": (c_int, [c_int]),
         "cm_get_partition": (c_int, []),
         "cm_stable_merge_segmented_each": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
@@ -663,6 +668,18 @@ def set_block_order(order: int):
     and copy_tiles: c >= 2 (default 32) runs of c blocks per XCD, 1 one
     contiguous run per XCD, 0 workgroup order."""
     _check(load().cm_set_block_order(order), "cm_set_block_order")
+
+
+def get_block_order() -> int:
+    return load().cm_get_block_order()
+
+
+def get_coarse_stride() -> int:
+    return load().cm_get_coarse_stride()
+
+
+def get_fine_lanes() -> int:
+    return load().cm_get_fine_lanes()
 
 
 # ---------------------------------------------------------------------------

@@ -609,6 +609,10 @@ int cm_set_block_order(int order) {
   return CM_OK;
 }
 
+int cm_get_block_order(void) { return g_set.shape.xcd_order; }
+int cm_get_coarse_stride(void) { return (int)g_set.shape.coarse_stride; }
+int cm_get_fine_lanes(void) { return g_set.shape.fine_lanes; }
+
 // ---- autotuner
 
 int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,

@@ -29,12 +29,13 @@ def restore_settings():
     import paper_1303_4312_amd as cm
     kts = ("uint32", "uint64", "float32")
     search, partition = cm.get_search(), cm.get_partition()
+    order, stride, lanes = cm.get_block_order(), cm.get_coarse_stride(), cm.get_fine_lanes()
     cfgs = {(kt, v): cm.get_config(kt, v) for kt in kts for v in (False, True)}
     yield
     cm.set_search(search)
     cm.set_partition(partition)
-    cm.set_coarse_stride(64)
-    cm.set_block_order(32)  # the default
-    cm.set_fine_lanes(1)
+    cm.set_coarse_stride(stride)
+    cm.set_block_order(order)
+    cm.set_fine_lanes(lanes)
     for (kt, v), c in cfgs.items():
         cm.set_config(kt, v, c)

@@ -153,6 +153,7 @@ def test_config_table(restore_settings):
     # block order: workgroup order, one run per XCD, or runs of up to 2^20 blocks
     for order in (0, 1, 2, 32, 1 << 20):
         assert cm.load().cm_set_block_order(order) == OK
+        assert cm.get_block_order() == order
     assert cm.load().cm_set_block_order(-1) == EINVAL
     assert cm.load().cm_set_block_order((1 << 20) + 1) == EINVAL
     for mode in range(-1, 5):
