@@ -273,11 +273,15 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *   cm_config_info: NT and E of configuration id (CM_ECONFIG if unknown).
  *   cm_set_config: the configuration used by the merge calls
  *     for (key_type, with_payload) in this process (not thread-safe against
- *     concurrent merges; set it before launching).  Until cm_set_config is
- *     called for (key_type, with_payload), the calls use configuration 0
- *     (256 x 7), except sorts (configuration 6, 256 x 9; 1, 256 x 11, for
- *     4-byte keys without payloads), single merges without payloads (6),
- *     segmented batches and batches of separate merges (2, 256 x 15).
+ *     concurrent merges; set it before launching); config_id -1 returns the
+ *     pair to the per-operation defaults.  Until cm_set_config is
+ *     called for (key_type, with_payload), or after it is called with -1,
+ *     single merges with payloads use configuration 0 (256 x 7), those
+ *     without payloads 6 (256 x 9), both 7 (512 x 11) where the automatic
+ *     boundary mode skips the pass from 2^21 outputs (2^22 without
+ *     payloads); sorts use 6 (256 x 9; 1, 256 x 11, for 4-byte keys
+ *     without payloads); segmented batches and batches of separate merges
+ *     2 (256 x 15).
  *   cm_set_search: co-rank search of the per-thread searches inside a
  *     block and of the one-level boundary pass: 0 = Algorithm 1, 1 = plain
  *     bisection over the diagonal (default).  Both return the unique pair
@@ -285,7 +289,7 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *   cm_set_partition: how block boundaries are co-ranked (Algorithm 2):
  *     -1 (default) = automatic: mode 4 for single merges of fewer than
  *     2^24 outputs (from 2^21 outputs with payloads, 2^22 keys only, with
- *     the 512 x 11 tile unless cm_set_config was called), else mode 2;
+ *     the 512 x 11 tile unless a configuration is set), else mode 2;
  *     0 = one GPU thread per boundary over the whole diagonal; 1 = two levels: every coarse boundary by a whole wave
  *     with a 64-ary search, then the others by bisection between their two
  *     coarse neighbours; 2 = two levels with 16 lanes (a 16-ary search) per
@@ -313,11 +317,20 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     address range); 1 = one contiguous run per XCD; 0 = workgroup order.
  *     At most 2^20 (else CM_EINVAL).  Segmented batches keep workgroup
  *     order.
+ *   cm_set_grid: workgroups of every block-merge kernel launch (single
+ *     merges, segmented batches, batches of separate merges, sort runs and
+ *     passes): 0 (default) = one workgroup per block of Algorithm 2; -1 =
+ *     a persistent grid of as many workgroups as the device holds at once
+ *     (CUs x occupancy of that kernel), each striding over the blocks, as
+ *     Algorithm 2 with p = the resident workgroups deals blocks to them;
+ *     g > 0 = at most g workgroups.  Never more workgroups than blocks.
+ *     CM_EINVAL below -1.
  *   cm_get_config / cm_get_search / cm_get_partition / cm_get_block_order /
- *     cm_get_coarse_stride / cm_get_fine_lanes return the current setting
- *     (cm_get_config: the value set for the pair, 0 until set, not the
- *     per-operation default above; cm_tuning_get reports the choice a call
- *     would actually make).
+ *     cm_get_coarse_stride / cm_get_fine_lanes / cm_get_grid return the
+ *     current setting
+ *     (cm_get_config: the value set for the pair, or -1 while none is set
+ *     and the per-operation defaults above apply; cm_tuning_get reports the
+ *     choice a call would actually make).
  *   (Settings are process-wide and not thread-safe against concurrent
  *   merges; set them before launching.)
  */
@@ -335,6 +348,8 @@ int cm_get_block_order(void);
 int cm_get_coarse_stride(void);
 int cm_get_fine_lanes(void);
 int cm_set_fine_lanes(int lanes);
+int cm_set_grid(int workgroups);
+int cm_get_grid(void);
 
 /*
  * Autotuner (self-written; not part of the method).  Times every tile

@@ -31,7 +31,7 @@ __all__ = [
     "stable_sort", "sort_workspace_size", "merge_partition_ablation", "origin_codes",
     "gather_records", "merge_records",
     "launch_batch", "set_coarse_stride", "set_block_order", "set_fine_lanes", "get_block_order",
-    "get_coarse_stride", "get_fine_lanes",
+    "get_coarse_stride", "get_fine_lanes", "set_grid", "get_grid",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -55,7 +55,7 @@ EXPORTS = [
     "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
     "cm_plan_update_merge", "cm_plan_update_segmented", "cm_get_block_order",
-    "cm_get_coarse_stride", "cm_get_fine_lanes",
+    "cm_get_coarse_stride", "cm_get_fine_lanes", "cm_set_grid", "cm_get_grid",
     "cm_batch_prepare", "cm_batch_workspace_size", "cm_stable_merge_batch",
     "cm_set_coarse_stride", "cm_set_block_order", "cm_set_fine_lanes",
     "cm_server_create", "cm_server_submit", "cm_server_submit_host", "cm_server_poll",
@@ -120,6 +120,8 @@ def load():
         "cm_get_coarse_stride": (c_int, []),
         "cm_get_fine_lanes": (c_int, []),
         "cm_set_fine_lanes": (c_int, [c_int]),
+        "cm_set_grid": (c_int, [c_int]),
+        "cm_get_grid": (c_int, []),
         "cm_get_partition": (c_int, []),
         "cm_stable_merge_segmented_each": (c_int, [c_int, vp, vp, vp, c_u64, vp, vp, vp, c_u64,
                                                    c_u64, vp, vp, vp, c_size, vp]),
@@ -622,11 +624,15 @@ def config_info(config_id: int):
 
 
 def set_config(key_dtype, with_payload: bool, config_id: int):
+    """Tile configuration of the merge calls for (key type, payload mode);
+    -1 returns the pair to the per-operation defaults."""
     kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
     _check(load().cm_set_config(kt, int(bool(with_payload)), config_id), "cm_set_config")
 
 
 def get_config(key_dtype, with_payload: bool) -> int:
+    """The configuration set for (key type, payload mode), or -1 while none
+    is set (tuning_get gives the one a call would use)."""
     kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
     return load().cm_get_config(kt, int(bool(with_payload)))
 
@@ -651,6 +657,17 @@ def set_partition(mode: int):
 
 def get_partition() -> int:
     return load().cm_get_partition()
+
+
+def set_grid(workgroups: int):
+    """Workgroups of the block-merge kernels: 0 = one per block (default),
+    -1 = a persistent grid of the resident workgroups, g > 0 = at most g;
+    the workgroups stride over the blocks."""
+    _check(load().cm_set_grid(workgroups), "cm_set_grid")
+
+
+def get_grid() -> int:
+    return load().cm_get_grid()
 
 
 def set_coarse_stride(blocks: int):

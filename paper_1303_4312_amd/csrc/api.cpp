@@ -28,6 +28,7 @@ struct Settings {
   bool cfg_set[CM_KEY_F32_DESC + 1][2] = {};  // set by the caller (else the defaults of resolve)
   int search = 1;                             // bisection
   int partition = -1;                         // automatic (see resolve)
+  int grid = 0;                               // block-kernel grid (Choice::grid)
   Shape shape;                                // coarse stride, block order
 };
 Settings g_set;
@@ -64,7 +65,11 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
   {
     std::lock_guard<std::mutex> lk(g_tuning_mu);
     auto it = g_tuning.find(TuneKey{op, kt, val ? 1 : 0, size_class(N)});
-    if (it != g_tuning.end()) return it->second.ch;
+    if (it != g_tuning.end()) {
+      Choice c = it->second.ch;
+      c.grid = g_set.grid;
+      return c;
+    }
   }
   int part = g_set.partition;
   const bool auto_part = part < 0;
@@ -72,13 +77,16 @@ Choice resolve(int op, int kt, bool val, uint64_t N) {
     part = (op == kOpMerge && N < kInBlockBelow) ? 4 : 2;
   int cfg = g_set.cfg[kt][val ? 1 : 0];
   if (!g_set.cfg_set[kt][val ? 1 : 0]) {
-    if (op == kOpMerge && auto_part && part == 4 && N >= (val ? kInBlockWideFrom : kInBlockWideKeysFrom))
-      cfg = kInBlockWideCfg;
+    if (op == kOpMerge) {
+      if (auto_part && part == 4 && N >= (val ? kInBlockWideFrom : kInBlockWideKeysFrom))
+        cfg = kInBlockWideCfg;  // the widest tile: fewest blocks, so fewest in-block searches
+      else
+        cfg = val ? 0 : kKeysMergeCfg;
+    }
     if (op == kOpSort) cfg = (val || kt == CM_KEY_U64 || kt == CM_KEY_U64_DESC) ? kSortCfg : kSortKeysCfg;
-    if (op == kOpMerge && !val) cfg = kKeysMergeCfg;
     if (op == kOpSegmented || op == kOpBatch) cfg = kSegCfg;
   }
-  return Choice{cfg, g_set.search, part};
+  return Choice{cfg, g_set.search, part, g_set.grid};
 }
 
 // ---------------------------------------------------------------------------
@@ -307,7 +315,7 @@ int sort_impl(int kt, bool val, const void* X, const uint32_t* Xv, uint64_t N, v
   uint64_t* bj = (uint64_t*)(w + round256(N * ks) + (val ? round256(N * 4) : 0));
   // ping-pong between Y and the workspace so that the last pass writes Y
   int cur = passes % 2;
-  int rc = launch_sort_blocks(kt, val, ch.cfg, X, val ? Xv : nullptr, N, bk[cur], bv[cur], tiles, st);
+  int rc = launch_sort_blocks(kt, val, ch, X, val ? Xv : nullptr, N, bk[cur], bv[cur], tiles, st);
   for (int sh = 1; rc == CM_OK && sh <= passes; ++sh) {  // runs of T << (sh - 1)
     rc = launch_sort_pass(kt, val, ch, g_set.shape, bk[cur], bv[cur], N, sh, bk[cur ^ 1], bv[cur ^ 1], bj, tiles, st);
     cur ^= 1;
@@ -564,15 +572,16 @@ int cm_config_info(int config_id, int* threads, int* items_per_thread) {
 
 int cm_set_config(int key_type, int with_payload, int config_id) {
   if (!key_type_ok(key_type)) return CM_EDTYPE;
-  if (config_id < 0 || config_id >= kNumCfgs) return CM_ECONFIG;
-  g_set.cfg[key_type][with_payload ? 1 : 0] = config_id;
-  g_set.cfg_set[key_type][with_payload ? 1 : 0] = true;
+  if (config_id < -1 || config_id >= kNumCfgs) return CM_ECONFIG;
+  // -1: back to the per-operation defaults of resolve()
+  g_set.cfg[key_type][with_payload ? 1 : 0] = config_id < 0 ? 0 : config_id;
+  g_set.cfg_set[key_type][with_payload ? 1 : 0] = config_id >= 0;
   return CM_OK;
 }
 
 int cm_get_config(int key_type, int with_payload) {
   if (!key_type_ok(key_type)) return CM_EDTYPE;
-  return g_set.cfg[key_type][with_payload ? 1 : 0];
+  return g_set.cfg_set[key_type][with_payload ? 1 : 0] ? g_set.cfg[key_type][with_payload ? 1 : 0] : -1;
 }
 
 int cm_set_search(int search_mode) {
@@ -610,6 +619,14 @@ int cm_set_block_order(int order) {
 }
 
 int cm_get_block_order(void) { return g_set.shape.xcd_order; }
+
+int cm_set_grid(int workgroups) {
+  if (workgroups < -1) return CM_EINVAL;
+  g_set.grid = workgroups;
+  return CM_OK;
+}
+
+int cm_get_grid(void) { return g_set.grid; }
 int cm_get_coarse_stride(void) { return (int)g_set.shape.coarse_stride; }
 int cm_get_fine_lanes(void) { return g_set.shape.fine_lanes; }
 
@@ -630,7 +647,7 @@ int cm_autotune_merge(int key_type, const void* A, const uint32_t* A_val, uint64
   for (int cfg = 0; cfg < kNumCfgs; ++cfg)
     for (int search = 0; search < 2; ++search)
       for (int part = 0; part <= kMaxPartition; ++part) {
-        const Choice ch{cfg, search, part};
+        const Choice ch{cfg, search, part, g_set.grid};
         double ms = 0;
         const int rc = time_calls(
             [&] {
@@ -673,7 +690,7 @@ int cm_autotune_segmented(int key_type, const void* A, const uint32_t* A_val, co
   for (int cfg = 0; cfg < kNumCfgs; ++cfg)
     for (int search = 0; search < 2; ++search)
       for (int part = 0; part < 3; part += 2) {
-      const Choice ch{cfg, search, part};
+      const Choice ch{cfg, search, part, g_set.grid};
       double ms = 0;
       const int rc = time_calls(
           [&] {
@@ -821,17 +838,42 @@ static int plan_capture(cm_plan** out, int kind, int (*body)(void*, hipStream_t)
   return CM_OK;
 }
 
+// Do graphs a and b hold the same sequence of nodes, kernel nodes running
+// the same kernel functions?  (A tile, payload-width or alignment change
+// keeps the node count and types but swaps the kernel instantiation.)
+static bool same_kernels(hipGraph_t a, hipGraph_t b) {
+  size_t na = 0, nb = 0;
+  if (hipGraphGetNodes(a, nullptr, &na) != hipSuccess || hipGraphGetNodes(b, nullptr, &nb) != hipSuccess ||
+      na != nb)
+    return false;
+  std::vector<hipGraphNode_t> xa(na), xb(nb);
+  if (na && (hipGraphGetNodes(a, xa.data(), &na) != hipSuccess || hipGraphGetNodes(b, xb.data(), &nb) != hipSuccess))
+    return false;
+  for (size_t x = 0; x < na; ++x) {
+    hipGraphNodeType ta, tb;
+    if (hipGraphNodeGetType(xa[x], &ta) != hipSuccess || hipGraphNodeGetType(xb[x], &tb) != hipSuccess || ta != tb)
+      return false;
+    if (ta != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams pa{}, pb{};
+    if (hipGraphKernelNodeGetParams(xa[x], &pa) != hipSuccess || hipGraphKernelNodeGetParams(xb[x], &pb) != hipSuccess ||
+        pa.func != pb.func)
+      return false;
+  }
+  return true;
+}
+
 // Re-points plan p at the call body(ctx) describes: a new capture, applied
 // to the executable graph in place when its topology is unchanged (same
-// kernels, new arguments and grid sizes), else a new executable graph.  On
-// failure the plan is left as it was.
+// kernel functions, new arguments and grid sizes), else a new executable
+// graph.  On failure the plan is left as it was.
 static int plan_recapture(cm_plan* p, int (*body)(void*, hipStream_t), void* ctx) {
   hipGraph_t g = nullptr;
   int rc = capture_graph(body, ctx, &g);
   if (rc != CM_OK) return rc;
   hipGraphNode_t err_node = nullptr;
   hipGraphExecUpdateResult res;
-  if (hipGraphExecUpdate(p->exec, g, &err_node, &res) == hipSuccess && res == hipGraphExecUpdateSuccess) {
+  if (same_kernels(p->graph, g) && hipGraphExecUpdate(p->exec, g, &err_node, &res) == hipSuccess &&
+      res == hipGraphExecUpdateSuccess) {
     (void)hipGraphDestroy(p->graph);
     p->graph = g;
     return CM_OK;

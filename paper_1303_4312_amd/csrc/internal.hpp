@@ -38,7 +38,22 @@ struct Choice {
                   // 64-lane coarse search; 2 two-level with a 16-lane coarse search;
                   // 3 one block per resident workgroup (streaming kernel); 4 no pass,
                   // each block co-ranks its own ends
+  int grid = 0;   // workgroups of the block kernels: 0 one per block; -1 as many as
+                  // are resident on the device at once; g > 0 at most g (the
+                  // workgroups then stride over the blocks)
 };
+
+// Workgroups of `kernel` (nt threads each) resident on the whole device at
+// once (CUs x occupancy), cached per kernel; 256 if the runtime cannot say.
+uint32_t resident_workgroups(const void* kernel, int nt);
+
+// Grid of a block-kernel launch over `tiles` blocks for the choice's grid
+// setting (never more workgroups than blocks, at least one).
+inline unsigned launch_grid(const void* kernel, int nt, uint64_t tiles, int grid) {
+  if (grid == 0 || tiles == 0) return (unsigned)tiles;
+  const uint64_t g = grid > 0 ? (uint64_t)grid : (uint64_t)resident_workgroups(kernel, nt);
+  return (unsigned)(g < tiles ? (g ? g : 1) : tiles);
+}
 constexpr int kMaxPartition = 4;
 // Every device array of a call holds fewer elements than this, so that no
 // byte count or index sum of the host-side checks can wrap (2^48 elements of
@@ -93,7 +108,7 @@ inline bool all_aligned16(std::initializer_list<const void*> ps) {
 // Merge sort (sort.hip): sort every run of T = tile_size(cfg) elements of X
 // into Y; then one pass merging runs of 2^(sh-1) blocks (T << (sh - 1)
 // elements) of X pairwise into Y (block co-ranks in bj, `tiles` entries).
-int launch_sort_blocks(int kt, bool val, int cfg, const void* X, const uint32_t* Xv, uint64_t N, void* Y,
+int launch_sort_blocks(int kt, bool val, const Choice& ch, const void* X, const uint32_t* Xv, uint64_t N, void* Y,
                        uint32_t* Yv, uint64_t tiles, hipStream_t st);
 int launch_sort_pass(int kt, bool val, const Choice& ch, const Shape& shape, const void* X, const uint32_t* Xv,
                      uint64_t N, int sh, void* Y, uint32_t* Yv, uint64_t* bj, uint64_t tiles, hipStream_t st);

@@ -285,6 +285,17 @@ __device__ __forceinline__ uint64_t block_order(uint64_t b, uint64_t P, int xcd)
   return g * group + (w & 7) * c + (w >> 3);
 }
 
+// Block taken by this workgroup at grid-stride step b (b = blockIdx.x + r G
+// for a grid of G workgroups).  With one workgroup per block (G = P) that is
+// block_order(b); a smaller, persistent grid takes the blocks in rounds of
+// G, each full round in block_order over its G blocks (so the XCDs again
+// take runs of neighbouring blocks), the last partial round in workgroup
+// order.  Either way a bijection of [0, P).
+__device__ __forceinline__ uint64_t grid_block(uint64_t b, uint64_t P, int xcd) {
+  const uint64_t G = gridDim.x, base = b - blockIdx.x;
+  return base + G <= P ? base + block_order(blockIdx.x, G, xcd) : b;
+}
+
 template <typename K, bool VAL, int NT, int E, bool VEC, typename V = uint32_t>
 __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, const V* __restrict__ Av,
                                                      uint64_t m, const K* __restrict__ B,
@@ -297,7 +308,7 @@ __global__ __launch_bounds__(NT) void k_merge_blocks(const K* __restrict__ A, co
   __shared__ __attribute__((aligned(16))) V s_val[VAL ? T + 16 : 1];
   const uint64_t N = m + n;
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
-    const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
+    const uint64_t t = grid_block(b, num_tiles, xcd);
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
     merge_block<K, VAL, NT, E, VEC, V>(A, Av, m, B, Bv, n, C, Cv, i0, len, bj[t], bj[t + 1], search, s_key, s_val);
@@ -326,7 +337,7 @@ __global__ __launch_bounds__(NT) void k_merge_blocks_self(const K* __restrict__ 
   const uint64_t N = m + n;
   const int wave = (int)(threadIdx.x >> 6);
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
-    const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
+    const uint64_t t = grid_block(b, num_tiles, xcd);
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
     if (wave < 2) {  // wave-uniform
@@ -661,7 +672,7 @@ __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __re
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
   __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
-    const uint64_t g = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
+    const uint64_t g = grid_block(b, num_tiles, xcd);
     const uint32_t r = desc_of(d, count, g, 0);
     const MergeDesc q = d[r];
     const uint64_t t = g - q.first_block;

@@ -4,6 +4,8 @@
 
 #include <stddef.h>
 
+#include <map>
+#include <mutex>
 #include <type_traits>
 
 #include "corank_merge.h"
@@ -224,6 +226,27 @@ int launch_merge_blocks(int kt, bool val, int vbytes, const Choice& ch, const Sh
 
 // Resident workgroups per CU of `kernel` at nt threads, times the CU count;
 // cached per kernel (the library drives one device type).
+uint32_t resident_workgroups(const void* kernel, int nt) {
+  static std::mutex mu;
+  static std::map<const void*, uint32_t> cache;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(kernel);
+    if (it != cache.end()) return it->second;
+  }
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || cus <= 0 ||
+      per_cu <= 0) {
+    (void)hipGetLastError();
+    return 256;  // a safe count for any device: correctness never depends on it
+  }
+  const uint32_t r = (uint32_t)cus * (uint32_t)per_cu;
+  std::lock_guard<std::mutex> lk(mu);
+  cache[kernel] = r;
+  return r;
+}
 
 uint32_t stream_blocks(int kt, bool val, const Choice& ch, uint64_t N) {
   const uint64_t T = tile_size(ch.cfg);

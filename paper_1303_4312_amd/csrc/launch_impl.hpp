@@ -17,21 +17,6 @@
 
 namespace cm {
 
-// Workgroups of `kernel` (nt threads) resident on the whole device, cached.
-inline uint32_t resident_blocks(const void* kernel, int nt, int* cache) {
-  if (*cache > 0) return (uint32_t)*cache;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || cus <= 0 ||
-      per_cu <= 0) {
-    (void)hipGetLastError();
-    return 256;  // a safe count for any device: correctness never depends on it
-  }
-  *cache = cus * per_cu;
-  return (uint32_t)*cache;
-}
-
 template <typename K>
 int Launch<K>::block_co_ranks(const Choice& ch, const Shape& sh, const void* A, uint64_t m, const void* B, uint64_t n,
                               uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
@@ -73,17 +58,21 @@ int Launch<K>::merge_blocks(bool val, int vbytes, const Choice& ch, const Shape&
     constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
     static_assert((NT * E) % 4 == 0, "blocks must start at multiples of 4 outputs");
     const bool vec = val ? all_aligned16({A, B, C, Av, Bv, Cv}) : all_aligned16({A, B, C});
-    const dim3 g((unsigned)tiles), b(NT);
+    const dim3 b(NT);
     // bj == nullptr: every block co-ranks its own ends (no boundary pass)
     auto go = [&](auto val_c, auto vec_c, auto pay) {
       constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
       using P = decltype(pay);  // payload type
       if (bj)
-        hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W, P>), g, b, 0, st, (const K*)A, (const P*)Av, m,
-                           (const K*)B, (const P*)Bv, n, (K*)C, (P*)Cv, bj, tiles, ch.search, sh.xcd_order);
+        hipLaunchKernelGGL((k_merge_blocks<K, V, NT, E, W, P>),
+                           dim3(launch_grid((const void*)k_merge_blocks<K, V, NT, E, W, P>, NT, tiles, ch.grid)), b,
+                           0, st, (const K*)A, (const P*)Av, m, (const K*)B, (const P*)Bv, n, (K*)C, (P*)Cv, bj,
+                           tiles, ch.search, sh.xcd_order);
       else
-        hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W, P>), g, b, 0, st, (const K*)A, (const P*)Av, m,
-                           (const K*)B, (const P*)Bv, n, (K*)C, (P*)Cv, tiles, ch.search, sh.xcd_order);
+        hipLaunchKernelGGL((k_merge_blocks_self<K, V, NT, E, W, P>),
+                           dim3(launch_grid((const void*)k_merge_blocks_self<K, V, NT, E, W, P>, NT, tiles, ch.grid)),
+                           b, 0, st, (const K*)A, (const P*)Av, m, (const K*)B, (const P*)Bv, n, (K*)C, (P*)Cv,
+                           tiles, ch.search, sh.xcd_order);
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -163,9 +152,10 @@ int Launch<K>::seg_merge_blocks(bool val, const Choice& ch, const void* A, const
     const bool vst = val ? all_aligned16({C, Cv}) : all_aligned16({C});
     auto go = [&](auto val_c, auto vst_c) {
       constexpr bool V = decltype(val_c)::value, W = decltype(vst_c)::value;
-      hipLaunchKernelGGL((k_seg_merge_blocks<K, V, NT, E, W>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                         (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs, tiles, flag,
-                         ch.search);
+      hipLaunchKernelGGL((k_seg_merge_blocks<K, V, NT, E, W>),
+                         dim3(launch_grid((const void*)k_seg_merge_blocks<K, V, NT, E, W>, NT, tiles, ch.grid)),
+                         dim3(NT), 0, st, (const K*)A, Av, a_off, (const K*)B, Bv, b_off, S, N, (K*)C, Cv, bj, bs,
+                         tiles, flag, ch.search);
     };
     using T_ = std::true_type;
     using F_ = std::false_type;
@@ -194,19 +184,23 @@ int Launch<K>::batch_merge_blocks(bool val, const Choice& ch, const void* d, uin
                                   uint64_t tiles, bool vec, int xcd, hipStream_t st) {
   return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
     constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-    const dim3 g((unsigned)tiles), b(NT);
+    const dim3 b(NT);
     const MergeDesc* q = (const MergeDesc*)d;
+    auto go = [&](auto val_c, auto vec_c) {
+      constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
+      const dim3 g(launch_grid((const void*)k_batch_merge_blocks<K, V, NT, E, W>, NT, tiles, ch.grid));
+      hipLaunchKernelGGL((k_batch_merge_blocks<K, V, NT, E, W>), g, b, 0, st, q, count, bj, tiles, ch.search, xcd);
+    };
+    using T_ = std::true_type;
+    using F_ = std::false_type;
     if (val && vec)
-      hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, true>), g, b, 0, st, q, count, bj, tiles, ch.search, xcd);
+      go(T_{}, T_{});
     else if (val)
-      hipLaunchKernelGGL((k_batch_merge_blocks<K, true, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                         ch.search, xcd);
+      go(T_{}, F_{});
     else if (vec)
-      hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, true>), g, b, 0, st, q, count, bj, tiles,
-                         ch.search, xcd);
+      go(F_{}, T_{});
     else
-      hipLaunchKernelGGL((k_batch_merge_blocks<K, false, NT, E, false>), g, b, 0, st, q, count, bj, tiles,
-                         ch.search, xcd);
+      go(F_{}, F_{});
     return launch_status();
   });
 }
@@ -223,9 +217,8 @@ template <typename K>
 int Launch<K>::stream_resident(bool val, int cfg) {
   return by_cfg(cfg, [&](auto nt, auto e) -> int {
     constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
-    static int cache_v = 0, cache_k = 0;
-    return val ? (int)resident_blocks((const void*)k_merge_stream<K, true, NT, E>, NT, &cache_v)
-               : (int)resident_blocks((const void*)k_merge_stream<K, false, NT, E>, NT, &cache_k);
+    return val ? (int)resident_workgroups((const void*)k_merge_stream<K, true, NT, E>, NT)
+               : (int)resident_workgroups((const void*)k_merge_stream<K, false, NT, E>, NT);
   });
 }
 

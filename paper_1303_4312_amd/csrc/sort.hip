@@ -190,7 +190,7 @@ __global__ __launch_bounds__(NT) void k_sort_pass_merge(const K* __restrict__ X,
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
   __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
-    const uint64_t t = gridDim.x == num_tiles ? block_order(b, num_tiles, xcd) : b;
+    const uint64_t t = grid_block(b, num_tiles, xcd);
     const PassPair p = pass_pair(t, (uint64_t)T, sh, N);
     const int len = (int)std::min((uint64_t)T, N - t * (uint64_t)T);
     const uint64_t j0 = bj[t];
@@ -204,18 +204,20 @@ __global__ __launch_bounds__(NT) void k_sort_pass_merge(const K* __restrict__ X,
   }
 }
 
-int launch_sort_blocks(int kt, bool val, int cfg, const void* X, const uint32_t* Xv, uint64_t N, void* Y,
+int launch_sort_blocks(int kt, bool val, const Choice& ch, const void* X, const uint32_t* Xv, uint64_t N, void* Y,
                        uint32_t* Yv, uint64_t tiles, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
     using K = decltype(key);
-    return by_cfg(cfg, [&](auto nt, auto e) -> int {
+    return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
       constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
       if (val)
-        hipLaunchKernelGGL((k_sort_blocks<K, true, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st, (const K*)X, Xv,
-                           N, (K*)Y, Yv, tiles);
+        hipLaunchKernelGGL((k_sort_blocks<K, true, NT, E>),
+                           dim3(launch_grid((const void*)k_sort_blocks<K, true, NT, E>, NT, tiles, ch.grid)), dim3(NT),
+                           0, st, (const K*)X, Xv, N, (K*)Y, Yv, tiles);
       else
-        hipLaunchKernelGGL((k_sort_blocks<K, false, NT, E>), dim3((unsigned)tiles), dim3(NT), 0, st, (const K*)X,
-                           Xv, N, (K*)Y, Yv, tiles);
+        hipLaunchKernelGGL((k_sort_blocks<K, false, NT, E>),
+                           dim3(launch_grid((const void*)k_sort_blocks<K, false, NT, E>, NT, tiles, ch.grid)),
+                           dim3(NT), 0, st, (const K*)X, Xv, N, (K*)Y, Yv, tiles);
       return launch_status();
     });
   });
@@ -235,9 +237,10 @@ int launch_sort_pass(int kt, bool val, const Choice& ch, const Shape& shape, con
       const bool vec = val ? all_aligned16({X, Y, Xv, Yv}) : all_aligned16({X, Y});
       auto go = [&](auto val_c, auto vec_c) {
         constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
-        hipLaunchKernelGGL((k_sort_pass_merge<K, V, NT, E, W>), dim3((unsigned)tiles), dim3(NT), 0, st,
-                           (const K*)X, Xv, N, sh, (K*)Y, Yv, (const uint64_t*)bj, tiles, ch.search,
-                           shape.xcd_order);
+        hipLaunchKernelGGL((k_sort_pass_merge<K, V, NT, E, W>),
+                           dim3(launch_grid((const void*)k_sort_pass_merge<K, V, NT, E, W>, NT, tiles, ch.grid)),
+                           dim3(NT), 0, st, (const K*)X, Xv, N, sh, (K*)Y, Yv, (const uint64_t*)bj, tiles,
+                           ch.search, shape.xcd_order);
       };
       using T_ = std::true_type;
       using F_ = std::false_type;

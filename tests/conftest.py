@@ -25,17 +25,20 @@ def figure():
 @pytest.fixture
 def restore_settings():
     """Tests may change the library's process-wide settings; put back the
-    ones found before the test (the defaults unless a test failed to)."""
+    ones found before the test, a configuration that was not set included."""
     import paper_1303_4312_amd as cm
-    kts = ("uint32", "uint64", "float32")
+    lib = cm.load()
     search, partition = cm.get_search(), cm.get_partition()
     order, stride, lanes = cm.get_block_order(), cm.get_coarse_stride(), cm.get_fine_lanes()
-    cfgs = {(kt, v): cm.get_config(kt, v) for kt in kts for v in (False, True)}
+    grid = cm.get_grid()
+    # -1: no configuration set (the per-operation defaults apply)
+    cfgs = {(kt, v): lib.cm_get_config(kt, v) for kt in range(6) for v in (0, 1)}
     yield
     cm.set_search(search)
     cm.set_partition(partition)
     cm.set_coarse_stride(stride)
     cm.set_block_order(order)
     cm.set_fine_lanes(lanes)
+    cm.set_grid(grid)
     for (kt, v), c in cfgs.items():
-        cm.set_config(kt, v, c)
+        assert lib.cm_set_config(kt, v, c) == 0

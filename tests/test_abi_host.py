@@ -149,6 +149,7 @@ def test_config_table(restore_settings):
     assert cm.get_config("uint32", True) == n - 1
     cm.set_config("uint32", True, old)
     assert cm.load().cm_set_config(0, 1, n) == ECONFIG
+    assert cm.load().cm_set_config(0, 1, -2) == ECONFIG
     assert cm.load().cm_set_search(2) == EINVAL
     # block order: workgroup order, one run per XCD, or runs of up to 2^20 blocks
     for order in (0, 1, 2, 32, 1 << 20):
@@ -195,19 +196,35 @@ def test_workloads_shapes():
     assert np.all(np.diff(s["a_off"].astype(np.int64)) >= 1)
 
 
-def test_tuning_table_host_logic(tmp_path):
+def test_tuning_table_host_logic(tmp_path, restore_settings):
     """The tuning table is host state: set / get / save / load / clear."""
+    cm.set_partition(-1)
+    cm.set_config("uint32", True, -1)
+    cm.set_config("uint32", False, -1)
     cm.tuning_clear()
     assert cm.tuning_count() == 0
     default = cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000)
     # automatic boundary pass: none below 2^24 outputs, two-level from
-    # there and for batches
+    # there and for batches; no configuration set: the per-operation tiles
     assert cm.get_partition() == -1
-    assert default == (cm.get_config("uint32", True), cm.get_search(), 4)
+    assert cm.get_config("uint32", True) == -1 and cm.get_config("uint32", False) == -1
+    assert default == (0, cm.get_search(), 4)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, (1 << 24) - 1)[2] == 4
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1 << 24)[2] == 2
     assert cm.tuning_get(cm.OP_MERGE, "uint32", False, (1 << 24) - 1)[2] == 4
     assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1 << 24)[2] == 2
+    # tiles: 256 x 7 with payloads, 256 x 9 keys only; 512 x 11 where the
+    # pass is skipped from 2^21 outputs (2^22 keys only)
+    tile = lambda v, N: cm.tuning_get(cm.OP_MERGE, "uint32", v, N)[0]
+    assert [tile(True, N) for N in (1 << 20, (1 << 21) - 1, 1 << 21, 1 << 23, 1 << 24)] == [0, 0, 7, 7, 0]
+    assert [tile(False, N) for N in (1 << 21, (1 << 22) - 1, 1 << 22, 1 << 23, 1 << 24)] == [6, 6, 7, 7, 6]
+    assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1 << 20)[0] == 2
+    assert cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 20)[0] == 2
+    # a set configuration wins over every default, and -1 unsets it
+    cm.set_config("uint32", False, 3)
+    assert tile(False, 1 << 22) == 3 and tile(False, 1 << 24) == 3
+    cm.set_config("uint32", False, -1)
+    assert cm.get_config("uint32", False) == -1 and tile(False, 1 << 22) == 7
     assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1000)[2] == 2
     # a batch of separate merges always co-ranks its boundaries in one level
     assert cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 30)[2] == 0
@@ -218,8 +235,7 @@ def test_tuning_table_host_logic(tmp_path):
     cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, 3, 0, 0)  # size class 10: N in [512, 1024)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1000) == (3, 0, 0)
     assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 1024) == default
-    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1000) == (
-        cm.get_config("uint32", False), cm.get_search(), 4)
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", False, 1000) == (6, cm.get_search(), 4)
     cm.tuning_set(cm.OP_SEGMENTED, "uint64", False, 30, 5, 1, 0)
     path = tmp_path / "tune.txt"
     cm.tuning_save(str(path))
@@ -423,7 +439,7 @@ def test_descending_key_types_accepted():
         assert lib.cm_set_config(6, 1, 0) == EDTYPE
     finally:
         for kt in range(6):
-            lib.cm_set_config(kt, 1, 0)
+            lib.cm_set_config(kt, 1, -1)
 
 
 def test_records_argument_errors():

@@ -89,7 +89,7 @@ def test_two_level_partition_edges(partition, stride, xcd, lanes):
     cm.set_coarse_stride(stride)
     cm.set_block_order(xcd)
     cm.set_fine_lanes(lanes)
-    nt, e = cm.config_info(cm.get_config("uint32", True))
+    nt, e = cm.config_info(cm.tuning_get(cm.OP_MERGE, "uint32", True, 1 << 30)[0])
     T = nt * e
     rng = np.random.default_rng(21)
     for N in (64 * T, 64 * T + 1, 64 * T - 1, 65 * T, 128 * T + T // 2, 200 * T + 7,

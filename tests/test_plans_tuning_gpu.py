@@ -196,3 +196,38 @@ def test_plan_update_segmented():
     with pytest.raises(RuntimeError):
         plan.update(A, B, Av, Bv)
     plan.close()
+
+
+def test_plan_update_across_kernel_instantiations():
+    """Updates that keep the node count and types but change the kernel a
+    node runs: a merge with payloads crossing 2^21 outputs (the automatic
+    mode switches from the 256 x 7 to the 512 x 11 tile, one kernel either
+    way), and 16-byte-aligned buffers followed by buffers 4 bytes off (the
+    16-byte staging kernel, then the element-wise one), and back; every
+    replay against the oracle."""
+    print("[plan update] kernel instantiations", flush=True)
+    cases = [((1 << 20) - 3, (1 << 20) - 5, 0), ((1 << 20) + 7, (1 << 20) + 1, 0),
+             ((1 << 20) + 7, (1 << 20) + 1, 1), (600_001, 500_003, 1), (600_001, 500_003, 0)]
+    plan = None
+    for seed, (m, n, off) in enumerate(cases):
+        d = workloads.dup16(seed=50 + seed, m=m, n=n)
+        A, Av, B, Bv = (to_dev(d[k], off) for k in ("A", "Av", "B", "Bv"))
+        Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        if plan is None:
+            plan = cm.plan_merge(A, B, Av, Bv)
+        else:
+            plan.update(A, B, Av, Bv)
+        _replays_match(plan, Ce, Cve, lambda: cm.stable_merge_pairs(A, Av, B, Bv))
+    plan.close()
+    # keys only, aligned then not
+    plan = None
+    for seed, off in enumerate((0, 1, 0)):
+        d = workloads.dup16(seed=70 + seed, m=300_001, n=200_002)
+        A, B = to_dev(d["A"], off), to_dev(d["B"], off)
+        Ce, _ = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        if plan is None:
+            plan = cm.plan_merge(A, B)
+        else:
+            plan.update(A, B)
+        _replays_match(plan, Ce, None, lambda: cm.stable_merge(A, B))
+    plan.close()

@@ -42,7 +42,7 @@ def check(keys, payload=True, offset=0):
 @pytest.mark.parametrize("dtype", DTYPES)
 def test_sizes_around_blocks_and_passes(dtype):
     rng = np.random.default_rng(11)
-    nt, e = cm.config_info(cm.get_config(np.dtype(dtype).name, True))
+    nt, e = cm.config_info(cm.tuning_get(cm.OP_SORT, np.dtype(dtype).name, True, 1 << 20)[0])
     T = nt * e
     for n in (0, 1, 2, 7, T - 1, T, T + 1, 2 * T, 2 * T + 1, 3 * T + 5, 4 * T, 4 * T - 1,
               8 * T + 3, 33 * T + 17, 100_003):
