@@ -130,6 +130,10 @@ def cpu_baseline_leg(d, C_gpu, Cv_gpu, seconds):
                 break
     except OSError:
         pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
     return {
         "value": n * reps / t_total,
         "unit": "keys/s",
@@ -137,6 +141,9 @@ def cpu_baseline_leg(d, C_gpu, Cv_gpu, seconds):
         "kind": "oracle",
         "sample": (f"the full workload arrays ({n} outputs), merged {reps}x by the "
                    f"single-threaded oracle in {t_total:.1f} s on {cpu}"),
+        "cpu_model": cpu,
+        "host_cores": os.cpu_count(),
+        "host_cores_usable": usable,
     }, exact
 
 
@@ -733,7 +740,7 @@ def tile_copy_ceiling(cfg, A, Av, B, Bv, reps=20):
 
 
 def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.1),
-                seed=5000):
+                seed=5000, python_scheduler=True):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
     payload, uniform keys), staged in HBM before they arrive.  The library's
     serving runtime (cm_server_*: a native scheduler thread) admits them
@@ -769,6 +776,7 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
                                  max_requests=4096, device=dev)
         submit, poll, release = srv.submit_ptrs, srv.poll, srv.release
         lat, late, outputs, sub = [], {}, 0, 0
+        parts = []  # per request: lateness, submit->launch, launch->end seen, device, end seen->report
         t0 = time.perf_counter()
         t_done = t0
         while len(lat) < total:
@@ -787,6 +795,8 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
                     raise cm.CMError(d.status, "serving request")
                 lateness, req = late.pop(d.ticket)
                 lat.append(lateness + d.latency_ns * 1e-9)
+                parts.append((lateness, d.queued_ns * 1e-9, (d.ended_ns - d.queued_ns) * 1e-9,
+                              d.device_ns * 1e-9, (d.latency_ns - d.ended_ns) * 1e-9))
                 n_out = sizes[req]
                 outputs += n_out
                 if check:
@@ -804,16 +814,23 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
 
         def pick(q):
             return lat[min(len(lat) - 1, int(round(q * (len(lat) - 1))))]
+        names = ("client_lateness", "submit_to_launch", "launch_to_end_seen", "batch_device",
+                 "end_seen_to_report")
+        breakdown = {k: statistics.median(p[x] for p in parts) * 1e3 for x, k in enumerate(names)}
         return {"keys_per_s": outputs / wall, "requests_per_s": total / wall,
                 "p50_ms": pick(0.5) * 1e3, "p99_ms": pick(0.99) * 1e3,
                 "mean_batch": st["submitted"] / max(st["batches"], 1),
-                "gpu_busy_fraction": st["busy_ms"] / (wall * 1e3)}
+                "gpu_busy_fraction": st["busy_ms"] / (wall * 1e3),
+                # bytes moved (read and write one key and one payload per
+                # output) over the time some batch was running on the GPU
+                "busy_rate_gbs": outputs * 16 / (st["busy_ms"] * 1e-3) / 1e9 if st["busy_ms"] else None,
+                "median_breakdown_ms": breakdown}
 
     run_native([0.0] * per_point, check=True)  # warm-up; every output checked
     sat = run_native([0.0] * per_point)
     sat_rate = sat["requests_per_s"]
     log(f"serving (native): saturation {sat_rate:.0f} req/s, {sat['keys_per_s'] / 1e9:.1f} "
-        f"G keys/s, busy {sat['gpu_busy_fraction']:.2f}")
+        f"G keys/s, busy {sat['gpu_busy_fraction']:.2f} ({sat['busy_rate_gbs']:.0f} GB/s while busy)")
     rng = np.random.default_rng(seed)
     points = []
     for frac in fractions:
@@ -823,7 +840,9 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
         st.update({"rate_per_s": lam, "fraction_of_saturation": frac})
         points.append(st)
         log(f"serving (native): rate {lam:.0f}/s p50 {st['p50_ms']:.3f} ms "
-            f"p99 {st['p99_ms']:.3f} ms busy {st['gpu_busy_fraction']:.2f}")
+            f"p99 {st['p99_ms']:.3f} ms busy {st['gpu_busy_fraction']:.2f} "
+            f"({st['busy_rate_gbs']:.0f} GB/s while busy); medians (ms): "
+            + ", ".join(f"{k} {v:.3f}" for k, v in st["median_breakdown_ms"].items()))
     del arena, alone
     torch.cuda.empty_cache()
 
@@ -838,6 +857,22 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
                 f.result(timeout=120)
         return srv.stats()
 
+    native = {
+        "workload": ("requests with sides log-uniform in [2^10,2^24], uint32 keys uniform, "
+                     "uint32 payloads, device-resident"),
+        "runtime": "cm_server (native scheduler thread), 16 GiB output arena, max_batch 64, "
+                   "2 batches in flight",
+        "boundary_pass": ["one_level", "two_level_64", "two_level_16", "two_level_16",
+                          "in_block"][cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 28)[2]],
+        "pool": pool_size,
+        "requests_per_point": per_point,
+        "alone_vs_mix_checked": per_point,
+        "mean_outputs_per_request": float(np.mean(sizes)),
+        "saturation": sat,
+        "points": points,
+    }
+    if not python_scheduler:
+        return native
     sys.setswitchinterval(1e-4)  # let the scheduler thread in often
     run_python(per_point)
     py = run_python(per_point)
@@ -845,16 +880,7 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
     log(f"serving (python scheduler): saturation "
         f"{per_point * py['keys_per_s'] / outputs:.0f} req/s")
     return {
-        "workload": ("requests with sides log-uniform in [2^10,2^24], uint32 keys uniform, "
-                     "uint32 payloads, device-resident"),
-        "runtime": "cm_server (native scheduler thread), 16 GiB output arena, max_batch 64, "
-                   "2 batches in flight",
-        "pool": pool_size,
-        "requests_per_point": per_point,
-        "alone_vs_mix_checked": per_point,
-        "mean_outputs_per_request": float(np.mean(sizes)),
-        "saturation": sat,
-        "points": points,
+        **native,
         "python_scheduler_saturation": {
             "requests_per_s": per_point * py["keys_per_s"] / outputs,
             "keys_per_s": py["keys_per_s"], "p50_ms": py["p50_s"] * 1e3,
@@ -895,6 +921,9 @@ def main():
                          "rocprofv3")
     ap.add_argument("--only-sort", action="store_true",
                     help="run the merge-sort leg only and print its record (for profiling)")
+    ap.add_argument("--only-serving", action="store_true",
+                    help="run the native serving leg only (saturation and the 0.25 and 1.0 "
+                         "load points) and print its record (for profiling)")
     args = ap.parse_args()
     if args.only_step:
         for leg in ("cpu_baseline", "batched", "latency", "serving", "boundary_ab", "ablation",
@@ -910,6 +939,11 @@ def main():
     import numpy as np
     import torch
     import paper_1303_4312_amd as cm
+
+    if args.only_serving:
+        r = serving_leg(per_point=500, fractions=(0.25, 1.0), python_scheduler=False)
+        print(json.dumps({"serving": r}), flush=True)
+        return
 
     if args.only_sort:
         r = sort_leg()

@@ -62,7 +62,9 @@ enum cm_status {
     CM_EUNSORTED = -7, /* cm_check_sorted: the array is not sorted */
     CM_ECONFIG = -8,   /* unknown tile configuration */
     CM_EBUSY = -9,     /* server: every request slot is taken */
-    CM_ECANCELED = -10 /* server: request dropped at shutdown without running */
+    CM_ECANCELED = -10, /* server: request dropped at shutdown without running */
+    CM_ESTALE = -11     /* tuning file made for another device, HIP runtime or
+                           library build (or with no such identity) */
 };
 
 /*
@@ -182,18 +184,31 @@ int cm_stable_merge_pairs64(int key_type,
  *   host-only; fills descs[r].first_block (blocks of the merges before r)
  *   for the block size the batch call will use, and the total block count.
  * cm_batch_workspace_size(total_blocks, count): workspace bytes (one uint64
- *   co-rank per block end of every merge), rounded up to 256.
+ *   co-rank per block end of every merge, one per 16th of those for the
+ *   two-level pass, one uint32 per block naming its merge, and room for
+ *   CM_BATCH_INLINE_MAX descriptors), each part rounded up to 256.
  * cm_stable_merge_batch(key_type, with_payload, descs_host, descs_dev,
  *   count, total_blocks, workspace, workspace_bytes, stream):
  *   descs_host is the prepared host array (used to check the arguments);
  *   descs_dev is a byte-identical copy of it in device memory, read by the
  *   kernels (the caller uploads it and keeps it alive until the stream has
- *   run the call).  No output may overlap an input or another output of the
- *   batch.  count = 0 is a no-op.
+ *   run the call).  With count <= CM_BATCH_INLINE_MAX, descs_dev may be
+ *   NULL: the descriptors then travel in the kernel arguments (copied at
+ *   the call; nothing to upload first).  No output may overlap an input or
+ *   another output of the batch.  count = 0 is a no-op.  Block ends are
+ *   co-ranked as the boundary mode says (cm_set_partition, or the tuning
+ *   table's entry for operation 2): 0 = one thread per block end over its
+ *   merge's diagonal; 1, 2 = two levels (every 64th block end of the whole
+ *   batch searched by 64 or 16 lanes over its merge, the others by
+ *   bisection between the nearest of those in the same merge, or the
+ *   merge's own ends); 4 = no pass, every block co-ranks its two ends
+ *   itself (one wave each), for batches of at most CM_BATCH_INLINE_MAX
+ *   merges (larger ones take 2); 3 is taken as 2.
  * Errors: CM_EDTYPE, CM_EINVAL (null pointer with nonzero length, counts
  *   or first_block that do not match cm_batch_prepare), CM_EALIAS,
  *   CM_ENOSPC, CM_EHIP.
  */
+#define CM_BATCH_INLINE_MAX 16
 typedef struct cm_merge_desc {
     const void *A;
     const uint32_t *A_val;
@@ -302,7 +317,10 @@ int cm_check_sorted(int key_type, const void *X, uint64_t len, uint32_t *flag,
  *     only; saves a launch on small merges).  The segmented batch uses two
  *     levels (segment search and co-rank narrowed by coarse neighbours) for
  *     any nonzero mode and one level for 0; the batch of separate merges
- *     always uses one level.  All give the same results.
+ *     takes modes 0, 1, 2 and 4 as above (3 as 2) and, automatically,
+ *     mode 4 when it has at most CM_BATCH_INLINE_MAX merges, each of fewer
+ *     than 2^24 outputs, else mode 2 (cm_tuning_get reports 2 for it: the
+ *     rule depends on the merges).  All give the same results.
  *   cm_set_coarse_stride: blocks between coarse boundaries of the two-level
  *     pass (default 64; at least 16).
  *   cm_set_fine_lanes: lanes that search each boundary of the two-level
@@ -386,8 +404,8 @@ int cm_autotune_segmented(int key_type,
  * 2 = batch of separate merges (size class of its total output count),
  * 3 = stable sort (size class of n; the partition field is unused).  A
  * segmented batch takes partition 0 as the one-level pass and any other
- * value as the two-level pass; a batch of separate merges always co-ranks
- * its block boundaries in one level, whatever the entry says;
+ * value as the two-level pass; a batch of separate merges takes the modes
+ * of cm_stable_merge_batch;
  * the size class of a merge of N outputs is the bit length of N (0..64).
  * A merge call uses the entry of its size class when there is one, else
  * the settings of cm_set_config / cm_set_search / cm_set_partition.
@@ -395,9 +413,17 @@ int cm_autotune_segmented(int key_type,
  *   cm_tuning_get: choice[0..2] that a call of N outputs would use now
  *     (CM_EINVAL for an unknown op).
  *   cm_tuning_save / cm_tuning_load: text file, one entry per line
- *     "op key_type with_payload size_class config search partition ms";
- *     load merges the file into the table (CM_EINVAL on a malformed line,
- *     leaving the table unchanged).
+ *     "op key_type with_payload size_class config search partition ms",
+ *     after a header naming what the timings hold for: the device
+ *     architecture (gcnArchName of the current device), the HIP runtime
+ *     version and the library's build id (cm_build_id).  load merges the
+ *     file into the table; CM_EINVAL on a malformed line, CM_ESTALE if the
+ *     header is missing or names another device, runtime or build (either
+ *     way the table is unchanged).  path NULL: the file named by the
+ *     environment variable CM_TUNING_FILE, else
+ *     $XDG_CACHE_HOME/corank_merge/tuning.txt, else
+ *     $HOME/.cache/corank_merge/tuning.txt (save creates its directories).
+ *   cm_build_id: the library's build id, a hash of its sources.
  *   cm_tuning_clear / cm_tuning_count: empty / size of the table.
  */
 int cm_tuning_set(int op, int key_type, int with_payload, int size_class,
@@ -405,6 +431,7 @@ int cm_tuning_set(int op, int key_type, int with_payload, int size_class,
 int cm_tuning_get(int op, int key_type, int with_payload, uint64_t num_outputs, int *choice);
 int cm_tuning_save(const char *path);
 int cm_tuning_load(const char *path);
+const char *cm_build_id(void);
 int cm_tuning_clear(void);
 int cm_tuning_count(void);
 
@@ -663,7 +690,11 @@ int cm_stable_sort_pairs(int key_type, const void *keys, const uint32_t *vals, u
  *   copy staying at the offsets until release); keys_offset / vals_offset:
  *   their byte offsets in the arena; queued_ns: submit to launch;
  *   latency_ns: submit to completion as seen by the scheduler (for a host
- *   request: outputs back in host memory).  Thread-safe.
+ *   request: outputs back in host memory); ended_ns: submit to the moment
+ *   the scheduler saw the request's batch end on the device (before any
+ *   copy back); device_ns: that batch's device time (from HIP events
+ *   around its upload and kernels; 0 if they could not be read).
+ *   Thread-safe.
  * cm_server_release(server, ticket): the client is done with a reported
  *   merge's outputs; its arena space and slot are reused.  CM_EINVAL for an
  *   unknown, unreported or already released ticket.
@@ -687,6 +718,8 @@ typedef struct cm_server_done {
     uint64_t vals_offset;
     uint64_t queued_ns;
     uint64_t latency_ns;
+    uint64_t ended_ns;
+    uint64_t device_ns;
 } cm_server_done;
 typedef struct cm_server_stats {
     uint64_t submitted, completed, failed, canceled, batches, max_batch_seen;

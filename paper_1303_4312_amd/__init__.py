@@ -26,7 +26,7 @@ __all__ = [
     "set_config", "get_config", "set_search", "KEY_TYPES", "stable_merge_segmented_each",
     "copy", "timing_start", "timing_stop", "get_search", "set_partition", "get_partition",
     "autotune_merge", "autotune_segmented", "tuning_set", "tuning_get", "tuning_save",
-    "tuning_load", "tuning_clear", "tuning_count", "Plan", "plan_merge", "plan_segmented",
+    "tuning_load", "tuning_clear", "tuning_count", "build_id", "ESTALE", "Plan", "plan_merge", "plan_segmented",
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
     "stable_sort", "sort_workspace_size", "merge_partition_ablation", "origin_codes",
     "gather_records", "merge_records",
@@ -40,6 +40,7 @@ library_path = os.path.join(_HERE, "libcorank_merge.so")
 # C enum cm_key_type
 KEY_U32, KEY_U64, KEY_F32 = 0, 1, 2
 KEY_DESC_OFFSET = 3  # CM_KEY_*_DESC = CM_KEY_* + 3: the same keys, nonincreasing order
+ESTALE = -11  # CM_ESTALE: a tuning table made for another device, runtime or build
 # operations of the tuning table
 OP_MERGE, OP_SEGMENTED, OP_BATCH, OP_SORT = 0, 1, 2, 3
 KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
@@ -52,7 +53,7 @@ EXPORTS = [
     "cm_set_search", "cm_get_search", "cm_set_partition", "cm_get_partition",
     "cm_stable_merge_segmented_each", "cm_copy", "cm_copy_tiles", "cm_timing_start", "cm_timing_stop",
     "cm_autotune_merge", "cm_autotune_segmented", "cm_tuning_set", "cm_tuning_get",
-    "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count",
+    "cm_tuning_save", "cm_tuning_load", "cm_tuning_clear", "cm_tuning_count", "cm_build_id",
     "cm_plan_create_merge", "cm_plan_create_segmented", "cm_plan_launch", "cm_plan_destroy",
     "cm_plan_update_merge", "cm_plan_update_segmented", "cm_get_block_order",
     "cm_get_coarse_stride", "cm_get_fine_lanes", "cm_set_grid", "cm_get_grid",
@@ -134,6 +135,7 @@ def load():
         "cm_tuning_set": (c_int, [c_int, c_int, c_int, c_int, c_int, c_int, c_int]),
         "cm_tuning_get": (c_int, [c_int, c_int, c_int, c_u64, ctypes.POINTER(c_int)]),
         "cm_tuning_save": (c_int, [ctypes.c_char_p]),
+        "cm_build_id": (ctypes.c_char_p, []),
         "cm_tuning_load": (c_int, [ctypes.c_char_p]),
         "cm_tuning_clear": (c_int, []),
         "cm_tuning_count": (c_int, []),
@@ -784,12 +786,22 @@ def tuning_get(op, key_dtype, with_payload, num_outputs):
     return tuple(out)
 
 
-def tuning_save(path):
-    _check(load().cm_tuning_save(os.fsencode(path)), "cm_tuning_save")
+def tuning_save(path=None):
+    """Save the tuning table (path None: $CM_TUNING_FILE, else the user's
+    cache directory)."""
+    _check(load().cm_tuning_save(None if path is None else os.fsencode(path)), "cm_tuning_save")
 
 
-def tuning_load(path):
-    _check(load().cm_tuning_load(os.fsencode(path)), "cm_tuning_load")
+def tuning_load(path=None):
+    """Merge a saved tuning table into the library's (path None: as for
+    tuning_save).  Raises CMError with status ESTALE for a table made for
+    another device, HIP runtime or library build."""
+    _check(load().cm_tuning_load(None if path is None else os.fsencode(path)), "cm_tuning_load")
+
+
+def build_id() -> str:
+    """The library's build id (a hash of its sources)."""
+    return load().cm_build_id().decode()
 
 
 def tuning_clear():
@@ -895,11 +907,13 @@ def plan_segmented(A, a_off, B, b_off, A_val=None, B_val=None, C=None, C_val=Non
 _DESC_FIELDS = ("A", "A_val", "m", "B", "B_val", "n", "C", "C_val", "first_block")
 
 
-def stable_merge_batch(merges, with_payload=None, stream=None):
+def stable_merge_batch(merges, with_payload=None, stream=None, upload=None):
     """Merge several separately allocated pairs of sorted device arrays in one
     launch (cm_stable_merge_batch).  merges: list of (A, B) or
-    (A, A_val, B, B_val) tuples, all of one key dtype.  Returns a list of C
-    or (C, C_val) in the same order."""
+    (A, A_val, B, B_val) tuples, all of one key dtype.  upload: copy the
+    descriptors to the device (default: only for more than
+    CM_BATCH_INLINE_MAX merges; fewer travel in the kernel arguments).
+    Returns a list of C or (C, C_val) in the same order."""
     import numpy as np
     torch = _torch()
     if not merges:
@@ -909,7 +923,7 @@ def stable_merge_batch(merges, with_payload=None, stream=None):
     device = merges[0][0].device
     s = stream if stream is not None else torch.cuda.current_stream(device)
     with torch.cuda.stream(s):  # outputs, descriptor upload and workspace all on s
-        return _merge_batch_on(merges, with_payload, s)
+        return _merge_batch_on(merges, with_payload, s, upload)
 
 
 def batch_descriptors(count):
@@ -918,21 +932,28 @@ def batch_descriptors(count):
     return np.zeros(count, dtype=np.dtype([(f, np.uint64) for f in _DESC_FIELDS]))
 
 
-def launch_batch(key_dtype, with_payload, descs, device, stream):
-    """cm_batch_prepare + upload + cm_stable_merge_batch for descriptors the
-    caller filled (pointers and sizes; first_block is set here).  Returns the
-    device buffers the call uses; they must stay alive until the stream has
-    run it (torch's allocator keeps them ordered on `stream`)."""
+BATCH_INLINE_MAX = 16  # CM_BATCH_INLINE_MAX
+
+
+def launch_batch(key_dtype, with_payload, descs, device, stream, upload=None):
+    """cm_batch_prepare + (upload) + cm_stable_merge_batch for descriptors the
+    caller filled (pointers and sizes; first_block is set here).  Without an
+    upload (the default for at most BATCH_INLINE_MAX merges) the descriptors
+    travel in the kernel arguments.  Returns the device buffers the call
+    uses; they must stay alive until the stream has run it (torch's
+    allocator keeps them ordered on `stream`)."""
     import numpy as np
     torch = _torch()
     kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
     total = ctypes.c_uint64()
     _check(load().cm_batch_prepare(kt, int(with_payload), descs.ctypes.data_as(ctypes.c_void_p),
                                    len(descs), ctypes.byref(total)), "cm_batch_prepare")
+    if upload is None:
+        upload = len(descs) > BATCH_INLINE_MAX
     with torch.cuda.stream(stream):
         # pinned staging so the upload is stream-ordered and does not block the host
-        descs_dev = torch.from_numpy(descs.view(np.uint8)).pin_memory().to(device,
-                                                                            non_blocking=True)
+        descs_dev = torch.from_numpy(descs.view(np.uint8)).pin_memory().to(
+            device, non_blocking=True) if upload else None
         ws, wsb = _workspace(load().cm_batch_workspace_size(total.value, len(descs)), device,
                              None)
     _check(load().cm_stable_merge_batch(kt, int(with_payload),
@@ -943,7 +964,7 @@ def launch_batch(key_dtype, with_payload, descs, device, stream):
     return descs_dev, ws
 
 
-def _merge_batch_on(merges, with_payload, stream):
+def _merge_batch_on(merges, with_payload, stream, upload=None):
     import numpy as np
     torch = _torch()
     prepared = []
@@ -962,5 +983,5 @@ def _merge_batch_on(merges, with_payload, stream):
         descs[r] = (A.data_ptr() if m else 0, Av.data_ptr() if with_payload and m else 0, m,
                     B.data_ptr() if n else 0, Bv.data_ptr() if with_payload and n else 0, n,
                     C.data_ptr() if m + n else 0, Cv.data_ptr() if with_payload and m + n else 0, 0)
-    launch_batch(prepared[0][4].dtype, with_payload, descs, device, stream)
+    launch_batch(prepared[0][4].dtype, with_payload, descs, device, stream, upload)
     return [(p[8], p[9]) if with_payload else p[8] for p in prepared]

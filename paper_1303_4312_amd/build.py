@@ -7,6 +7,7 @@ binding loads; nothing is installed elsewhere.
 from __future__ import annotations
 
 import concurrent.futures
+import hashlib
 import os
 import subprocess
 import sys
@@ -35,18 +36,39 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
+def build_id() -> str:
+    """First 16 hex digits of a SHA-256 over the library's sources and
+    header (names and contents): the library's build identity, compiled in
+    and written into saved tuning tables."""
+    h = hashlib.sha256()
+    files = sorted(os.listdir(CSRC))
+    for name in files:
+        if name.endswith((".hip", ".cpp", ".hpp")):
+            h.update(name.encode() + b"\0")
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(INCLUDE, "corank_merge.h"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def compile_command(src: str, obj: str, bid: str) -> list:
+    """The compile command of one source file of the library."""
+    if src.endswith(".cpp"):
+        return [hipcc(), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE,
+                f'-DCM_BUILD_ID="{bid}"', "-c", os.path.join(CSRC, src), "-o", obj]
+    return [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", os.path.join(CSRC, src),
+            "-o", obj]
+
+
 def build(verbose: bool = False) -> str:
     out_dir = os.path.join(HERE, "_build")
     os.makedirs(out_dir, exist_ok=True)
     cmds, objs = [], []
+    bid = build_id()
     for src in HIP_SOURCES + CXX_SOURCES:
         obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
-        cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c",
-               os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".cpp"):
-            cmd = [hipcc(), "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE,
-                   "-c", os.path.join(CSRC, src), "-o", obj]
-        cmds.append(cmd)
+        cmds.append(compile_command(src, obj, bid))
         objs.append(obj)
     if verbose:
         for cmd in cmds:

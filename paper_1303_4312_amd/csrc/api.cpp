@@ -5,7 +5,9 @@
 #include <hip/hip_runtime_api.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
+#include <sys/stat.h>
 
 #include <algorithm>
 #include <map>
@@ -17,7 +19,22 @@
 #include "corank_merge.h"
 #include "internal.hpp"
 
+#ifndef CM_BUILD_ID
+#define CM_BUILD_ID "unversioned"
+#endif
+
+static_assert(cm::kBatchInline == CM_BATCH_INLINE_MAX, "inline descriptor counts differ");
+
 namespace cm {
+
+// Tile configurations (the cases of by_cfg in dispatch.hpp, which
+// instantiates every one for every key type and payload mode, must match).
+// E is odd so that the strided LDS accesses of the transposes (stride E
+// words) fall on distinct banks.
+const TileCfg kCfgs[] = {{256, 7}, {256, 11}, {256, 15}, {128, 7}, {512, 7}, {256, 5}, {256, 9}, {512, 11}};
+const int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
+const uint64_t kMinTile = 128 * 7;  // smallest nt * e in kCfgs
+
 namespace {
 
 // ---------------------------------------------------------------------------
@@ -154,22 +171,23 @@ struct SegWs {
   size_t bytes;
 };
 
+// The parts of a segmented merge's workspace at ws (all null when ws is
+// null: then only the byte count is wanted).
 SegWs seg_ws(void* ws, uint64_t N) {
   const uint64_t nb = (N + kMinTile - 1) / kMinTile + 1;
   const uint64_t nc = num_coarse(nb, kMinCoarse);
+  const size_t o_bj = 256;
+  const size_t o_bs = o_bj + round256(nb * sizeof(uint64_t));
+  const size_t o_jc = o_bs + round256(nb * sizeof(uint32_t));
+  const size_t o_sc = o_jc + round256(nc * sizeof(uint64_t));
   char* p = (char*)ws;
   SegWs w;
   w.flag = (uint32_t*)p;
-  size_t off = 256;
-  w.bj = (uint64_t*)(p + off);
-  off += round256(nb * sizeof(uint64_t));
-  w.bs = (uint32_t*)(p + off);
-  off += round256(nb * sizeof(uint32_t));
-  w.jc = (uint64_t*)(p + off);
-  off += round256(nc * sizeof(uint64_t));
-  w.sc = (uint32_t*)(p + off);
-  off += round256(nc * sizeof(uint32_t));
-  w.bytes = off;
+  w.bj = p ? (uint64_t*)(p + o_bj) : nullptr;
+  w.bs = p ? (uint32_t*)(p + o_bs) : nullptr;
+  w.jc = p ? (uint64_t*)(p + o_jc) : nullptr;
+  w.sc = p ? (uint32_t*)(p + o_sc) : nullptr;
+  w.bytes = o_sc + round256(nc * sizeof(uint32_t));
   return w;
 }
 
@@ -266,16 +284,48 @@ int seg_impl(int kt, const void* A, const uint32_t* Av, const uint64_t* a_off, u
   return rc;
 }
 
-// Block size a batch of separate merges uses (from its total output count).
+// Is there a tuning-table entry for this call?
+bool tuned(int op, int kt, bool val, uint64_t N) {
+  std::lock_guard<std::mutex> lk(g_tuning_mu);
+  return g_tuning.count(TuneKey{op, kt, val ? 1 : 0, size_class(N)}) != 0;
+}
+
+// Block size and boundary mode of a batch of separate merges (from its
+// total output count).  Automatically: no pass (mode 4) for a batch of at
+// most kBatchInline merges, each below kInBlockBelow outputs (one launch,
+// descriptors in the kernel arguments; measured on the serving runtime's
+// low-load batches: p50 0.067-0.073 ms and 2.8-3.0 TB/s while busy,
+// against 0.079-0.085 ms and 2.1-2.3 TB/s with a pass), else the two-level
+// pass.
 Choice batch_choice(int kt, bool val, const cm_merge_desc* d, uint32_t count) {
-  uint64_t N = 0;
+  uint64_t N = 0, largest = 0;
   for (uint32_t r = 0; r < count; ++r) {  // saturating: only the size class matters here
     const uint64_t x = d[r].m + d[r].n;
     N = (x < d[r].m || N + x < N) ? UINT64_MAX : N + x;
+    largest = std::max(largest, x < d[r].m ? UINT64_MAX : x);
   }
   Choice ch = resolve(kOpBatch, kt, val, N);
-  ch.partition = 0;  // per-merge boundaries: one-level pass
+  if (ch.partition == 3) ch.partition = 2;  // no streaming form for batches: the two-level pass
+  if (g_set.partition < 0 && !tuned(kOpBatch, kt, val, N) && count <= kBatchInline && largest < kInBlockBelow)
+    ch.partition = 4;
   return ch;
+}
+
+// Workspace of a batch: one co-rank per boundary slot (a slot per block end
+// of every merge), the coarse slots of the two-level pass (every
+// kMinCoarse-th slot at most), and one merge index per block.
+uint64_t batch_slots(uint64_t total_blocks, uint32_t count) { return total_blocks + count; }
+size_t batch_coarse_offset(uint64_t total_blocks, uint32_t count) {
+  return round256(batch_slots(total_blocks, count) * sizeof(uint64_t));
+}
+size_t batch_index_offset(uint64_t total_blocks, uint32_t count) {
+  const uint64_t nb = batch_slots(total_blocks, count);
+  return batch_coarse_offset(total_blocks, count) + round256((nb + kMinCoarse - 1) / kMinCoarse * sizeof(uint64_t));
+}
+// then room for a device copy of up to kBatchInline descriptors (a small
+// batch's descriptors come in the kernel arguments; the pass leaves a copy)
+size_t batch_descs_offset(uint64_t total_blocks, uint32_t count) {
+  return batch_index_offset(total_blocks, count) + round256(total_blocks * sizeof(uint32_t));
 }
 
 // ---- stable merge sort
@@ -364,6 +414,58 @@ int time_calls(F&& f, int reps, hipStream_t st, double* ms) {
   return rc;
 }
 
+// Identity of a saved tuning table: the device architecture (gcnArchName
+// of the current device; "none" without one), the HIP runtime version and
+// the library's build id (a hash of its sources).
+struct Identity {
+  std::string arch = "none";
+  int runtime = 0;
+  std::string build = CM_BUILD_ID;
+};
+
+Identity current_identity() {
+  Identity id;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.gcnArchName[0])
+    id.arch = prop.gcnArchName;
+  int v = 0;
+  if (hipRuntimeGetVersion(&v) == hipSuccess) id.runtime = v;
+  (void)hipGetLastError();  // no device is not an error of later calls
+  return id;
+}
+
+// The tuning file: `path`, or with path null $CM_TUNING_FILE, else
+// $XDG_CACHE_HOME/corank_merge/tuning.txt, else
+// $HOME/.cache/corank_merge/tuning.txt.  For a save of the default file its
+// directories are created.
+bool tuning_path(const char* path, bool for_save, std::string* out) {
+  if (path) {
+    *out = path;
+    return true;
+  }
+  const char* env = getenv("CM_TUNING_FILE");
+  if (env && *env) {
+    *out = env;
+    return true;
+  }
+  std::string dir;
+  const char* xdg = getenv("XDG_CACHE_HOME");
+  const char* home = getenv("HOME");
+  if (xdg && *xdg)
+    dir = xdg;
+  else if (home && *home)
+    dir = std::string(home) + "/.cache";
+  else
+    return false;
+  if (for_save) {
+    (void)mkdir(dir.c_str(), 0755);
+    (void)mkdir((dir + "/corank_merge").c_str(), 0755);
+  }
+  *out = dir + "/corank_merge/tuning.txt";
+  return true;
+}
+
 }  // namespace
 }  // namespace cm
 
@@ -393,6 +495,7 @@ const char* cm_status_string(int status) {
     case CM_ECONFIG: return "unknown tile configuration";
     case CM_EBUSY: return "every request slot is taken";
     case CM_ECANCELED: return "canceled at shutdown";
+    case CM_ESTALE: return "tuning table made for another device, runtime or library build";
     default: return "unknown status";
   }
 }
@@ -497,7 +600,7 @@ int cm_batch_prepare(int key_type, int with_payload, cm_merge_desc* descs, uint3
 }
 
 size_t cm_batch_workspace_size(uint64_t total_blocks, uint32_t count) {
-  return round256((total_blocks + count) * sizeof(uint64_t));
+  return batch_descs_offset(total_blocks, count) + round256(kBatchInline * sizeof(cm_merge_desc));
 }
 
 int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* descs_host,
@@ -505,10 +608,11 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
                           size_t workspace_bytes, hipStream_t stream) {
   if (!key_type_ok(key_type)) return CM_EDTYPE;
   if (count == 0) return total_blocks == 0 ? CM_OK : CM_EINVAL;
-  if (!descs_host || !descs_dev) return CM_EINVAL;
+  // small batches may leave the descriptors on the host: they travel in the kernel arguments
+  if (!descs_host || (!descs_dev && count > kBatchInline)) return CM_EINVAL;
   const bool val = with_payload != 0;
   const size_t ks = key_bytes(key_type);
-  const Choice ch = batch_choice(key_type, val, descs_host, count);
+  Choice ch = batch_choice(key_type, val, descs_host, count);
   const uint64_t T = tile_size(ch.cfg);
   std::vector<Span> outs, ins;
   outs.reserve(2 * (size_t)count + 1);
@@ -539,16 +643,27 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
   const size_t need = cm_batch_workspace_size(total_blocks, count);
   if (!workspace || workspace_bytes < need) return CM_ENOSPC;
   outs.push_back({workspace, need});
-  ins.push_back({descs_dev, (uint64_t)count * sizeof(cm_merge_desc)});
+  if (descs_dev) ins.push_back({descs_dev, (uint64_t)count * sizeof(cm_merge_desc)});
   if (spans_overlap(outs, ins)) return CM_EALIAS;
   if (total_blocks == 0) return CM_OK;
   uint64_t* bj = (uint64_t*)workspace;
+  uint64_t* coarse = (uint64_t*)((char*)workspace + batch_coarse_offset(total_blocks, count));
+  uint32_t* bm = (uint32_t*)((char*)workspace + batch_index_offset(total_blocks, count));
+  void* wd = (char*)workspace + batch_descs_offset(total_blocks, count);
+  // no pass (every block co-ranks its own ends) only for batches whose
+  // descriptors fit in the kernel arguments; larger ones take two levels
+  const bool self = ch.partition == 4 && count <= kBatchInline;
+  if (ch.partition == 4 && !self) ch.partition = 2;
   timing_mark(0, stream);
-  int rc = launch_batch_co_ranks(key_type, ch, descs_dev, count, T, total_blocks + count, bj, stream);
-  if (rc != CM_OK) return rc;
+  if (!self) {
+    const int rc = launch_batch_co_ranks(key_type, ch, g_set.shape, descs_host, descs_dev, wd, count, T,
+                                         batch_slots(total_blocks, count), bj, coarse, bm, stream);
+    if (rc != CM_OK) return rc;
+  }
   timing_mark(1, stream);
-  rc = launch_batch_merge_blocks(key_type, val, ch, descs_dev, count, bj, total_blocks, vec, g_set.shape.xcd_order,
-                                 stream);
+  const int rc = launch_batch_merge_blocks(key_type, val, ch, descs_host, descs_dev ? descs_dev : wd, count,
+                                           self ? nullptr : bj, bm, total_blocks, vec, g_set.shape.xcd_order,
+                                           stream);
   timing_mark(2, stream);
   return rc;
 }
@@ -749,15 +864,19 @@ int cm_tuning_get(int op, int key_type, int with_payload, uint64_t num_outputs, 
   const Choice ch = resolve(op, key_type, with_payload != 0, num_outputs);
   choice[0] = ch.cfg;
   choice[1] = ch.search;
-  choice[2] = op == kOpBatch ? 0 : ch.partition;  // a batch always takes the one-level pass (batch_choice)
+  choice[2] = op == kOpBatch && ch.partition == 3 ? 2 : ch.partition;  // as batch_choice
   return CM_OK;
 }
 
 int cm_tuning_save(const char* path) {
-  if (!path) return CM_EINVAL;
-  FILE* f = fopen(path, "w");
+  std::string p;
+  if (!tuning_path(path, true, &p)) return CM_EINVAL;
+  FILE* f = fopen(p.c_str(), "w");
   if (!f) return CM_EINVAL;
-  fprintf(f, "# corank_merge tuning v1: op key_type with_payload size_class config search partition ms\n");
+  const Identity id = current_identity();
+  fprintf(f, "# corank_merge tuning v2\n# arch %s\n# hip_runtime %d\n# library %s\n", id.arch.c_str(), id.runtime,
+          id.build.c_str());
+  fprintf(f, "# op key_type with_payload size_class config search partition ms\n");
   {
     std::lock_guard<std::mutex> lk(g_tuning_mu);
     for (const auto& kv : g_tuning) {
@@ -771,14 +890,34 @@ int cm_tuning_save(const char* path) {
 }
 
 int cm_tuning_load(const char* path) {
-  if (!path) return CM_EINVAL;
-  FILE* f = fopen(path, "r");
+  std::string p;
+  if (!tuning_path(path, false, &p)) return CM_EINVAL;
+  FILE* f = fopen(p.c_str(), "r");
   if (!f) return CM_EINVAL;
-  char line[256];
+  char line[512];
   int rc = CM_OK;
   std::map<TuneKey, TuneEntry> loaded;
+  Identity file_id;
+  bool v2 = false, have_arch = false, have_runtime = false, have_build = false;
   while (fgets(line, sizeof line, f)) {
-    if (line[0] == '#' || line[0] == '\n') continue;
+    if (line[0] == '\n') continue;
+    if (line[0] == '#') {
+      char word[256] = {0};
+      int num = 0;
+      if (strncmp(line, "# corank_merge tuning v2", 24) == 0) {
+        v2 = true;
+      } else if (sscanf(line, "# arch %255s", word) == 1) {
+        file_id.arch = word;
+        have_arch = true;
+      } else if (sscanf(line, "# hip_runtime %d", &num) == 1) {
+        file_id.runtime = num;
+        have_runtime = true;
+      } else if (sscanf(line, "# library %255s", word) == 1) {
+        file_id.build = word;
+        have_build = true;
+      }
+      continue;
+    }
     int op, kt, val, sc, cfg, search, part;
     double ms;
     if (sscanf(line, "%d %d %d %d %d %d %d %lf", &op, &kt, &val, &sc, &cfg, &search, &part, &ms) != 8 ||
@@ -791,10 +930,18 @@ int cm_tuning_load(const char* path) {
   }
   fclose(f);
   if (rc != CM_OK) return rc;
+  // a table is timed on one device type, runtime and library build: one
+  // made elsewhere (or with no identity) is refused
+  const Identity id = current_identity();
+  if (!v2 || !have_arch || !have_runtime || !have_build || file_id.arch != id.arch ||
+      file_id.runtime != id.runtime || file_id.build != id.build)
+    return CM_ESTALE;
   std::lock_guard<std::mutex> lk(g_tuning_mu);
   for (const auto& kv : loaded) g_tuning[kv.first] = kv.second;
   return CM_OK;
 }
+
+const char* cm_build_id(void) { return CM_BUILD_ID; }
 
 // ---- graph plans
 

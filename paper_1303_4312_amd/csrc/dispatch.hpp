@@ -1,5 +1,5 @@
 // Host-side template dispatch shared by the launcher files: key type and
-// tile configuration (the cases of by_cfg must match kCfgs in launch.hip).
+// tile configuration (the cases of by_cfg must match kCfgs in api.cpp).
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -25,13 +25,6 @@ extern template struct Launch<Desc<uint64_t>>;
 extern template struct Launch<float>;
 extern template struct Launch<Desc<float>>;
 
-// Every configuration is instantiated for every key type and payload mode.
-// E is odd so that the strided LDS accesses of the transposes (stride E
-// words) fall on distinct banks.
-const TileCfg kCfgs[] = {{256, 7}, {256, 11}, {256, 15}, {128, 7}, {512, 7}, {256, 5}, {256, 9}, {512, 11}};
-const int kNumCfgs = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
-const uint64_t kMinTile = 128 * 7;  // smallest nt * e in kCfgs
-
 // ---- non-template kernels (launched from this file only)
 
 // flag |= 1 if the offsets are inconsistent (not starting at 0, decreasing
@@ -314,14 +307,20 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
 static_assert(sizeof(MergeDesc) == sizeof(cm_merge_desc), "descriptor layouts differ");
 static_assert(offsetof(MergeDesc, first_block) == offsetof(cm_merge_desc, first_block), "descriptor layouts differ");
 
-int launch_batch_co_ranks(int kt, const Choice& ch, const void* d, uint32_t count, uint64_t tile, uint64_t nb,
-                          uint64_t* bj, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::batch_co_ranks(ch, d, count, tile, nb, bj, st); });
+int launch_batch_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* h, const void* d, void* wd,
+                          uint32_t count, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, uint32_t* bm,
+                          hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    return Launch<decltype(key)>::batch_co_ranks(ch, sh, h, d, wd, count, tile, nb, bj, coarse, bm, st);
+  });
 }
 
-int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* d, uint32_t count,
-                              const uint64_t* bj, uint64_t tiles, bool vec, int xcd, hipStream_t st) {
-  return by_key(kt, [&](auto key) -> int { return Launch<decltype(key)>::batch_merge_blocks(val, ch, d, count, bj, tiles, vec, xcd, st); });
+int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* h, const void* d, uint32_t count,
+                              const uint64_t* bj, const uint32_t* bm, uint64_t tiles, bool vec, int xcd,
+                              hipStream_t st) {
+  return by_key(kt, [&](auto key) -> int {
+    return Launch<decltype(key)>::batch_merge_blocks(val, ch, h, d, count, bj, bm, tiles, vec, xcd, st);
+  });
 }
 
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,

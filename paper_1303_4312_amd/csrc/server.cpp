@@ -20,7 +20,7 @@
 #include "internal.hpp"
 #include "ring_alloc.hpp"
 
-static_assert(sizeof(cm_server_done) == 64, "cm_server_done layout (mirrored by the Python binding)");
+static_assert(sizeof(cm_server_done) == 80, "cm_server_done layout (mirrored by the Python binding)");
 static_assert(sizeof(cm_server_stats) == 80, "cm_server_stats layout (mirrored by the Python binding)");
 
 namespace {
@@ -50,7 +50,8 @@ struct Request {
   int copy_status = CM_OK;        // enqueueing the copy in
   bool out_pending = false;       // outputs being copied back (done when out_done is)
   hipEvent_t out_done = nullptr;  // recorded on copy_out after this request's copies
-  Clock::time_point t_submit, t_launch;
+  Clock::time_point t_submit, t_launch, t_ended;
+  uint64_t device_ns = 0;  // device time of the batch that ran it
 };
 
 struct Slot {  // one batch in flight
@@ -215,10 +216,14 @@ uint32_t launch(cm_server* s, Slot& b) {
     else
       rc = CM_EHIP;
   }
-  if (rc == CM_OK &&
+  // a small batch's descriptors travel in the kernel arguments: no upload
+  const bool inline_descs = n <= CM_BATCH_INLINE_MAX;
+  if (rc == CM_OK && !inline_descs &&
       hipMemcpyAsync(b.dev, b.host, (size_t)n * sizeof(cm_merge_desc), hipMemcpyHostToDevice, b.stream) != hipSuccess)
     rc = CM_EHIP;
-  if (rc == CM_OK) rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, b.dev, n, total, b.ws, b.ws_bytes, b.stream);
+  if (rc == CM_OK)
+    rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, inline_descs ? nullptr : b.dev, n, total, b.ws,
+                               b.ws_bytes, b.stream);
   // the end event is recorded whatever happened, so completion is detected the same way
   if (hipEventRecord(b.end, b.stream) != hipSuccess && rc == CM_OK) rc = CM_EHIP;
   // host requests: their outputs go back on copy_out once the batch has
@@ -265,6 +270,8 @@ void finish_request(cm_server* s, uint32_t idx, int status, Clock::time_point no
     e.vals_offset = r.vals_off;
     e.queued_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r.t_launch - r.t_submit).count();
     e.latency_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(now - r.t_submit).count();
+    e.ended_ns = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(r.t_ended - r.t_submit).count();
+    e.device_ns = r.device_ns;
     s->done.push_back(e);
     if (status == CM_OK)
       s->st.completed += 1;
@@ -273,11 +280,14 @@ void finish_request(cm_server* s, uint32_t idx, int status, Clock::time_point no
   }
 }
 
-// A slot's batch has ended (mu held): report its requests, except host
-// requests whose outputs are still on their way back, and free the slot.
-void finish(cm_server* s, Slot& b, int status) {
+// A slot's batch has ended (mu held; seen at `ended`, device time
+// device_ns): report its requests, except host requests whose outputs are
+// still on their way back, and free the slot.
+void finish(cm_server* s, Slot& b, int status, Clock::time_point ended, uint64_t device_ns) {
   const Clock::time_point now = Clock::now();
   for (uint32_t idx : b.reqs) {
+    s->reqs[idx].t_ended = ended;
+    s->reqs[idx].device_ns = device_ns;
     if (status == CM_OK && s->reqs[idx].out_pending)
       s->outgoing.push_back(idx);
     else
@@ -332,13 +342,14 @@ void scheduler(cm_server* s) {
       int status;
       bool timed;
       float t0, t1;
+      Clock::time_point seen;
     };
     std::vector<Finished> finished;
     for (Slot& b : s->slots) {
       if (!b.busy) continue;
       const hipError_t q = hipEventQuery(b.end);
       if (q == hipErrorNotReady) continue;
-      Finished f{&b, b.status, false, 0.f, 0.f};
+      Finished f{&b, b.status, false, 0.f, 0.f, Clock::now()};
       if (q != hipSuccess && f.status == CM_OK) f.status = CM_EHIP;
       f.timed = b.timed && hipEventElapsedTime(&f.t0, s->ref, b.start) == hipSuccess &&
                 hipEventElapsedTime(&f.t1, s->ref, b.end) == hipSuccess;
@@ -363,7 +374,7 @@ void scheduler(cm_server* s) {
     }
     for (const Finished& f : finished) {
       if (f.timed) s->intervals.emplace_back(f.t0, f.t1);
-      finish(s, *f.b, f.status);
+      finish(s, *f.b, f.status, f.seen, f.timed ? (uint64_t)((double)(f.t1 - f.t0) * 1e6) : 0);
     }
     const Clock::time_point now = Clock::now();
     for (const auto& rb : back) finish_request(s, rb.first, rb.second, now);
@@ -372,11 +383,17 @@ void scheduler(cm_server* s) {
       s->cv_done.notify_all();
     }
     if (!progressed) {
-      // admitted requests still waiting for their inputs count as work in flight
-      bool any_busy = !s->outgoing.empty() || !s->admitted.empty();
-      for (const Slot& b : s->slots) any_busy = any_busy || b.busy;
-      // poll in-flight batches every 20 us; otherwise sleep until woken
-      if (any_busy)
+      bool in_flight = !s->outgoing.empty();
+      for (const Slot& b : s->slots) in_flight = in_flight || b.busy;
+      // batches or copies in flight: poll their events again at once (a
+      // timed wait would oversleep by tens of microseconds, each added to
+      // the latency of every request in the batch); admitted requests still
+      // waiting for their inputs: poll every 20 us; otherwise sleep until woken
+      if (in_flight) {
+        lk.unlock();
+        std::this_thread::yield();
+        lk.lock();
+      } else if (!s->admitted.empty())
         s->cv_sched.wait_for(lk, std::chrono::microseconds(20));
       else if (!s->stop && s->pending.empty())
         s->cv_sched.wait(lk);

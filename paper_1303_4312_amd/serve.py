@@ -355,11 +355,12 @@ class Server:
 
 
 class ServerDone(ctypes.Structure):
-    """cm_server_done (64 bytes)."""
+    """cm_server_done (80 bytes)."""
     _fields_ = [("ticket", ctypes.c_uint64), ("status", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("C", ctypes.c_void_p), ("C_val", ctypes.c_void_p),
                 ("keys_offset", ctypes.c_uint64), ("vals_offset", ctypes.c_uint64),
-                ("queued_ns", ctypes.c_uint64), ("latency_ns", ctypes.c_uint64)]
+                ("queued_ns", ctypes.c_uint64), ("latency_ns", ctypes.c_uint64),
+                ("ended_ns", ctypes.c_uint64), ("device_ns", ctypes.c_uint64)]
 
 
 class ServerStats(ctypes.Structure):

@@ -226,8 +226,13 @@ def test_tuning_table_host_logic(tmp_path, restore_settings):
     cm.set_config("uint32", False, -1)
     assert cm.get_config("uint32", False) == -1 and tile(False, 1 << 22) == 7
     assert cm.tuning_get(cm.OP_SEGMENTED, "uint32", True, 1000)[2] == 2
-    # a batch of separate merges always co-ranks its boundaries in one level
-    assert cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 30)[2] == 0
+    # a batch of separate merges: two-level pass automatically, any mode
+    # when set, the streaming mode taken as two-level
+    assert cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 30)[2] == 2
+    for mode, batch_mode in ((0, 0), (1, 1), (2, 2), (3, 2), (4, 4)):
+        cm.set_partition(mode)
+        assert cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 20)[2] == batch_mode
+    cm.set_partition(-1)
     with pytest.raises(cm.CMError):
         cm.tuning_get(cm.OP_SORT + 1, "uint32", True, 1000)
     with pytest.raises(cm.CMError):
@@ -252,6 +257,57 @@ def test_tuning_table_host_logic(tmp_path, restore_settings):
     assert cm.tuning_count() == 2
     with pytest.raises(cm.CMError):
         cm.tuning_set(cm.OP_MERGE, "uint32", True, 10, cm.config_count(), 0, 0)
+    cm.tuning_clear()
+
+
+def test_tuning_file_identity(tmp_path, monkeypatch):
+    """A saved table names the device architecture, HIP runtime and library
+    build it was timed with; one naming anything else, or nothing, is
+    refused with CM_ESTALE and leaves the table as it was.  With no path the
+    file is $CM_TUNING_FILE, else the user's cache directory."""
+    cm.tuning_clear()
+    cm.tuning_set(cm.OP_MERGE, "uint32", True, 12, 2, 1, 0)
+    good = tmp_path / "tune.txt"
+    cm.tuning_save(str(good))
+    text = good.read_text()
+    head = [l for l in text.splitlines() if l.startswith("#")]
+    assert head[0] == "# corank_merge tuning v2"
+    assert f"# library {cm.build_id()}" in head
+    assert any(l.startswith("# arch ") for l in head) and any(l.startswith("# hip_runtime ") for l in head)
+    assert len(cm.build_id()) == 16
+    cm.tuning_clear()
+    cm.tuning_load(str(good))
+    assert cm.tuning_count() == 1
+    for old, new in (("# library " + cm.build_id(), "# library 0123456789abcdef"),
+                     ("# arch ", "# arch gfx000-"), ("# hip_runtime ", "# hip_runtime 1")):
+        stale = tmp_path / "stale.txt"
+        line = next(l for l in text.splitlines() if l.startswith(old))
+        stale.write_text(text.replace(line, line.replace(old, new) if old.endswith(" ") else new))
+        cm.tuning_clear()
+        with pytest.raises(cm.CMError) as err:
+            cm.tuning_load(str(stale))
+        assert err.value.status == cm.ESTALE
+        assert cm.tuning_count() == 0
+    # an identity-free table (the old format) is refused the same way
+    plain = tmp_path / "plain.txt"
+    plain.write_text("\n".join(l for l in text.splitlines() if not l.startswith("#")) + "\n")
+    with pytest.raises(cm.CMError) as err:
+        cm.tuning_load(str(plain))
+    assert err.value.status == cm.ESTALE
+    # default location: the environment variable, then the cache directory
+    env_file = tmp_path / "env" / "t.txt"
+    env_file.parent.mkdir()
+    monkeypatch.setenv("CM_TUNING_FILE", str(env_file))
+    cm.tuning_set(cm.OP_MERGE, "uint32", True, 12, 2, 1, 0)
+    cm.tuning_save()
+    assert env_file.read_text() == text
+    cm.tuning_clear()
+    cm.tuning_load()
+    assert cm.tuning_get(cm.OP_MERGE, "uint32", True, 3000)[:3] == (2, 1, 0)
+    monkeypatch.delenv("CM_TUNING_FILE")
+    monkeypatch.setenv("XDG_CACHE_HOME", str(tmp_path / "cache"))
+    cm.tuning_save()
+    assert (tmp_path / "cache" / "corank_merge" / "tuning.txt").read_text() == text
     cm.tuning_clear()
 
 
@@ -324,6 +380,18 @@ def test_batch_prepare_and_argument_errors():
     assert lib.cm_stable_merge_batch(0, 0, pay.ctypes.data_as(ctypes.c_void_p), P(0x1000), 3,
                                      total.value, P(0x2000), need, None) == EINVAL
     assert lib.cm_stable_merge_batch(0, 0, None, None, 0, 0, None, 0, None) == OK
+    # no device copy of the descriptors: allowed up to CM_BATCH_INLINE_MAX
+    # merges (checked here with an output over an input, refused before any
+    # launch), refused above
+    assert lib.cm_stable_merge_batch(0, 0, alias.ctypes.data_as(ctypes.c_void_p), None, 3,
+                                     total.value, P(0x2000), need, None) == EALIAS
+    over = np.zeros(cm.BATCH_INLINE_MAX + 1, dtype=descs.dtype)
+    assert lib.cm_batch_prepare(0, 0, over.ctypes.data_as(ctypes.c_void_p), len(over),
+                                ctypes.byref(total)) == OK
+    assert lib.cm_stable_merge_batch(0, 0, over.ctypes.data_as(ctypes.c_void_p), None, len(over),
+                                     total.value, P(0x2000), 1 << 20, None) == EINVAL
+    # the workspace holds one co-rank per block end and a coarse part
+    assert lib.cm_batch_workspace_size(1000, 24) >= 8 * 1024 + 8 * (1024 // 16) + 4 * 1000
     # a batch whose block count reaches 2^31 is refused (checked merge by
     # merge, so the running sum cannot wrap); one such merge alone is fine
     many = np.zeros(64, dtype=descs.dtype)
@@ -513,3 +581,11 @@ def test_c_client_builds_against_the_header(tmp_path):
     from tests import c_client
     exe = c_client.build(str(tmp_path))
     assert os.path.exists(exe)
+
+
+def test_server_struct_mirrors():
+    """The binding's ctypes mirrors of cm_server_done / cm_server_stats have
+    the sizes the library asserts (80 bytes each)."""
+    from paper_1303_4312_amd import serve
+    assert ctypes.sizeof(serve.ServerDone) == 80
+    assert ctypes.sizeof(serve.ServerStats) == 80

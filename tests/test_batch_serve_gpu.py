@@ -117,3 +117,63 @@ def test_serving_refuses_request_over_budget():
     with srv:
         with pytest.raises(serve.BudgetError):
             srv.submit(*r).result(timeout=30)
+
+
+@pytest.mark.parametrize("partition", [0, 1, 2, 4])
+@pytest.mark.parametrize("count,upload", [(9, False), (9, True), (16, False), (40, True)])
+@pytest.mark.parametrize("stride", [16, 64])
+def test_batch_boundary_modes(partition, count, upload, stride, restore_settings):
+    """Every boundary mode of a batch (one-level pass, two-level pass with
+    64- or 16-lane coarse searches, no pass), descriptors in the kernel
+    arguments or uploaded, coarse strides that put coarse slots in some
+    merges and none in others; empty, one-element and lopsided merges among
+    them, keys and payloads against the oracle."""
+    print(f"[batch modes] partition={partition} count={count} upload={upload} stride={stride}",
+          flush=True)
+    cm.set_partition(partition)
+    cm.set_coarse_stride(stride)
+    rng = np.random.default_rng(600 + count)
+    host, merges = [], []
+    fixed = [(0, 0), (1, 0), (0, 1), (1 << 16, 3), (5, 200_001)]
+    for k in range(count):
+        if k < len(fixed):
+            m, n = fixed[k]
+        else:
+            m, n = (int(x) for x in np.exp(rng.uniform(0, np.log(300_000), 2)))
+        hi = (3, 1000, 1 << 30)[k % 3]
+        A = np.sort(rng.integers(0, hi, m)).astype(np.uint32)
+        B = np.sort(rng.integers(0, hi, n)).astype(np.uint32)
+        Av, Bv = workloads.origin_payloads(m, n)
+        host.append((A, B, Av, Bv))
+        merges.append((to_dev(A), to_dev(Av), to_dev(B), to_dev(Bv)))
+    outs = cm.stable_merge_batch(merges, upload=upload)
+    for k, ((A, B, Av, Bv), (C, Cv)) in enumerate(zip(host, outs)):
+        Ce, Cve = oracle.stable_merge(A, B, Av, Bv)
+        assert same_bits(to_host(C), Ce), f"merge {k} ({A.size}, {B.size}): keys"
+        assert same_bits(to_host(Cv), Cve), f"merge {k} ({A.size}, {B.size}): payloads"
+    keys_only = cm.stable_merge_batch([(m[0], m[2]) for m in merges], upload=upload)
+    for k, ((A, B, _, _), C) in enumerate(zip(host, keys_only)):
+        assert same_bits(to_host(C), oracle.stable_merge(A, B)), f"merge {k}: keys only"
+
+
+@pytest.mark.parametrize("dtype", [np.uint64, np.float32])
+@pytest.mark.parametrize("partition", [2, 4])
+def test_batch_modes_other_keys(dtype, partition, restore_settings):
+    cm.set_partition(partition)
+    rng = np.random.default_rng(650)
+    host, merges = [], []
+    for m, n in ((70_001, 3), (0, 5), (40_000, 90_000), (1, 1), (123_457, 65_536)):
+        if np.dtype(dtype) == np.float32:
+            A = np.sort(rng.standard_normal(m).astype(np.float32))
+            B = np.sort(rng.standard_normal(n).astype(np.float32))
+        else:
+            A = np.sort(rng.integers(0, 1 << 63, m, dtype=np.uint64))
+            B = np.sort(rng.integers(0, 1 << 63, n, dtype=np.uint64))
+        Av, Bv = workloads.origin_payloads(m, n)
+        host.append((A, B, Av, Bv))
+        merges.append((to_dev(A), to_dev(Av), to_dev(B), to_dev(Bv)))
+    for upload in (False, True):
+        outs = cm.stable_merge_batch(merges, upload=upload)
+        for (A, B, Av, Bv), (C, Cv) in zip(host, outs):
+            Ce, Cve = oracle.stable_merge(A, B, Av, Bv)
+            assert same_bits(to_host(C), Ce) and same_bits(to_host(Cv), Cve)
