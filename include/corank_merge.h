@@ -151,6 +151,30 @@ int cm_stable_merge_pairs(int key_type,
                           hipStream_t stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the merge
+ * of cm_stable_merge_pairs (payload pointers all NULL: cm_stable_merge)
+ * with no workspace argument.  Its block co-ranks go to a scratch array of
+ * CM_NOALLOC_SCRATCH_BYTES (4 MiB) in the library's device code, one per
+ * GPU, held from the first call on that GPU until the process ends.  The
+ * call allocates nothing and runs the same kernels with the same tile and
+ * boundary choice, so the results are those of cm_stable_merge_pairs.
+ * Limit: merges whose cm_merge_workspace_size fits the scratch array (up to
+ * about 4.4e8 outputs); larger ones are refused with CM_ENOSPC before
+ * anything is enqueued.  Every call on one GPU shares that GPU's array and
+ * leaves its contents behind (each call writes every co-rank it reads, so
+ * nothing needs clearing): calls whose kernels may overlap on one GPU (on
+ * different streams, or from different threads) race and must not be
+ * made.  Errors: those of cm_stable_merge_pairs, and CM_EHIP if the
+ * scratch array's device address cannot be found.
+ */
+#define CM_NOALLOC_SCRATCH_BYTES (4u << 20)
+int cm_stable_merge_pairs_noalloc(int key_type,
+                                  const void *A, const uint32_t *A_val, uint64_t m,
+                                  const void *B, const uint32_t *B_val, uint64_t n,
+                                  void *C, uint32_t *C_val, hipStream_t stream);
+
+/*
  * Stable merge of (key, uint64 payload) pairs (Sections 1-3): as
  * cm_stable_merge_pairs with 8-byte payloads (A_val: m, B_val: n, C_val:
  * m + n uint64 device arrays), moved by the same kernels; for 8-byte

@@ -29,7 +29,7 @@ __all__ = [
     "tuning_load", "tuning_clear", "tuning_count", "build_id", "ESTALE", "Plan", "plan_merge", "plan_segmented",
     "OP_MERGE", "OP_SEGMENTED", "OP_BATCH", "OP_SORT", "stable_merge_batch", "batch_descriptors",
     "stable_sort", "sort_workspace_size", "merge_partition_ablation", "origin_codes",
-    "gather_records", "merge_records",
+    "gather_records", "merge_records", "stable_merge_pairs_noalloc", "NOALLOC_SCRATCH_BYTES",
     "launch_batch", "set_coarse_stride", "set_block_order", "set_fine_lanes", "get_block_order",
     "get_coarse_stride", "get_fine_lanes", "set_grid", "get_grid",
 ]
@@ -48,6 +48,7 @@ KEY_TYPES = {"uint32": KEY_U32, "uint64": KEY_U64, "float32": KEY_F32}
 EXPORTS = [
     "cm_status_string", "cm_version", "cm_co_rank_host", "cm_co_rank",
     "cm_merge_workspace_size", "cm_stable_merge", "cm_stable_merge_pairs", "cm_stable_merge_pairs64",
+    "cm_stable_merge_pairs_noalloc",
     "cm_segmented_workspace_size", "cm_stable_merge_segmented", "cm_check_sorted",
     "cm_config_count", "cm_config_info", "cm_set_config", "cm_get_config",
     "cm_set_search", "cm_get_search", "cm_set_partition", "cm_get_partition",
@@ -102,6 +103,7 @@ def load():
         "cm_stable_merge": (c_int, [c_int, vp, c_u64, vp, c_u64, vp, vp, c_size, vp]),
         "cm_stable_merge_pairs": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp,
                                           c_size, vp]),
+        "cm_stable_merge_pairs_noalloc": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp]),
         "cm_stable_merge_pairs64": (c_int, [c_int, vp, vp, c_u64, vp, vp, c_u64, vp, vp, vp,
                                             c_size, vp]),
         "cm_segmented_workspace_size": (c_size, [c_int, c_int, c_u64, c_u64, c_u64]),
@@ -372,6 +374,26 @@ def stable_merge_pairs(A, A_val, B, B_val, C=None, C_val=None, workspace=None, s
                 (load().cm_stable_merge_pairs64, "cm_stable_merge_pairs64"))
     _check(fn(kt, _ptr(A), _ptr(A_val), m, _ptr(B), _ptr(B_val), n, _ptr(C), _ptr(C_val), _ptr(ws), wsb,
               _stream(stream, A.device)), name)
+    return C, C_val
+
+
+NOALLOC_SCRATCH_BYTES = 4 << 20  # CM_NOALLOC_SCRATCH_BYTES
+
+
+def stable_merge_pairs_noalloc(A, A_val, B, B_val, C, C_val, stream=None, descending=False):
+    """cm_stable_merge_pairs_noalloc: the merge of stable_merge_pairs into the
+    caller's C / C_val with no workspace and no allocation (the library's
+    per-GPU scratch array holds the block co-ranks).  Payload arguments all
+    None for keys only.  Returns (C, C_val)."""
+    A, B, C = _dev(A, "A"), _dev(B, "B"), _dev(C, "C")
+    if A_val is not None or B_val is not None or C_val is not None:
+        torch = _torch()
+        A_val, B_val = _dev(A_val, "A_val", torch.uint32), _dev(B_val, "B_val", torch.uint32)
+        C_val = _dev(C_val, "C_val", torch.uint32)
+    kt = _key_type(A, descending)
+    _check(load().cm_stable_merge_pairs_noalloc(kt, _ptr(A), _ptr(A_val), A.numel(), _ptr(B), _ptr(B_val),
+                                                B.numel(), _ptr(C), _ptr(C_val), _stream(stream, A.device)),
+           "cm_stable_merge_pairs_noalloc")
     return C, C_val
 
 

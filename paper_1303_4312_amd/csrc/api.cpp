@@ -24,6 +24,7 @@
 #endif
 
 static_assert(cm::kBatchInline == CM_BATCH_INLINE_MAX, "inline descriptor counts differ");
+static_assert(cm::kNoAllocScratchBytes == CM_NOALLOC_SCRATCH_BYTES, "scratch sizes differ");
 
 namespace cm {
 
@@ -529,6 +530,22 @@ int cm_stable_merge_pairs(int key_type, const void* A, const uint32_t* A_val, ui
                           const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, void* workspace,
                           size_t workspace_bytes, hipStream_t stream) {
   return merge_impl(key_type, true, 4, A, A_val, m, B, B_val, n, C, C_val, workspace, workspace_bytes, stream);
+}
+
+int cm_stable_merge_pairs_noalloc(int key_type, const void* A, const uint32_t* A_val, uint64_t m, const void* B,
+                                  const uint32_t* B_val, uint64_t n, void* C, uint32_t* C_val, hipStream_t stream) {
+  if (!key_type_ok(key_type)) return CM_EDTYPE;
+  if (!lengths_ok(m, n)) return CM_EINVAL;
+  const bool val = A_val || B_val || C_val;
+  // the block co-ranks must fit the scratch array (checked before anything
+  // touches the device)
+  if (merge_ws_bytes(m + n) > kNoAllocScratchBytes) return CM_ENOSPC;
+  void* ws = nullptr;
+  if (m + n) {
+    const int rc = noalloc_scratch(&ws);
+    if (rc != CM_OK) return rc;
+  }
+  return merge_impl(key_type, val, 4, A, A_val, m, B, B_val, n, C, C_val, ws, kNoAllocScratchBytes, stream);
 }
 
 int cm_stable_merge_pairs64(int key_type, const void* A, const uint64_t* A_val, uint64_t m, const void* B,

@@ -169,6 +169,13 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
 // from h in the kernel arguments (count <= kBatchInline); every block
 // co-ranks its own ends.
 constexpr uint32_t kBatchInline = 16;
+
+// The allocation-free single merge keeps its block co-ranks in a scratch
+// array of this many bytes in the library's device code (one per GPU);
+// noalloc_scratch gives its device address on the current device (looked
+// up once per device with hipGetSymbolAddress), or CM_EHIP.
+constexpr size_t kNoAllocScratchBytes = 4u << 20;
+int noalloc_scratch(void** out);
 int launch_batch_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* h, const void* d, void* wd,
                           uint32_t count, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, uint32_t* bm,
                           hipStream_t st);

@@ -25,6 +25,38 @@ extern template struct Launch<Desc<uint64_t>>;
 extern template struct Launch<float>;
 extern template struct Launch<Desc<float>>;
 
+// ---- scratch of the allocation-free entry point
+
+// The block co-ranks of cm_stable_merge_pairs_noalloc.  Each GPU holds its
+// own copy of the array for the life of the process.  In host code the
+// name stands for the array but is not a device address: the address is
+// looked up per device and kept (noalloc_scratch), and only that is ever
+// handed to a kernel.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+int noalloc_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* ptr[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return CM_EHIP;
+  }
+  if (dev < 0 || dev >= kMaxDevices) return CM_EINVAL;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!ptr[dev]) {  // once per device, with that device current
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return CM_EHIP;
+    }
+    ptr[dev] = p;
+  }
+  *out = ptr[dev];
+  return CM_OK;
+}
+
 // ---- non-template kernels (launched from this file only)
 
 // flag |= 1 if the offsets are inconsistent (not starting at 0, decreasing

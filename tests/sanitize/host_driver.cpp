@@ -66,6 +66,13 @@ static void abi_calls() {
     CHECK(cm_stable_merge(kt, nullptr, m, B.p(), n, C.p(), ws.p(), ws_bytes, nullptr) == CM_EINVAL);
   }
   CHECK(cm_stable_merge(7, A.p(), m, B.p(), n, C.p(), nullptr, 0, nullptr) == CM_EDTYPE);
+  // the allocation-free variant: same checks, the scratch array's limit
+  CHECK(cm_stable_merge_pairs_noalloc(0, A.p(), (const uint32_t*)Av.p(), m, B.p(), (const uint32_t*)Bv.p(), n, C.p(),
+                                      (uint32_t*)Cv.p(), nullptr) == CM_OK);
+  CHECK(cm_stable_merge_pairs_noalloc(0, A.p(), nullptr, m, B.p(), nullptr, n, C.p(), nullptr, nullptr) == CM_OK);
+  CHECK(cm_stable_merge_pairs_noalloc(0, A.p(), nullptr, 1ull << 40, B.p(), nullptr, n, C.p(), nullptr, nullptr) ==
+        CM_ENOSPC);
+  CHECK(cm_stable_merge_pairs_noalloc(0, A.p(), nullptr, m, B.p(), nullptr, n, A.p(), nullptr, nullptr) == CM_EALIAS);
   // grids, block orders, strides and lanes
   const size_t ws_bytes = cm_merge_workspace_size(0, 1, m, n);
   Buf ws(ws_bytes);

@@ -11,6 +11,12 @@ namespace cm {
 
 uint32_t resident_workgroups(const void*, int) { return 256; }
 
+int noalloc_scratch(void** out) {
+  static uint64_t scratch[kNoAllocScratchBytes / 8];
+  *out = scratch;
+  return CM_OK;
+}
+
 int launch_block_co_ranks(int, const Choice&, const Shape&, const void*, uint64_t, const void*, uint64_t, uint64_t,
                           uint64_t, uint64_t*, uint64_t*, hipStream_t) {
   return CM_OK;

@@ -589,3 +589,16 @@ def test_server_struct_mirrors():
     from paper_1303_4312_amd import serve
     assert ctypes.sizeof(serve.ServerDone) == 80
     assert ctypes.sizeof(serve.ServerStats) == 80
+
+
+def test_noalloc_refuses_merges_beyond_its_scratch():
+    """The allocation-free merge checks its size against the scratch array
+    before touching the device: too large is CM_ENOSPC, a bad key type
+    CM_EDTYPE, lengths past 2^48 CM_EINVAL."""
+    lib = cm.load()
+    P = ctypes.c_void_p
+    fake = P(1 << 44)
+    assert lib.cm_stable_merge_pairs_noalloc(0, fake, fake, 1 << 40, fake, fake, 0, fake, fake, None) == ENOSPC
+    assert lib.cm_stable_merge_pairs_noalloc(9, fake, fake, 10, fake, fake, 0, fake, fake, None) == EDTYPE
+    assert lib.cm_stable_merge_pairs_noalloc(0, fake, fake, 1 << 48, fake, fake, 0, fake, fake, None) == EINVAL
+    assert cm.NOALLOC_SCRATCH_BYTES == 4 << 20
