@@ -740,7 +740,7 @@ def tile_copy_ceiling(cfg, A, Av, B, Bv, reps=20):
 
 
 def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1.0, 1.1),
-                seed=5000, python_scheduler=True):
+                seed=5000, python_scheduler=True, max_batch=64, max_inflight=2):
     """Serving: requests with sides log-uniform in [2^10, 2^24] (uint32 key +
     payload, uniform keys), staged in HBM before they arrive.  The library's
     serving runtime (cm_server_*: a native scheduler thread) admits them
@@ -772,8 +772,8 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
 
     def run_native(arrivals, check=False):
         total = len(arrivals)
-        srv = serve.NativeServer("uint32", True, arena=arena, max_batch=64, max_inflight=2,
-                                 max_requests=4096, device=dev)
+        srv = serve.NativeServer("uint32", True, arena=arena, max_batch=max_batch,
+                                 max_inflight=max_inflight, max_requests=4096, device=dev)
         submit, poll, release = srv.submit_ptrs, srv.poll, srv.release
         lat, late, outputs, sub = [], {}, 0, 0
         parts = []  # per request: lateness, submit->launch, launch->end seen, device, end seen->report
@@ -860,8 +860,8 @@ def serving_leg(pool_size=16, per_point=1000, fractions=(0.25, 0.5, 0.75, 0.9, 1
     native = {
         "workload": ("requests with sides log-uniform in [2^10,2^24], uint32 keys uniform, "
                      "uint32 payloads, device-resident"),
-        "runtime": "cm_server (native scheduler thread), 16 GiB output arena, max_batch 64, "
-                   "2 batches in flight",
+        "runtime": f"cm_server (native scheduler thread), 16 GiB output arena, max_batch {max_batch}, "
+                   f"{max_inflight} batches in flight",
         "boundary_pass": ["one_level", "two_level_64", "two_level_16", "two_level_16",
                           "in_block"][cm.tuning_get(cm.OP_BATCH, "uint32", True, 1 << 28)[2]],
         "pool": pool_size,

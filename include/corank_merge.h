@@ -209,16 +209,19 @@ int cm_stable_merge_pairs64(int key_type,
  *   for the block size the batch call will use, and the total block count.
  * cm_batch_workspace_size(total_blocks, count): workspace bytes (one uint64
  *   co-rank per block end of every merge, one per 16th of those for the
- *   two-level pass, one uint32 per block naming its merge, and room for
- *   CM_BATCH_INLINE_MAX descriptors), each part rounded up to 256.
+ *   two-level pass, one uint32 per block and one per block end naming its
+ *   merge, and a copy of the count descriptors), each part rounded up to
+ *   256.
  * cm_stable_merge_batch(key_type, with_payload, descs_host, descs_dev,
  *   count, total_blocks, workspace, workspace_bytes, stream):
  *   descs_host is the prepared host array (used to check the arguments);
- *   descs_dev is a byte-identical copy of it in device memory, read by the
- *   kernels (the caller uploads it and keeps it alive until the stream has
- *   run the call).  With count <= CM_BATCH_INLINE_MAX, descs_dev may be
- *   NULL: the descriptors then travel in the kernel arguments (copied at
- *   the call; nothing to upload first).  No output may overlap an input or
+ *   descs_dev is a byte-identical copy of it that the device reads: device
+ *   memory, or host memory mapped for the device (hipHostMalloc; its
+ *   device address), so that no upload is needed; the call's first kernel
+ *   copies it into the workspace, and it must stay alive and unchanged
+ *   until the stream has run the call.  With count <= CM_BATCH_INLINE_MAX,
+ *   descs_dev may be NULL: the descriptors then travel in the kernel
+ *   arguments (copied at the call).  No output may overlap an input or
  *   another output of the batch.  count = 0 is a no-op.  Block ends are
  *   co-ranked as the boundary mode says (cm_set_partition, or the tuning
  *   table's entry for operation 2): 0 = one thread per block end over its
@@ -226,8 +229,8 @@ int cm_stable_merge_pairs64(int key_type,
  *   batch searched by 64 or 16 lanes over its merge, the others by
  *   bisection between the nearest of those in the same merge, or the
  *   merge's own ends); 4 = no pass, every block co-ranks its two ends
- *   itself (one wave each), for batches of at most CM_BATCH_INLINE_MAX
- *   merges (larger ones take 2); 3 is taken as 2.
+ *   itself (one wave each; a batch of at most CM_BATCH_INLINE_MAX merges
+ *   then runs as a single kernel launch); 3 is taken as 2.
  * Errors: CM_EDTYPE, CM_EINVAL (null pointer with nonzero length, counts
  *   or first_block that do not match cm_batch_prepare), CM_EALIAS,
  *   CM_ENOSPC, CM_EHIP.

@@ -319,14 +319,15 @@ uint64_t batch_slots(uint64_t total_blocks, uint32_t count) { return total_block
 size_t batch_coarse_offset(uint64_t total_blocks, uint32_t count) {
   return round256(batch_slots(total_blocks, count) * sizeof(uint64_t));
 }
-size_t batch_index_offset(uint64_t total_blocks, uint32_t count) {
+size_t batch_index_offset(uint64_t total_blocks, uint32_t count) {  // per block: its merge
   const uint64_t nb = batch_slots(total_blocks, count);
   return batch_coarse_offset(total_blocks, count) + round256((nb + kMinCoarse - 1) / kMinCoarse * sizeof(uint64_t));
 }
-// then room for a device copy of up to kBatchInline descriptors (a small
-// batch's descriptors come in the kernel arguments; the pass leaves a copy)
-size_t batch_descs_offset(uint64_t total_blocks, uint32_t count) {
+size_t batch_slot_index_offset(uint64_t total_blocks, uint32_t count) {  // per slot: its merge
   return batch_index_offset(total_blocks, count) + round256(total_blocks * sizeof(uint32_t));
+}
+size_t batch_descs_offset(uint64_t total_blocks, uint32_t count) {  // the descriptors' device copy
+  return batch_slot_index_offset(total_blocks, count) + round256(batch_slots(total_blocks, count) * sizeof(uint32_t));
 }
 
 // ---- stable merge sort
@@ -617,7 +618,7 @@ int cm_batch_prepare(int key_type, int with_payload, cm_merge_desc* descs, uint3
 }
 
 size_t cm_batch_workspace_size(uint64_t total_blocks, uint32_t count) {
-  return batch_descs_offset(total_blocks, count) + round256(kBatchInline * sizeof(cm_merge_desc));
+  return batch_descs_offset(total_blocks, count) + round256((uint64_t)count * sizeof(cm_merge_desc));
 }
 
 int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* descs_host,
@@ -666,21 +667,22 @@ int cm_stable_merge_batch(int key_type, int with_payload, const cm_merge_desc* d
   uint64_t* bj = (uint64_t*)workspace;
   uint64_t* coarse = (uint64_t*)((char*)workspace + batch_coarse_offset(total_blocks, count));
   uint32_t* bm = (uint32_t*)((char*)workspace + batch_index_offset(total_blocks, count));
+  uint32_t* sm = (uint32_t*)((char*)workspace + batch_slot_index_offset(total_blocks, count));
   void* wd = (char*)workspace + batch_descs_offset(total_blocks, count);
-  // no pass (every block co-ranks its own ends) only for batches whose
-  // descriptors fit in the kernel arguments; larger ones take two levels
-  const bool self = ch.partition == 4 && count <= kBatchInline;
-  if (ch.partition == 4 && !self) ch.partition = 2;
+  const uint64_t slots = batch_slots(total_blocks, count);
+  // no pass: a small batch in one launch with its descriptors in the kernel
+  // arguments; otherwise after the prep kernel.  With a pass: prep, pass, merge.
+  const int form = ch.partition != 4 ? kBatchPassFed : count <= kBatchInline ? kBatchArgs : kBatchSelf;
   timing_mark(0, stream);
-  if (!self) {
-    const int rc = launch_batch_co_ranks(key_type, ch, g_set.shape, descs_host, descs_dev, wd, count, T,
-                                         batch_slots(total_blocks, count), bj, coarse, bm, stream);
+  if (form != kBatchArgs) {
+    int rc = launch_batch_prep(descs_host, descs_dev, count, slots, total_blocks, wd, sm, bm, stream);
+    if (rc == CM_OK && form == kBatchPassFed)
+      rc = launch_batch_co_ranks(key_type, ch, g_set.shape, wd, sm, T, slots, bj, coarse, stream);
     if (rc != CM_OK) return rc;
   }
   timing_mark(1, stream);
-  const int rc = launch_batch_merge_blocks(key_type, val, ch, descs_host, descs_dev ? descs_dev : wd, count,
-                                           self ? nullptr : bj, bm, total_blocks, vec, g_set.shape.xcd_order,
-                                           stream);
+  const int rc = launch_batch_merge_blocks(key_type, val, ch, form, descs_host, wd, count, bm, bj, total_blocks, vec,
+                                           g_set.shape.xcd_order, stream);
   timing_mark(2, stream);
   return rc;
 }

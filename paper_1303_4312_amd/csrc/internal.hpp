@@ -156,19 +156,22 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
                             uint32_t S, uint64_t N, void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs,
                             uint64_t tiles, const uint32_t* flag, hipStream_t st);
 
-// Batch of separately allocated merges.  Boundary pass: d is the device
-// copy of the descriptors (layout of cm_merge_desc), or d is null and the
-// host array h (at most kBatchInline descriptors) travels in the kernel
-// arguments, the pass's first kernel leaving a device copy in wd (room for
-// kBatchInline).  nb = total blocks + count boundary slots.  ch.partition:
-// 0 one-level pass; 1, 2 two-level pass (coarse slots searched by 64 or 16
-// lanes; `coarse` holds ceil(nb / sh.coarse_stride) entries).  The pass
-// also writes bm (one uint32 per block: the merge it belongs to).  Block
-// merge after a pass: bj, bm and the descriptors in device memory (d: the
-// caller's copy or wd).  Block merge with no pass (bj null): descriptors
-// from h in the kernel arguments (count <= kBatchInline); every block
-// co-ranks its own ends.
+// Batch of separately allocated merges.
+// launch_batch_prep: copies the descriptors into the workspace (wd, count
+// entries) from d (device memory, or pinned host memory the device reads)
+// or, with d null, from the host array h (at most kBatchInline, passed in
+// the kernel arguments); and fills sm (per boundary slot) and bm (per
+// block) with the merge each belongs to.  slots = blocks + count.
+// launch_batch_co_ranks: the boundary pass over the prep's tables and
+// copy (d): ch.partition 0 one-level, 1 or 2 two-level (coarse slots
+// searched by 64 or 16 lanes; `coarse` holds ceil(nb / sh.coarse_stride)
+// entries).
+// launch_batch_merge_blocks, `form`: kBatchPassFed (bj from the pass),
+// kBatchSelf (after prep, every block co-ranks its own ends), kBatchArgs
+// (no prep: descriptors from h in the kernel arguments, count <=
+// kBatchInline, every block finds its merge and co-ranks its ends).
 constexpr uint32_t kBatchInline = 16;
+enum BatchForm : int { kBatchPassFed = 0, kBatchSelf = 1, kBatchArgs = 2 };
 
 // The allocation-free single merge keeps its block co-ranks in a scratch
 // array of this many bytes in the library's device code (one per GPU);
@@ -176,12 +179,13 @@ constexpr uint32_t kBatchInline = 16;
 // up once per device with hipGetSymbolAddress), or CM_EHIP.
 constexpr size_t kNoAllocScratchBytes = 4u << 20;
 int noalloc_scratch(void** out);
-int launch_batch_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* h, const void* d, void* wd,
-                          uint32_t count, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, uint32_t* bm,
-                          hipStream_t st);
-int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* h, const void* d, uint32_t count,
-                              const uint64_t* bj, const uint32_t* bm, uint64_t tiles, bool vec, int xcd,
-                              hipStream_t st);
+int launch_batch_prep(const void* h, const void* d, uint32_t count, uint64_t slots, uint64_t blocks, void* wd,
+                      uint32_t* sm, uint32_t* bm, hipStream_t st);
+int launch_batch_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* d, const uint32_t* sm,
+                          uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
+int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, int form, const void* h, const void* d,
+                              uint32_t count, const uint32_t* bm, const uint64_t* bj, uint64_t tiles, bool vec,
+                              int xcd, hipStream_t st);
 
 // Co-ranks of q arbitrary ranks.
 int launch_co_rank_many(int kt, int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m,

@@ -629,47 +629,25 @@ struct MergeDesc {
 };
 
 // Up to kInlineDescs descriptors of a batch travel in the kernel arguments,
-// so that a small batch needs no upload before its kernels run; a larger
-// batch is read from its device copy.
+// so that a small batch needs no upload before its kernels run.
 constexpr uint32_t kInlineDescs = 16;
 struct DescPack {
   MergeDesc d[kInlineDescs];
 };
 
-// Where a kernel reads a batch's descriptors.  The block merge reads one
-// source only, so its block's descriptor (the same in every lane) comes in
-// through scalar loads: from device memory (DevDescs) or from the kernel
-// arguments (PackDescs).  The boundary passes, whose lanes each look up
-// their own descriptor, take either (AnyDescs).
-struct DevDescs {
-  const MergeDesc* __restrict__ d;
-  __device__ MergeDesc at(uint32_t r) const { return d[r]; }
-  __device__ uint64_t first_block(uint32_t r) const { return d[r].first_block; }
-};
+// Boundary slots of a batch: merge r (nb_r blocks) owns the nb_r + 1 slots
+// [first_block[r] + r, first_block[r] + r + nb_r], one per block end; slot
+// s0 + t holds the A co-rank of rank min(t * tile, m + n) of merge r.
+// Block g of the batch is block g - first_block[r] of merge r.
 
-struct PackDescs {
-  const DescPack& p;
-  __device__ MergeDesc at(uint32_t r) const { return p.d[r < kInlineDescs ? r : 0]; }
-  __device__ uint64_t first_block(uint32_t r) const { return p.d[r < kInlineDescs ? r : 0].first_block; }
-};
-
-struct AnyDescs {
-  const MergeDesc* __restrict__ d;  // null: the pack
-  const DescPack& p;
-  __device__ MergeDesc at(uint32_t r) const { return d ? d[r] : p.d[r < kInlineDescs ? r : 0]; }
-  __device__ uint64_t first_block(uint32_t r) const {
-    return d ? d[r].first_block : p.d[r < kInlineDescs ? r : 0].first_block;
-  }
-};
-
-// Largest r in [0, count) with first_block[r] + r * extra <= x (merges with
-// no blocks share first_block with their successor and are skipped).
-template <typename Src>
-__device__ __forceinline__ uint32_t desc_of(const Src& src, uint32_t count, uint64_t x, uint64_t extra) {
+// Largest r in [0, count) with fb(r) + r * extra <= x (merges with no
+// blocks share first_block with their successor and are skipped).
+template <typename FB>
+__device__ __forceinline__ uint32_t merge_of(FB fb, uint32_t count, uint64_t x, uint64_t extra) {
   uint32_t lo = 0, hi = count - 1;
   while (lo < hi) {
     const uint32_t mid = lo + ((hi - lo + 1) >> 1);
-    if (src.first_block(mid) + mid * extra <= x)
+    if (fb(mid) + mid * extra <= x)
       lo = mid;
     else
       hi = mid - 1;
@@ -677,9 +655,6 @@ __device__ __forceinline__ uint32_t desc_of(const Src& src, uint32_t count, uint
   return lo;
 }
 
-// Boundary slots of a batch: merge r (nb_r blocks) owns the nb_r + 1 slots
-// [first_block[r] + r, first_block[r] + r + nb_r], one per block end; slot
-// s0 + t holds the A co-rank of rank min(t * tile, m + n) of merge r.
 struct BatchSlot {
   MergeDesc q;
   uint32_t r;   // the merge
@@ -687,43 +662,27 @@ struct BatchSlot {
   uint64_t i;   // rank of the slot inside the merge
 };
 
-template <typename Src>
-__device__ __forceinline__ BatchSlot batch_slot(const Src& src, uint32_t count, uint64_t tile, uint64_t b) {
+// Slot b: its merge from the prep kernel's table, the descriptor from the
+// workspace copy.
+__device__ __forceinline__ BatchSlot batch_slot(const MergeDesc* __restrict__ d, const uint32_t* __restrict__ sm,
+                                                uint64_t tile, uint64_t b) {
   BatchSlot x;
-  x.r = desc_of(src, count, b, 1);
-  x.q = src.at(x.r);
+  x.r = sm[b];
+  x.q = d[x.r];
   x.s0 = x.q.first_block + x.r;
   x.i = std::min((b - x.s0) * tile, x.q.m + x.q.n);
   return x;
 }
 
-// The boundary pass also records which merge every block belongs to
-// (bm[g] = r for block g of merge r, which starts at slot g + r), so that
-// the block merge reads that instead of searching the descriptors.  Every
-// slot but a merge's last starts a block.
-__device__ __forceinline__ void note_block(const BatchSlot& x, uint64_t b, uint32_t* __restrict__ bm) {
-  if (x.i < x.q.m + x.q.n) bm[b - x.r] = x.r;
-}
-
-// The first kernel of a pass-fed batch whose descriptors came in the kernel
-// arguments leaves a device copy of them (wd) for the kernels after it.
-__device__ __forceinline__ void stage_descs(const MergeDesc* d, const DescPack& pk, uint32_t count,
-                                            MergeDesc* __restrict__ wd) {
-  if (!d && blockIdx.x == 0 && threadIdx.x < count && threadIdx.x < kInlineDescs) wd[threadIdx.x] = pk.d[threadIdx.x];
-}
-
 // One-level boundary pass of a batch: one thread per slot, searching the
 // whole diagonal of its merge.
 template <typename K>
-__global__ __launch_bounds__(256) void k_batch_co_rank(DescPack pk, const MergeDesc* __restrict__ d,
-                                                       MergeDesc* __restrict__ wd, uint32_t count, uint64_t tile,
-                                                       uint64_t num_bounds, uint64_t* __restrict__ bj,
-                                                       uint32_t* __restrict__ bm, int search) {
-  stage_descs(d, pk, count, wd);
+__global__ __launch_bounds__(256) void k_batch_co_rank(const MergeDesc* __restrict__ d,
+                                                       const uint32_t* __restrict__ sm, uint64_t tile,
+                                                       uint64_t num_bounds, uint64_t* __restrict__ bj, int search) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= num_bounds) return;
-  const BatchSlot x = batch_slot(AnyDescs{d, pk}, count, tile, b);
-  note_block(x, b, bm);
+  const BatchSlot x = batch_slot(d, sm, tile, b);
   const K* A = (const K*)x.q.A;
   const K* B = (const K*)x.q.B;
   auto ra = [=](uint64_t y) { return A[y]; };
@@ -735,11 +694,10 @@ __global__ __launch_bounds__(256) void k_batch_co_rank(DescPack pk, const MergeD
 // whole batch (slot c * G), whatever merge it falls in, co-ranked over its
 // merge's diagonal by a group of L lanes (L-ary search).
 template <typename K, int L>
-__global__ __launch_bounds__(256) void k_batch_coarse_co_rank(DescPack pk, const MergeDesc* __restrict__ d,
-                                                              MergeDesc* __restrict__ wd, uint32_t count,
-                                                              uint64_t tile, uint32_t G, uint64_t num_coarse,
+__global__ __launch_bounds__(256) void k_batch_coarse_co_rank(const MergeDesc* __restrict__ d,
+                                                              const uint32_t* __restrict__ sm, uint64_t tile,
+                                                              uint32_t G, uint64_t num_coarse,
                                                               uint64_t* __restrict__ jc) {
-  stage_descs(d, pk, count, wd);
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if ((gid & ~63ull) / L >= num_coarse) return;  // whole waves with no coarse slot leave
   const uint64_t c = gid / L;
@@ -748,7 +706,7 @@ __global__ __launch_bounds__(256) void k_batch_coarse_co_rank(DescPack pk, const
   const K* A = nullptr;
   const K* B = nullptr;
   if (mine) {
-    const BatchSlot x = batch_slot(AnyDescs{d, pk}, count, tile, c * G);
+    const BatchSlot x = batch_slot(d, sm, tile, c * G);
     A = (const K*)x.q.A;
     B = (const K*)x.q.B;
     i = x.i;
@@ -765,21 +723,21 @@ __global__ __launch_bounds__(256) void k_batch_coarse_co_rank(DescPack pk, const
 // (c + 1) * G (c = b / G).  Each of them bounds b's co-rank when it belongs
 // to the same merge (co-ranks grow with the rank); otherwise the merge's own
 // start (rank 0, co-rank 0) or end (rank m + n, co-rank m) does.  Bisection
-// then runs only over that window.  d: the descriptors in device memory.
+// then runs only over that window.
 template <typename K>
-__global__ __launch_bounds__(256) void k_batch_fine_co_rank(const MergeDesc* __restrict__ d, uint32_t count,
-                                                            uint64_t tile, uint64_t num_bounds, uint32_t G,
+__global__ __launch_bounds__(256) void k_batch_fine_co_rank(const MergeDesc* __restrict__ d,
+                                                            const uint32_t* __restrict__ sm, uint64_t tile,
+                                                            uint64_t num_bounds, uint32_t G,
                                                             const uint64_t* __restrict__ jc,
-                                                            uint64_t* __restrict__ bj, uint32_t* __restrict__ bm) {
+                                                            uint64_t* __restrict__ bj) {
   const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= num_bounds) return;
-  const BatchSlot x = batch_slot(DevDescs{d}, count, tile, b);
-  note_block(x, b, bm);
   const uint64_t c = b / G;
   if (b == c * G) {
     bj[b] = jc[c];
     return;
   }
+  const BatchSlot x = batch_slot(d, sm, tile, b);
   const uint64_t m = x.q.m, n = x.q.n, N = m + n, i = x.i;
   const uint64_t nb = (N + tile - 1) / tile;  // the merge's slots are s0 .. s0 + nb
   uint64_t i0 = 0, j0 = 0, i1 = N, j1 = m;
@@ -804,72 +762,82 @@ __global__ __launch_bounds__(256) void k_batch_fine_co_rank(const MergeDesc* __r
   bj[b] = co_rank_bisect_in<K>(i, ra, rb, lo, hi);
 }
 
-// Block b of a batch's grid: block g = grid_block(b) of the batch is block
-// g - first_block[r] of merge r (descriptor q).  With its end co-ranks
-// j0, j1 it merges like the single merge's block.
-template <typename K, bool VAL, int NT, int E, bool VEC>
-__device__ __forceinline__ void batch_block(const MergeDesc& q, uint64_t t, uint64_t j0, uint64_t j1, int len,
-                                            int search, K* s_key, uint32_t* s_val) {
-  constexpr int T = NT * E;
-  merge_block<K, VAL, NT, E, VEC>((const K*)q.A, q.A_val, q.m, (const K*)q.B, q.B_val, q.n, (K*)q.C, q.C_val,
-                                  t * (uint64_t)T, len, j0, j1, search, s_key, s_val);
+// Waves 0 and 1 of the workgroup co-rank the start i0 and the end i0 + len
+// of a block of merge q over its whole diagonal (64-ary wave search) into
+// s_j[0], s_j[1]; the workgroup then waits for both.
+template <typename K>
+__device__ __forceinline__ void block_ends(const MergeDesc& q, uint64_t i0, int len, uint64_t* s_j) {
+  const int wave = (int)(threadIdx.x >> 6);
+  if (wave < 2) {  // wave-uniform
+    const uint64_t i = i0 + (wave ? (uint64_t)len : 0);
+    const K* A = (const K*)q.A;
+    const K* B = (const K*)q.B;
+    auto ra = [=](uint64_t y) { return A[y]; };
+    auto rb = [=](uint64_t y) { return B[y]; };
+    const uint64_t j = co_rank_wave64<K>(i, ra, rb, i > q.n ? i - q.n : 0, std::min(i, q.m));
+    if ((threadIdx.x & 63) == 0) s_j[wave] = j;
+  }
+  __syncthreads();
 }
 
-// Block merge of a batch fed by a boundary pass: the pass noted each
-// block's merge (bm) and co-ranked every block end (bj); d: the
-// descriptors in device memory.
-template <typename K, bool VAL, int NT, int E, bool VEC>
+// Block merge of a batch after the prep kernel: block g's merge comes from
+// bm, its descriptor from d (device memory).  Its end co-ranks come from
+// the boundary pass (bj), or, with SELF (no pass: Algorithm 2 as the paper
+// states it), the block finds them itself (block_ends).
+template <typename K, bool VAL, int NT, int E, bool VEC, bool SELF>
 __global__ __launch_bounds__(NT) void k_batch_merge_blocks(const MergeDesc* __restrict__ d,
-                                                           const uint64_t* __restrict__ bj,
-                                                           const uint32_t* __restrict__ bm, uint64_t num_tiles,
+                                                           const uint32_t* __restrict__ bm,
+                                                           const uint64_t* __restrict__ bj, uint64_t num_tiles,
                                                            int search, int xcd) {
+  static_assert(NT >= 128, "two waves search the block ends");
   constexpr int T = NT * E;
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
   __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
+  __shared__ uint64_t s_j[2];
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
     const uint64_t g = grid_block(b, num_tiles, xcd);
     const uint32_t r = bm[g];
     const MergeDesc q = d[r];
     const uint64_t t = g - q.first_block;
-    const int len = (int)std::min((uint64_t)T, q.m + q.n - t * (uint64_t)T);
-    const uint64_t slot = g + r;
-    batch_block<K, VAL, NT, E, VEC>(q, t, bj[slot], bj[slot + 1], len, search, s_key, s_val);
+    const uint64_t i0 = t * (uint64_t)T;
+    const int len = (int)std::min((uint64_t)T, q.m + q.n - i0);
+    uint64_t j0, j1;
+    if constexpr (SELF) {
+      block_ends<K>(q, i0, len, s_j);
+      j0 = s_j[0];
+      j1 = s_j[1];
+    } else {
+      j0 = bj[g + r];  // block g starts at slot g + r
+      j1 = bj[g + r + 1];
+    }
+    merge_block<K, VAL, NT, E, VEC>((const K*)q.A, q.A_val, q.m, (const K*)q.B, q.B_val, q.n, (K*)q.C, q.C_val, i0,
+                                    len, j0, j1, search, s_key, s_val);
     if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }
 
-// Block merge of a small batch with no boundary pass (Algorithm 2 as the
-// paper states it): the descriptors come in the kernel arguments; the block
-// finds its merge by searching them, and waves 0 and 1 co-rank its start
-// and end over the merge's diagonal (64-ary wave search).
+// The single-launch form for a small batch: the descriptors come in the
+// kernel arguments, the block finds its merge by searching them and
+// co-ranks its own ends (no prep, no pass).
 template <typename K, bool VAL, int NT, int E, bool VEC>
-__global__ __launch_bounds__(NT) void k_batch_merge_blocks_self(DescPack pk, uint32_t count, uint64_t num_tiles,
+__global__ __launch_bounds__(NT) void k_batch_merge_blocks_args(DescPack pk, uint32_t count, uint64_t num_tiles,
                                                                 int search, int xcd) {
   static_assert(NT >= 128, "two waves search the block ends");
   constexpr int T = NT * E;
   __shared__ __attribute__((aligned(16))) K s_key[T + 16];
   __shared__ __attribute__((aligned(16))) uint32_t s_val[VAL ? T + 16 : 1];
   __shared__ uint64_t s_j[2];
-  const int wave = (int)(threadIdx.x >> 6);
-  const PackDescs src{pk};
+  auto fb = [&](uint32_t r) { return pk.d[r < kInlineDescs ? r : 0].first_block; };
   for (uint64_t b = blockIdx.x; b < num_tiles; b += gridDim.x) {
     const uint64_t g = grid_block(b, num_tiles, xcd);
-    const uint32_t r = desc_of(src, count, g, 0);
-    const MergeDesc q = src.at(r);
+    const uint32_t r = merge_of(fb, count, g, 0);
+    const MergeDesc q = pk.d[r < kInlineDescs ? r : 0];
     const uint64_t t = g - q.first_block;
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, q.m + q.n - i0);
-    if (wave < 2) {  // wave-uniform
-      const uint64_t i = i0 + (wave ? (uint64_t)len : 0);
-      const K* A = (const K*)q.A;
-      const K* B = (const K*)q.B;
-      auto ra = [=](uint64_t y) { return A[y]; };
-      auto rb = [=](uint64_t y) { return B[y]; };
-      const uint64_t j = co_rank_wave64<K>(i, ra, rb, i > q.n ? i - q.n : 0, std::min(i, q.m));
-      if ((threadIdx.x & 63) == 0) s_j[wave] = j;
-    }
-    __syncthreads();
-    batch_block<K, VAL, NT, E, VEC>(q, t, s_j[0], s_j[1], len, search, s_key, s_val);
+    block_ends<K>(q, i0, len, s_j);
+    merge_block<K, VAL, NT, E, VEC>((const K*)q.A, q.A_val, q.m, (const K*)q.B, q.B_val, q.n, (K*)q.C, q.C_val, i0,
+                                    len, s_j[0], s_j[1], search, s_key, s_val);
     if (b + gridDim.x < num_tiles) __syncthreads();
   }
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <stddef.h>
+#include <string.h>
 
 #include <map>
 #include <mutex>
@@ -78,6 +79,54 @@ __global__ __launch_bounds__(256) void k_seg_validate(const uint64_t* __restrict
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v) { *p = v; }
+
+// Merges whose first_block values a prep workgroup holds in LDS.
+constexpr uint32_t kPrepTable = 2048;
+
+// First kernel of every batch call but the single-launch form: copies the
+// descriptors into the workspace (wd) from the kernel arguments (src null)
+// or from src, which may be device memory or host memory the device reads
+// (pinned), so that the later kernels read device memory only; and notes
+// for every boundary slot and every block the merge it belongs to (sm, bm),
+// so that no later kernel searches the descriptors.  The search runs over
+// an LDS copy of first_block when the batch has at most kPrepTable merges.
+__global__ __launch_bounds__(256) void k_batch_prep(DescPack pk, const MergeDesc* __restrict__ src, uint32_t count,
+                                                    uint64_t num_slots, uint64_t num_blocks,
+                                                    MergeDesc* __restrict__ wd, uint32_t* __restrict__ sm,
+                                                    uint32_t* __restrict__ bm) {
+  __shared__ uint64_t s_fb[kPrepTable];
+  const bool table = count <= kPrepTable;  // grid-uniform
+  auto fb_src = [&](uint32_t r) -> uint64_t {
+    return src ? src[r].first_block : pk.d[r < kInlineDescs ? r : 0].first_block;
+  };
+  if (table)
+    for (uint32_t x = threadIdx.x; x < count; x += blockDim.x) s_fb[x] = fb_src(x);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  for (uint64_t x = gid; x < count; x += stride) wd[x] = src ? src[x] : pk.d[x < kInlineDescs ? x : 0];
+  __syncthreads();
+  for (uint64_t b = gid; b < num_slots; b += stride) {
+    if (table) {
+      auto fb = [&](uint32_t r) { return s_fb[r]; };
+      sm[b] = merge_of(fb, count, b, 1);
+      if (b < num_blocks) bm[b] = merge_of(fb, count, b, 0);
+    } else {
+      sm[b] = merge_of(fb_src, count, b, 1);
+      if (b < num_blocks) bm[b] = merge_of(fb_src, count, b, 0);
+    }
+  }
+}
+
+int launch_batch_prep(const void* h, const void* d, uint32_t count, uint64_t slots, uint64_t blocks, void* wd,
+                      uint32_t* sm, uint32_t* bm, hipStream_t st) {
+  DescPack pk;
+  memset(&pk, 0, sizeof pk);
+  if (!d && h) memcpy(pk.d, h, (size_t)std::min(count, kInlineDescs) * sizeof(MergeDesc));
+  const uint64_t grid = std::max<uint64_t>(1, std::min<uint64_t>((slots + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_batch_prep, dim3((unsigned)grid), dim3(256), 0, st, pk, (const MergeDesc*)d, count, slots,
+                     blocks, (MergeDesc*)wd, sm, bm);
+  return launch_status();
+}
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -339,19 +388,18 @@ int launch_seg_merge_blocks(int kt, bool val, const Choice& ch, const void* A, c
 static_assert(sizeof(MergeDesc) == sizeof(cm_merge_desc), "descriptor layouts differ");
 static_assert(offsetof(MergeDesc, first_block) == offsetof(cm_merge_desc, first_block), "descriptor layouts differ");
 
-int launch_batch_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* h, const void* d, void* wd,
-                          uint32_t count, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, uint32_t* bm,
-                          hipStream_t st) {
+int launch_batch_co_ranks(int kt, const Choice& ch, const Shape& sh, const void* d, const uint32_t* sm,
+                          uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
-    return Launch<decltype(key)>::batch_co_ranks(ch, sh, h, d, wd, count, tile, nb, bj, coarse, bm, st);
+    return Launch<decltype(key)>::batch_co_ranks(ch, sh, d, sm, tile, nb, bj, coarse, st);
   });
 }
 
-int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, const void* h, const void* d, uint32_t count,
-                              const uint64_t* bj, const uint32_t* bm, uint64_t tiles, bool vec, int xcd,
-                              hipStream_t st) {
+int launch_batch_merge_blocks(int kt, bool val, const Choice& ch, int form, const void* h, const void* d,
+                              uint32_t count, const uint32_t* bm, const uint64_t* bj, uint64_t tiles, bool vec,
+                              int xcd, hipStream_t st) {
   return by_key(kt, [&](auto key) -> int {
-    return Launch<decltype(key)>::batch_merge_blocks(val, ch, h, d, count, bj, bm, tiles, vec, xcd, st);
+    return Launch<decltype(key)>::batch_merge_blocks(val, ch, form, h, d, count, bm, bj, tiles, vec, xcd, st);
   });
 }
 

@@ -33,11 +33,10 @@ struct Launch {
                               const void* B, const uint32_t* Bv, const uint64_t* b_off, uint32_t S, uint64_t N,
                               void* C, uint32_t* Cv, const uint64_t* bj, const uint32_t* bs, uint64_t tiles,
                               const uint32_t* flag, hipStream_t st);
-  static int batch_co_ranks(const Choice& ch, const Shape& sh, const void* h, const void* d, void* wd,
-                            uint32_t count, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse,
-                            uint32_t* bm, hipStream_t st);
-  static int batch_merge_blocks(bool val, const Choice& ch, const void* h, const void* d, uint32_t count,
-                                const uint64_t* bj, const uint32_t* bm, uint64_t tiles, bool vec, int xcd,
+  static int batch_co_ranks(const Choice& ch, const Shape& sh, const void* d, const uint32_t* sm, uint64_t tile,
+                            uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st);
+  static int batch_merge_blocks(bool val, const Choice& ch, int form, const void* h, const void* d, uint32_t count,
+                                const uint32_t* bm, const uint64_t* bj, uint64_t tiles, bool vec, int xcd,
                                 hipStream_t st);
   static int co_rank_many(int search, const uint64_t* ranks, uint64_t q, const void* A, uint64_t m, const void* B,
                           uint64_t n, uint64_t* j_out, hipStream_t st);

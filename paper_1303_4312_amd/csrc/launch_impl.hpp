@@ -172,61 +172,54 @@ int Launch<K>::seg_merge_blocks(bool val, const Choice& ch, const void* A, const
   });
 }
 
-// The kernel-argument pack of a batch: the host descriptors (h) when the
-// kernels are to read them from there (d null), else unused.
-inline DescPack batch_pack(const void* h, const void* d, uint32_t count) {
-  static_assert(kInlineDescs == kBatchInline, "inline descriptor counts differ");
-  DescPack pk;
-  memset(&pk, 0, sizeof pk);
-  if (!d && h) memcpy(pk.d, h, (size_t)std::min(count, kInlineDescs) * sizeof(MergeDesc));
-  return pk;
-}
-
 template <typename K>
-int Launch<K>::batch_co_ranks(const Choice& ch, const Shape& sh, const void* h, const void* d, void* wd,
-                              uint32_t count, uint64_t tile, uint64_t nb, uint64_t* bj, uint64_t* coarse,
-                              uint32_t* bm, hipStream_t st) {
-  const DescPack pk = batch_pack(h, d, count);
+int Launch<K>::batch_co_ranks(const Choice& ch, const Shape& sh, const void* d, const uint32_t* sm, uint64_t tile,
+                              uint64_t nb, uint64_t* bj, uint64_t* coarse, hipStream_t st) {
   const MergeDesc* q = (const MergeDesc*)d;
-  MergeDesc* w = (MergeDesc*)wd;
   if (ch.partition == 0) {
-    hipLaunchKernelGGL((k_batch_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, pk, q, w, count,
-                       tile, nb, bj, bm, ch.search);
+    hipLaunchKernelGGL((k_batch_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, q, sm, tile, nb,
+                       bj, ch.search);
     return launch_status();
   }
   const uint32_t G = sh.coarse_stride;
   const uint64_t nc = (nb + G - 1) / G;  // coarse slots 0, G, 2G, ... below nb
   if (ch.partition == 1)
-    hipLaunchKernelGGL((k_batch_coarse_co_rank<K, 64>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st, pk, q, w,
-                       count, tile, G, nc, coarse);
+    hipLaunchKernelGGL((k_batch_coarse_co_rank<K, 64>), dim3((unsigned)((nc + 3) / 4)), dim3(256), 0, st, q, sm,
+                       tile, G, nc, coarse);
   else
-    hipLaunchKernelGGL((k_batch_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st, pk, q,
-                       w, count, tile, G, nc, coarse);
+    hipLaunchKernelGGL((k_batch_coarse_co_rank<K, 16>), dim3((unsigned)((nc + 15) / 16)), dim3(256), 0, st, q, sm,
+                       tile, G, nc, coarse);
   if (launch_status() != CM_OK) return CM_EHIP;
-  // from here the descriptors are in device memory: the caller's copy or the staged one
-  hipLaunchKernelGGL((k_batch_fine_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st,
-                     (const MergeDesc*)(q ? q : w), count, tile, nb, G, (const uint64_t*)coarse, bj, bm);
+  hipLaunchKernelGGL((k_batch_fine_co_rank<K>), dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, q, sm, tile,
+                     nb, G, (const uint64_t*)coarse, bj);
   return launch_status();
 }
 
 template <typename K>
-int Launch<K>::batch_merge_blocks(bool val, const Choice& ch, const void* h, const void* d, uint32_t count,
-                                  const uint64_t* bj, const uint32_t* bm, uint64_t tiles, bool vec, int xcd,
+int Launch<K>::batch_merge_blocks(bool val, const Choice& ch, int form, const void* h, const void* d, uint32_t count,
+                                  const uint32_t* bm, const uint64_t* bj, uint64_t tiles, bool vec, int xcd,
                                   hipStream_t st) {
-  // pass-fed (bj): descriptors in device memory (d); no pass: from h, in the kernel arguments
-  const DescPack pk = batch_pack(h, bj ? d : nullptr, count);
+  static_assert(kInlineDescs == kBatchInline, "inline descriptor counts differ");
+  DescPack pk;
+  memset(&pk, 0, sizeof pk);
+  if (form == kBatchArgs) memcpy(pk.d, h, (size_t)std::min(count, kInlineDescs) * sizeof(MergeDesc));
   return by_cfg(ch.cfg, [&](auto nt, auto e) -> int {
     constexpr int NT = decltype(nt)::value, E = decltype(e)::value;
     const dim3 b(NT);
     const MergeDesc* q = (const MergeDesc*)d;
     auto go = [&](auto val_c, auto vec_c) {
       constexpr bool V = decltype(val_c)::value, W = decltype(vec_c)::value;
-      if (bj) {
-        const dim3 g(launch_grid((const void*)k_batch_merge_blocks<K, V, NT, E, W>, NT, tiles, ch.grid));
-        hipLaunchKernelGGL((k_batch_merge_blocks<K, V, NT, E, W>), g, b, 0, st, q, bj, bm, tiles, ch.search, xcd);
+      if (form == kBatchArgs) {
+        const dim3 g(launch_grid((const void*)k_batch_merge_blocks_args<K, V, NT, E, W>, NT, tiles, ch.grid));
+        hipLaunchKernelGGL((k_batch_merge_blocks_args<K, V, NT, E, W>), g, b, 0, st, pk, count, tiles, ch.search,
+                           xcd);
+      } else if (form == kBatchSelf) {
+        const dim3 g(launch_grid((const void*)k_batch_merge_blocks<K, V, NT, E, W, true>, NT, tiles, ch.grid));
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, V, NT, E, W, true>), g, b, 0, st, q, bm, bj, tiles, ch.search,
+                           xcd);
       } else {
-        const dim3 g(launch_grid((const void*)k_batch_merge_blocks_self<K, V, NT, E, W>, NT, tiles, ch.grid));
-        hipLaunchKernelGGL((k_batch_merge_blocks_self<K, V, NT, E, W>), g, b, 0, st, pk, count, tiles, ch.search,
+        const dim3 g(launch_grid((const void*)k_batch_merge_blocks<K, V, NT, E, W, false>, NT, tiles, ch.grid));
+        hipLaunchKernelGGL((k_batch_merge_blocks<K, V, NT, E, W, false>), g, b, 0, st, q, bm, bj, tiles, ch.search,
                            xcd);
       }
     };

@@ -57,8 +57,8 @@ struct Request {
 struct Slot {  // one batch in flight
   hipStream_t stream = nullptr;
   hipEvent_t start = nullptr, end = nullptr;
-  cm_merge_desc* host = nullptr;  // pinned
-  cm_merge_desc* dev = nullptr;
+  cm_merge_desc* host = nullptr;      // pinned, mapped for the device
+  cm_merge_desc* host_dev = nullptr;  // its device address (the batch kernels read it there)
   void* ws = nullptr;
   size_t ws_bytes = 0;
   std::vector<uint32_t> reqs;
@@ -107,7 +107,6 @@ void destroy_resources(cm_server* s) {
     if (b.start) (void)hipEventDestroy(b.start);
     if (b.end) (void)hipEventDestroy(b.end);
     if (b.host) (void)hipHostFree(b.host);
-    if (b.dev) (void)hipFree(b.dev);
     if (b.ws) (void)hipFree(b.ws);
   }
   if (s->copy_in) (void)hipStreamDestroy(s->copy_in);
@@ -216,13 +215,12 @@ uint32_t launch(cm_server* s, Slot& b) {
     else
       rc = CM_EHIP;
   }
-  // a small batch's descriptors travel in the kernel arguments: no upload
+  // no upload: a small batch's descriptors travel in the kernel arguments,
+  // a larger one's are read from the pinned host array by the batch's first
+  // kernel (a copy engine's transfer of a few kilobytes took ~22 us)
   const bool inline_descs = n <= CM_BATCH_INLINE_MAX;
-  if (rc == CM_OK && !inline_descs &&
-      hipMemcpyAsync(b.dev, b.host, (size_t)n * sizeof(cm_merge_desc), hipMemcpyHostToDevice, b.stream) != hipSuccess)
-    rc = CM_EHIP;
   if (rc == CM_OK)
-    rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, inline_descs ? nullptr : b.dev, n, total, b.ws,
+    rc = cm_stable_merge_batch(s->kt, s->val ? 1 : 0, b.host, inline_descs ? nullptr : b.host_dev, n, total, b.ws,
                                b.ws_bytes, b.stream);
   // the end event is recorded whatever happened, so completion is detected the same way
   if (hipEventRecord(b.end, b.stream) != hipSuccess && rc == CM_OK) rc = CM_EHIP;
@@ -496,8 +494,8 @@ int cm_server_create(int key_type, int with_payload, void* arena, uint64_t arena
     b.ws_bytes = cm_batch_workspace_size(max_blocks, max_batch);
     if (hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&b.start) != hipSuccess || hipEventCreate(&b.end) != hipSuccess ||
-        hipHostMalloc((void**)&b.host, (size_t)max_batch * sizeof(cm_merge_desc), hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&b.dev, (size_t)max_batch * sizeof(cm_merge_desc)) != hipSuccess ||
+        hipHostMalloc((void**)&b.host, (size_t)max_batch * sizeof(cm_merge_desc), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&b.host_dev, b.host, 0) != hipSuccess ||
         hipMalloc(&b.ws, b.ws_bytes) != hipSuccess)
       rc = CM_EHIP;
   }

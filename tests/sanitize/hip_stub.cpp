@@ -108,6 +108,11 @@ hipError_t hipFree(void* p) {
 }
 
 hipError_t hipHostMalloc(void** p, size_t bytes, unsigned int) { return hipMalloc(p, bytes); }
+hipError_t hipHostGetDevicePointer(void** d, void* h, unsigned int) {
+  if (!d || !h) return hipErrorInvalidValue;
+  *d = h;
+  return hipSuccess;
+}
 hipError_t hipHostFree(void* p) { return hipFree(p); }
 
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind, hipStream_t) {

@@ -68,12 +68,16 @@ int launch_seg_merge_blocks(int, bool, const Choice&, const void*, const uint32_
                             const uint32_t*, uint64_t, const uint32_t*, hipStream_t) {
   return CM_OK;
 }
-int launch_batch_co_ranks(int, const Choice&, const Shape&, const void*, const void*, void*, uint32_t, uint64_t,
-                          uint64_t, uint64_t*, uint64_t*, uint32_t*, hipStream_t) {
+int launch_batch_prep(const void*, const void*, uint32_t, uint64_t, uint64_t, void*, uint32_t*, uint32_t*,
+                      hipStream_t) {
   return CM_OK;
 }
-int launch_batch_merge_blocks(int, bool, const Choice&, const void*, const void*, uint32_t, const uint64_t*,
-                              const uint32_t*, uint64_t, bool, int, hipStream_t) {
+int launch_batch_co_ranks(int, const Choice&, const Shape&, const void*, const uint32_t*, uint64_t, uint64_t,
+                          uint64_t*, uint64_t*, hipStream_t) {
+  return CM_OK;
+}
+int launch_batch_merge_blocks(int, bool, const Choice&, int, const void*, const void*, uint32_t, const uint32_t*,
+                              const uint64_t*, uint64_t, bool, int, hipStream_t) {
   return CM_OK;
 }
 int launch_co_rank_many(int, int, const uint64_t*, uint64_t, const void*, uint64_t, const void*, uint64_t, uint64_t*,

@@ -292,3 +292,44 @@ def test_native_server_close_with_host_requests_in_flight():
     for d, (C, Cv) in zip(reqs, outs):
         Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
         assert same_bits(C.numpy(), Ce) and same_bits(Cv.numpy(), Cve)
+
+
+@pytest.mark.parametrize("partition", [-1, 2, 4])
+def test_native_server_large_batches(partition, restore_settings):
+    """Batches of more than CM_BATCH_INLINE_MAX merges: their descriptors are
+    read from the server's pinned host array by the batch's first kernel (no
+    upload), in the automatic boundary mode, with the two-level pass, and
+    with none (every block co-ranks its ends after the prep kernel).  Every
+    request equals the merge run alone and the oracle."""
+    import torch
+    print(f"[server large batches] partition={partition}", flush=True)
+    cm.set_partition(partition)
+    reqs = make_requests(150, seed=31, lo=1, hi=1 << 14)
+    dev = [(to_dev(d["A"]), to_dev(d["B"]), to_dev(d["Av"]), to_dev(d["Bv"])) for d in reqs]
+    alone = []
+    for A, B, Av, Bv in dev:
+        C, Cv = cm.stable_merge_pairs(A, Av, B, Bv)
+        alone.append((to_host(C), to_host(Cv)))
+    srv = serve.NativeServer("uint32", True, arena_bytes=1 << 28, max_batch=64, max_inflight=2,
+                             max_requests=256)
+    x = torch.randn(4096, 4096, device="cuda:0")
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    tickets, sizes, results = [], {}, {}
+    with torch.cuda.stream(side):
+        for _ in range(8):  # milliseconds of work ahead of every request's inputs
+            x = x @ x / 4096
+        for A, B, Av, Bv in dev:  # all become ready at once: batches fill up to max_batch
+            t = srv.submit(A, B, Av, Bv)
+            tickets.append(t)
+            sizes[t] = A.numel() + B.numel()
+    drain(srv, len(tickets), sizes, results)
+    st = srv.stats()
+    srv.close()
+    for k, t in enumerate(tickets):
+        C, Cv = results[t]
+        assert same_bits(C, alone[k][0]) and same_bits(Cv, alone[k][1]), f"request {k} differs"
+    for d, (C, Cv) in list(zip(reqs, [results[t] for t in tickets]))[:10]:
+        Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
+        assert same_bits(C, Ce) and same_bits(Cv, Cve)
+    assert st["completed"] == len(reqs) and st["max_batch_seen"] > 16
