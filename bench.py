@@ -41,6 +41,11 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_1303_4312_amd", "csrc", f)
 COUNTERS_FILES = {
     "zipf": os.path.join(ROOT, "profiles", "k_merge_blocks_zipf_u32_pairs_counters.md"),
     "segmented": os.path.join(ROOT, "profiles", "k_seg_merge_blocks_segmented_u32_pairs_counters.md"),
+    "u64": os.path.join(ROOT, "profiles", "k_merge_blocks_u64_pairs_counters.md"),
+    "f32": os.path.join(ROOT, "profiles", "k_merge_blocks_f32_pairs_counters.md"),
+    "a_below_b": os.path.join(ROOT, "profiles", "k_merge_blocks_a_below_b_u32_pairs_counters.md"),
+    "interleaved": os.path.join(ROOT, "profiles", "k_merge_blocks_interleaved_u32_pairs_counters.md"),
+    "all_equal": os.path.join(ROOT, "profiles", "k_merge_blocks_all_equal_u32_pairs_counters.md"),
 }
 
 
