@@ -429,7 +429,8 @@ int cm_autotune_segmented(int key_type,
  * Tuning table.  Entries map (op, key_type, with_payload, size class) to
  * {config, search, partition}; op 0 = single merge, 1 = segmented batch,
  * 2 = batch of separate merges (size class of its total output count),
- * 3 = stable sort (size class of n; the partition field is unused).  A
+ * 3 = stable sort (size class of n; partition 0 = one-level boundary pass,
+ * any other value = two-level for pairs longer than the coarse stride).  A
  * segmented batch takes partition 0 as the one-level pass and any other
  * value as the two-level pass; a batch of separate merges takes the modes
  * of cm_stable_merge_batch;
@@ -638,13 +639,19 @@ int cm_merge_partition_ablation(int key_type, const void *A, const uint32_t *A_v
  * keys_out (vals_out) in nondecreasing key order; equal keys keep their
  * input order (stable).  Float keys compare as IEEE values (-0.0 == +0.0,
  * NaN not allowed).
- *   Runs of one block's size are first sorted inside LDS (per-thread sorting
- *   networks, then co-rank merges in LDS); then ceil(log2(n / block)) passes
- *   merge runs pairwise, each pass one boundary kernel and one block merge
- *   over all pairs (Algorithm 2 per pair).  Passes alternate between the
- *   output and the workspace.
+ *   Runs of 4, 2 or 1 blocks (as many as fit two workgroups' LDS per CU:
+ *   4 for 4-byte keys with payloads in the default 256 x 9 tile, runs of
+ *   9,216) are first sorted inside LDS (per-thread sorting networks, then
+ *   co-rank merges in LDS); then ceil(log2(n / run)) passes merge runs
+ *   pairwise, each pass a boundary pass and one block merge over all pairs
+ *   (Algorithm 2 per pair).  The boundary pass co-ranks every block start in
+ *   its pair: one thread each (partition 0), or, for pairs longer than the
+ *   coarse stride, every coarse_stride-th start first by 16-lane groups and
+ *   the others inside those brackets (cm_set_fine_lanes lanes each).  Passes
+ *   alternate between the output and the workspace.
  * cm_sort_workspace_size(key_type, with_payload, n): bytes (a second key and
- *   payload buffer of n entries plus one uint64 per block), 0 for n == 0.
+ *   payload buffer of n entries, one uint64 per block and one per 16
+ *   blocks), 0 for n == 0.
  * cm_stable_sort(key_type, keys, n, keys_out, workspace, bytes, stream)
  * cm_stable_sort_pairs(key_type, keys, vals, n, keys_out, vals_out,
  *   workspace, bytes, stream)

@@ -332,12 +332,14 @@ size_t batch_descs_offset(uint64_t total_blocks, uint32_t count) {  // the descr
 
 // ---- stable merge sort
 
-// Workspace of a sort: a second key (and payload) buffer for the passes and
-// one block co-rank per block (sized for the smallest block).
+// Workspace of a sort: a second key (and payload) buffer for the passes,
+// one block co-rank per block and one coarse co-rank per coarse_stride-th
+// block (both sized for the smallest block and stride).
 size_t sort_ws_bytes(int kt, bool val, uint64_t N) {
   if (N == 0) return 0;
-  return round256(N * key_bytes(kt)) + (val ? round256(N * 4) : 0) +
-         round256(((N + kMinTile - 1) / kMinTile + 1) * sizeof(uint64_t));
+  const uint64_t nb = (N + kMinTile - 1) / kMinTile;
+  return round256(N * key_bytes(kt)) + (val ? round256(N * 4) : 0) + round256((nb + 1) * sizeof(uint64_t)) +
+         round256(num_coarse(nb, kMinCoarse) * sizeof(uint64_t));
 }
 
 int sort_impl(int kt, bool val, const void* X, const uint32_t* Xv, uint64_t N, void* Y, uint32_t* Yv, void* ws,
@@ -359,17 +361,24 @@ int sort_impl(int kt, bool val, const void* X, const uint32_t* Xv, uint64_t N, v
   const uint64_t T = tile_size(ch.cfg);
   const uint64_t tiles = (N + T - 1) / T;
   if (tiles >= (1ull << 31)) return CM_EINVAL;
+  // the first sorted runs are M blocks long (M a power of two), so the
+  // first pass merges pairs of 2M blocks: shift log2(M) + 1
+  const uint32_t M = sort_run_blocks(kt, val, ch.cfg);
+  int sh0 = 1;
+  while ((1u << (sh0 - 1)) < M) ++sh0;
   int passes = 0;
-  for (uint64_t L = T; L < N; L *= 2) ++passes;
+  for (uint64_t L = T * M; L < N; L *= 2) ++passes;
   char* w = (char*)ws;
   void* bk[2] = {Y, w};
   uint32_t* bv[2] = {Yv, val ? (uint32_t*)(w + round256(N * ks)) : nullptr};
   uint64_t* bj = (uint64_t*)(w + round256(N * ks) + (val ? round256(N * 4) : 0));
+  uint64_t* coarse = (uint64_t*)((char*)bj + round256(((N + kMinTile - 1) / kMinTile + 1) * sizeof(uint64_t)));
   // ping-pong between Y and the workspace so that the last pass writes Y
   int cur = passes % 2;
-  int rc = launch_sort_blocks(kt, val, ch, X, val ? Xv : nullptr, N, bk[cur], bv[cur], tiles, st);
-  for (int sh = 1; rc == CM_OK && sh <= passes; ++sh) {  // runs of T << (sh - 1)
-    rc = launch_sort_pass(kt, val, ch, g_set.shape, bk[cur], bv[cur], N, sh, bk[cur ^ 1], bv[cur ^ 1], bj, tiles, st);
+  int rc = launch_sort_blocks(kt, val, ch, X, val ? Xv : nullptr, N, bk[cur], bv[cur], (N + T * M - 1) / (T * M), st);
+  for (int sh = sh0; rc == CM_OK && sh < sh0 + passes; ++sh) {  // runs of T << (sh - 1)
+    rc = launch_sort_pass(kt, val, ch, g_set.shape, bk[cur], bv[cur], N, sh, bk[cur ^ 1], bv[cur ^ 1], bj, coarse,
+                          tiles, st);
     cur ^= 1;
   }
   return rc;

@@ -105,13 +105,20 @@ inline bool all_aligned16(std::initializer_list<const void*> ps) {
   return true;
 }
 
-// Merge sort (sort.hip): sort every run of T = tile_size(cfg) elements of X
-// into Y; then one pass merging runs of 2^(sh-1) blocks (T << (sh - 1)
-// elements) of X pairwise into Y (block co-ranks in bj, `tiles` entries).
+// Merge sort (sort.hip): sort every run of sort_run_blocks(kt, val, cfg)
+// blocks of T = tile_size(cfg) elements of X into Y (`runs` of them); then
+// one pass merging runs of 2^(sh-1) blocks (T << (sh - 1) elements) of X
+// pairwise into Y (block co-ranks in bj, `tiles` entries).
+uint32_t sort_run_blocks(int kt, bool val, int cfg);
 int launch_sort_blocks(int kt, bool val, const Choice& ch, const void* X, const uint32_t* Xv, uint64_t N, void* Y,
-                       uint32_t* Yv, uint64_t tiles, hipStream_t st);
+                       uint32_t* Yv, uint64_t runs, hipStream_t st);
+// ch.partition 0: one thread per block start, bisection over its pair;
+// otherwise, for pairs longer than shape.coarse_stride blocks, two levels
+// (coarse holds ceil(tiles / coarse_stride) entries), the fine step with
+// shape.fine_lanes lanes per block start.
 int launch_sort_pass(int kt, bool val, const Choice& ch, const Shape& shape, const void* X, const uint32_t* Xv,
-                     uint64_t N, int sh, void* Y, uint32_t* Yv, uint64_t* bj, uint64_t tiles, hipStream_t st);
+                     uint64_t N, int sh, void* Y, uint32_t* Yv, uint64_t* bj, uint64_t* coarse, uint64_t tiles,
+                     hipStream_t st);
 
 // Block merge of one merge over `tiles` blocks whose boundary co-ranks are bj
 // (bj == nullptr: each block searches its own two boundary co-ranks).

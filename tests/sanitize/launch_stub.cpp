@@ -21,12 +21,13 @@ int launch_block_co_ranks(int, const Choice&, const Shape&, const void*, uint64_
                           uint64_t, uint64_t*, uint64_t*, hipStream_t) {
   return CM_OK;
 }
+uint32_t sort_run_blocks(int, bool, int) { return 4; }
 int launch_sort_blocks(int, bool, const Choice&, const void*, const uint32_t*, uint64_t, void*, uint32_t*, uint64_t,
                        hipStream_t) {
   return CM_OK;
 }
 int launch_sort_pass(int, bool, const Choice&, const Shape&, const void*, const uint32_t*, uint64_t, int, void*,
-                     uint32_t*, uint64_t*, uint64_t, hipStream_t) {
+                     uint32_t*, uint64_t*, uint64_t*, uint64_t, hipStream_t) {
   return CM_OK;
 }
 int launch_merge_blocks(int, bool, int, const Choice&, const Shape&, const void*, const void*, uint64_t, const void*,

@@ -44,8 +44,9 @@ def test_sizes_around_blocks_and_passes(dtype):
     rng = np.random.default_rng(11)
     nt, e = cm.config_info(cm.tuning_get(cm.OP_SORT, np.dtype(dtype).name, True, 1 << 20)[0])
     T = nt * e
+    # the first sorted runs are 1, 2 or 4 blocks long (as LDS allows)
     for n in (0, 1, 2, 7, T - 1, T, T + 1, 2 * T, 2 * T + 1, 3 * T + 5, 4 * T, 4 * T - 1,
-              8 * T + 3, 33 * T + 17, 100_003):
+              4 * T + 1, 8 * T + 3, 16 * T - 1, 16 * T + 1, 33 * T + 17, 100_003):
         for hi in (3, 1 << 20):
             check(keys_of(rng, n, dtype, hi))
     check(keys_of(rng, 50_001, dtype, 1000), payload=False)
@@ -67,6 +68,30 @@ def test_every_configuration(dtype):
                 check(k, payload=False)
             finally:
                 cm.tuning_clear()
+
+
+@pytest.mark.parametrize("stride", [16, 64])
+def test_two_level_pass_boundaries(stride):
+    """Passes whose pairs span more than the coarse stride co-rank every
+    stride-th block start first and search the others between them (by
+    bisection, or by groups of 2 or 4 lanes); sizes
+    put pairs just past one and two strides, ragged last pairs included, and
+    the one-level pass must give the same bits."""
+    rng = np.random.default_rng(16 + stride)
+    cm.set_coarse_stride(stride)
+    nt, e = cm.config_info(cm.tuning_get(cm.OP_SORT, "uint32", True, 1 << 20)[0])
+    T = nt * e
+    for n in (2 * stride * T + 1, 2 * stride * T + T - 1, 3 * stride * T + 17, 5 * stride * T - 3):
+        for hi in (5, 1 << 30):
+            k = keys_of(rng, n, np.uint32, hi)
+            for part, lanes in ((2, 1), (2, 4), (2, 2), (0, 1)):
+                cm.set_partition(part)
+                cm.set_fine_lanes(lanes)
+                check(k)
+    cm.set_fine_lanes(1)
+    cm.set_partition(2)
+    check(keys_of(rng, 2 * stride * T + 333, np.uint64, 1 << 40), payload=False)
+    check(keys_of(rng, 3 * stride * T + 1, np.float32, 1 << 16))
 
 
 def test_structured_inputs_and_misaligned_bases():
