@@ -652,6 +652,10 @@ int cm_merge_partition_ablation(int key_type, const void *A, const uint32_t *A_v
  * cm_sort_workspace_size(key_type, with_payload, n): bytes (a second key and
  *   payload buffer of n entries, one uint64 per block and one per 16
  *   blocks), 0 for n == 0.
+ * cm_sort_run_length(key_type, with_payload, n): elements per run of the
+ *   LDS run sort in the configuration a sort of n keys would use now (the
+ *   passes then number ceil(log2(n / run))); 0 for an unknown key type.
+ *   Host-only; no GPU work.
  * cm_stable_sort(key_type, keys, n, keys_out, workspace, bytes, stream)
  * cm_stable_sort_pairs(key_type, keys, vals, n, keys_out, vals_out,
  *   workspace, bytes, stream)
@@ -663,6 +667,7 @@ int cm_merge_partition_ablation(int key_type, const void *A, const uint32_t *A_v
  *   from the tuning table (operation 3) or the process defaults.
  */
 size_t cm_sort_workspace_size(int key_type, int with_payload, uint64_t n);
+uint64_t cm_sort_run_length(int key_type, int with_payload, uint64_t n);
 int cm_stable_sort(int key_type, const void *keys, uint64_t n, void *keys_out, void *workspace,
                    size_t workspace_bytes, hipStream_t stream);
 int cm_stable_sort_pairs(int key_type, const void *keys, const uint32_t *vals, uint64_t n,

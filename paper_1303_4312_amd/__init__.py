@@ -62,7 +62,7 @@ EXPORTS = [
     "cm_set_coarse_stride", "cm_set_block_order", "cm_set_fine_lanes",
     "cm_server_create", "cm_server_submit", "cm_server_submit_host", "cm_server_poll",
     "cm_server_release",
-    "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_stable_sort",
+    "cm_server_get_stats", "cm_server_destroy", "cm_sort_workspace_size", "cm_sort_run_length", "cm_stable_sort",
     "cm_stable_sort_pairs", "cm_partition_ablation_workspace_size", "cm_merge_partition_ablation",
     "cm_origin_codes", "cm_gather_records",
 ]
@@ -167,6 +167,7 @@ def load():
         "cm_server_get_stats": (c_int, [vp, vp]),
         "cm_server_destroy": (c_int, [vp]),
         "cm_sort_workspace_size": (c_size, [c_int, c_int, c_u64]),
+        "cm_sort_run_length": (c_u64, [c_int, c_int, c_u64]),
         "cm_stable_sort": (c_int, [c_int, vp, c_u64, vp, vp, c_size, vp]),
         "cm_stable_sort_pairs": (c_int, [c_int, vp, vp, c_u64, vp, vp, vp, c_size, vp]),
         "cm_partition_ablation_workspace_size": (c_size, [ctypes.c_uint32]),
@@ -525,6 +526,13 @@ def timing_stop(per_call=False):
 def sort_workspace_size(key_dtype, with_payload: bool, n: int) -> int:
     kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
     return load().cm_sort_workspace_size(kt, int(bool(with_payload)), n)
+
+
+def sort_run_length(key_dtype, with_payload: bool, n: int) -> int:
+    """Elements per run of the LDS run sort that a sort of n keys would use
+    now (its merge passes then number ceil(log2(n / run)))."""
+    kt = KEY_TYPES[str(key_dtype).replace("torch.", "")]
+    return load().cm_sort_run_length(kt, int(bool(with_payload)), n)
 
 
 def stable_sort(keys, vals=None, out=None, out_vals=None, workspace=None, stream=None,

@@ -1254,6 +1254,13 @@ size_t cm_sort_workspace_size(int key_type, int with_payload, uint64_t n) {
   return sort_ws_bytes(key_type, with_payload != 0, n);
 }
 
+uint64_t cm_sort_run_length(int key_type, int with_payload, uint64_t n) {
+  if (!key_type_ok(key_type)) return 0;
+  const bool val = with_payload != 0;
+  const Choice ch = resolve(kOpSort, key_type, val, n);
+  return tile_size(ch.cfg) * sort_run_blocks(key_type, val, ch.cfg);
+}
+
 int cm_stable_sort(int key_type, const void* keys, uint64_t n, void* keys_out, void* workspace,
                    size_t workspace_bytes, hipStream_t stream) {
   return sort_impl(key_type, false, keys, nullptr, n, keys_out, nullptr, workspace, workspace_bytes, stream);

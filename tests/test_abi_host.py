@@ -602,3 +602,22 @@ def test_noalloc_refuses_merges_beyond_its_scratch():
     assert lib.cm_stable_merge_pairs_noalloc(9, fake, fake, 10, fake, fake, 0, fake, fake, None) == EDTYPE
     assert lib.cm_stable_merge_pairs_noalloc(0, fake, fake, 1 << 48, fake, fake, 0, fake, fake, None) == EINVAL
     assert cm.NOALLOC_SCRATCH_BYTES == 4 << 20
+
+
+@pytest.mark.usefixtures("restore_settings")
+def test_sort_run_length():
+    """The LDS run sort takes 4, 2 or 1 pass blocks per run, as many as keep
+    two workgroups' runs (keys and payloads) within a CU's LDS."""
+    lib = cm.load()
+    for kt in range(6):
+        assert lib.cm_set_config(kt, 0, -1) == 0 and lib.cm_set_config(kt, 1, -1) == 0
+    assert cm.sort_run_length("uint32", True, 1 << 28) == 4 * 256 * 9     # 73,728 B per run
+    assert cm.sort_run_length("float32", True, 1 << 20) == 4 * 256 * 9
+    assert cm.sort_run_length("uint32", False, 1 << 28) == 4 * 256 * 11   # keys alone: 256 x 11
+    assert cm.sort_run_length("uint64", True, 1 << 28) == 2 * 256 * 9     # 12 B per element
+    cm.tuning_set(cm.OP_SORT, "uint32", True, 29, 2, 0, 2)  # 256 x 15
+    try:
+        assert cm.sort_run_length("uint32", True, 1 << 28) == 2 * 256 * 15
+    finally:
+        cm.tuning_clear()
+    assert lib.cm_sort_run_length(6, 1, 1000) == 0

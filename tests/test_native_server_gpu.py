@@ -300,7 +300,8 @@ def test_native_server_large_batches(partition, restore_settings):
     read from the server's pinned host array by the batch's first kernel (no
     upload), in the automatic boundary mode, with the two-level pass, and
     with none (every block co-ranks its ends after the prep kernel).  Every
-    request equals the merge run alone and the oracle."""
+    request equals the merge run alone and the oracle; a batch of more than
+    16 is formed for certain (the requests are let in together)."""
     import torch
     print(f"[server large batches] partition={partition}", flush=True)
     cm.set_partition(partition)
@@ -310,19 +311,36 @@ def test_native_server_large_batches(partition, restore_settings):
     for A, B, Av, Bv in dev:
         C, Cv = cm.stable_merge_pairs(A, Av, B, Bv)
         alone.append((to_host(C), to_host(Cv)))
-    srv = serve.NativeServer("uint32", True, arena_bytes=1 << 28, max_batch=64, max_inflight=2,
+    # A first request whose outputs fill the arena holds the others back
+    # (admission is in arrival order and waits for space); its release lets
+    # all of them in at once, inputs long ready, so the scheduler fills
+    # batches up to max_batch.
+    half = 1 << 22
+    big = [torch.arange(half, dtype=torch.int32, device="cuda:0").view(torch.uint32) for _ in range(4)]
+    srv = serve.NativeServer("uint32", True, arena_bytes=16 * half + 256, max_batch=64, max_inflight=2,
                              max_requests=256)
-    x = torch.randn(4096, 4096, device="cuda:0")
-    side = torch.cuda.Stream()
     torch.cuda.synchronize()
+    first = srv.submit(big[0], big[1], big[2], big[3])
     tickets, sizes, results = [], {}, {}
-    with torch.cuda.stream(side):
-        for _ in range(8):  # milliseconds of work ahead of every request's inputs
-            x = x @ x / 4096
-        for A, B, Av, Bv in dev:  # all become ready at once: batches fill up to max_batch
-            t = srv.submit(A, B, Av, Bv)
-            tickets.append(t)
-            sizes[t] = A.numel() + B.numel()
+    for A, B, Av, Bv in dev:
+        t = srv.submit(A, B, Av, Bv)
+        tickets.append(t)
+        sizes[t] = A.numel() + B.numel()
+    t_end = time.time() + 60
+    first_done = False
+    while not first_done:
+        assert time.time() < t_end, "the first request did not finish in time"
+        for d in srv.poll(wait_us=2000):
+            assert d.status == 0, f"ticket {d.ticket}: status {d.status}"
+            if d.ticket == first:
+                first_done = True
+                continue
+            # only empty requests take no arena space and may pass it
+            assert sizes[d.ticket] == 0, "a request was admitted while the arena was full"
+            C, Cv = srv.outputs(d, 0)
+            results[d.ticket] = (to_host(C), to_host(Cv))
+            srv.release(d.ticket)
+    srv.release(first)
     drain(srv, len(tickets), sizes, results)
     st = srv.stats()
     srv.close()
@@ -332,4 +350,4 @@ def test_native_server_large_batches(partition, restore_settings):
     for d, (C, Cv) in list(zip(reqs, [results[t] for t in tickets]))[:10]:
         Ce, Cve = oracle.stable_merge(d["A"], d["B"], d["Av"], d["Bv"])
         assert same_bits(C, Ce) and same_bits(Cv, Cve)
-    assert st["completed"] == len(reqs) and st["max_batch_seen"] > 16
+    assert st["completed"] == len(reqs) + 1 and st["max_batch_seen"] > 16
