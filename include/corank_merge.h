@@ -400,8 +400,9 @@ int cm_get_grid(void);
  * Autotuner (self-written; not part of the method).  Times every tile
  * configuration x co-rank search x boundary pass on the caller's buffers
  * (each candidate: one warm call, then `reps` calls between two HIP events
- * on `stream`; the call synchronises), stores the fastest in the tuning
- * table under (operation, key type, payload, size class of m + n) and, if
+ * on `stream`; the call synchronises), times the four fastest three times
+ * more, round-robin, keeps each one's best time, stores the fastest in the
+ * tuning table under (operation, key type, payload, size class of m + n) and, if
  * best is not NULL, writes best[0..2] = {config, search, partition}.  Every
  * candidate produces the same output, so C (and C_val) hold the merge
  * afterwards.  Arguments are those of cm_stable_merge_pairs (payload

@@ -197,6 +197,10 @@ __device__ __forceinline__ void merge_block(const K* __restrict__ A, const V* __
                                             const K* __restrict__ B, const V* __restrict__ Bv, uint64_t n,
                                             K* __restrict__ C, V* __restrict__ Cv, uint64_t i0, int len,
                                             uint64_t j0, uint64_t j1, int search, K* s_key, V* s_val) {
+  // with sorted input j0 <= j1; for unsorted input (co-ranks out of order)
+  // starting at the smaller one keeps both windows inside A and B: the B
+  // window then ends at i0 + len - j1, which the end's search bounds by n
+  j0 = std::min(j0, j1);
   const int a_len = window_a_len(j0, j1, len);
   const int b_len = len - a_len;
   const uint64_t k0 = i0 - j0;
@@ -1009,7 +1013,9 @@ __global__ __launch_bounds__(NT) void k_seg_merge_blocks(
   for (uint64_t t = blockIdx.x; t < num_tiles; t += gridDim.x) {
     const uint64_t i0 = t * (uint64_t)T;
     const int len = (int)std::min((uint64_t)T, N - i0);
-    const uint64_t j0 = bj[t];
+    // the smaller of the two co-ranks starts the windows: equal to bj[t] for
+    // sorted segments, inside A and B for unsorted ones (as in merge_block)
+    const uint64_t j0 = std::min(bj[t], bj[t + 1]);
     const uint64_t k0 = i0 - j0;
     const int a_len = window_a_len(j0, bj[t + 1], len);
     const int b_len = len - a_len;

@@ -176,8 +176,9 @@ __device__ __forceinline__ I co_rank(int mode, I i, RA A, I m, RB B, I n) {
 }
 
 // Length of a block's A window from the co-ranks of its two ends.  With
-// sorted input j0 <= j1 <= j0 + len always holds; the clamp only keeps every
-// access in bounds when the precondition is broken.
+// sorted input j0 <= j1 <= j0 + len always holds; the clamp (with the
+// callers starting the windows at min(j0, j1)) only keeps every access in
+// bounds when the precondition is broken.
 __device__ __forceinline__ int window_a_len(uint64_t j0, uint64_t j1, int len) {
   return j1 < j0 ? 0 : (int)(j1 - j0 < (uint64_t)len ? j1 - j0 : (uint64_t)len);
 }
