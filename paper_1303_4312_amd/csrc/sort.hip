@@ -11,8 +11,9 @@
 //      sequentially, payloads alongside.
 //   2. Passes: runs of length L = MT, 2MT, 4MT, ... are merged pairwise, the
 //      pair p being X[2pL, 2pL + L) and X[2pL + L, 2pL + 2L) (clipped to N).
-//      Each pass is Algorithm 2 on every pair at once: a boundary kernel
-//      co-ranks the start of every output block inside its pair, and the
+//      Each pass is Algorithm 2 on every pair at once: boundary kernels
+//      co-rank the start of every output block inside its pair (one level,
+//      or every G-th start first and the others between those), and the
 //      block merge of the single merge (merge_block) merges the block.  L is
 //      a multiple of T, so no block straddles two pairs.
 #include <hip/hip_runtime.h>
